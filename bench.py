@@ -1,0 +1,182 @@
+"""Benchmark: predictor-corrector time steps per second of the pipe-flow step.
+
+Workload (default): N = 64 radial points, |m| < 48, |k| < 64 (3/2-dealiased
+grid 64 x 144 x 192), alpha = 0.5, Re = 5300, dt = 0.005, fixed flux; a
+synthetic state (laminar flow plus a seeded divergence-free perturbation of
+10% of the laminar energy, broadband spectrum).  Inputs are resident in HBM
+before the timed region.  One "step" is the whole hot path: two dealiased
+nonlinear evaluations and two radial solves.
+
+Prints one JSON line: headline value = FP64 steps/s; the mixed-precision form
+(FP32 transforms and products, FP64 solves) is reported beside it, with the
+roofline of the dominant kernel (HIP-event timed) and the CPU oracle timed on
+this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(name, N, M, K, mixed):
+    """Algorithmic bytes one launch moves: its inputs and outputs at the
+    stored precision (per-unit figures times the units one launch covers)."""
+    nk = 2 * K - 1
+    cw = 8 if mixed else 16          # complex word of the transform path
+    S64 = 16 * M * nk * N            # one FP64 spectral field
+    S = cw * M * nk * N              # one spectral field in transform precision
+    H = cw * N * M * 3 * K           # one z-transformed field
+    if name == "zinv":
+        return 6 * S + 6 * H
+    if name == "theta":
+        return 6 * H + 3 * H
+    if name == "zfwd":
+        return 3 * H + 3 * S
+    if name == "solve_pred":   # read u^n, N^n; write u^p, omega^p
+        return 3 * S64 + 3 * S + (6 * S if mixed else 6 * S64)
+    if name == "solve_corr":   # read u^n, N^n, N^p; write u^{n+1}, omega (+ FP32 shadow)
+        return 3 * S64 + 6 * S + 3 * S64 + (6 * S if mixed else 3 * S64)
+    raise KeyError(name)
+
+
+def step_bytes(N, M, K, mixed):
+    return sum(kernel_bytes(k, N, M, K, mixed) * (2 if k in ("zinv", "theta", "zfwd") else 1)
+               for k in ("zinv", "theta", "zfwd", "solve_pred", "solve_corr"))
+
+
+def traffic_for(kernel, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_pipe64_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1705_03838_amd", "csrc", rec["source"])
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != rec.get("source_sha256"):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(w, precision, steps, warmup, profile_steps):
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import workload_state
+
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"],
+                   dt=w["dt"], precision=precision)
+    u0 = workload_state(w, s.nodes())
+    s.set_state(torch.from_numpy(u0))
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_steps(profile_steps)
+    diag = s.diagnostics()
+    s.close()
+    return (t1 - t0) / steps, prof, diag
+
+
+def cpu_baseline(w, nsteps=2):
+    """The oracle as it stands, on this host: one untimed step to build its
+    caches, then nsteps timed steps of the same workload."""
+    from threadpoolctl import threadpool_info
+
+    from inputs import workload_state
+    from oracle import Oracle, Params
+
+    o = Oracle(Params(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"],
+                      dt=w["dt"]))
+    u = workload_state(w, o.g.r)
+    u = o.step(u)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        u = o.step(u)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": nsteps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsteps} FP64 predictor-corrector steps of the same workload after one "
+                      f"untimed step; {dt:.1f} s (numpy + LAPACK dense solves)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--workload", default="pipe64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(ensemble members and Newton seeds would shard as independent units)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1705_03838_amd as opf
+    from inputs import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    N, M, K = w["N"], w["M"], w["K"]
+    ms64, prof64, diag64 = run_gpu(w, opf.OPF_FP64, args.steps, args.warmup, args.profile_steps)
+
+    def roofline(prof, mixed, prec):
+        per = {k: (t / n if n else 0.0) for k, (t, n) in prof.items()}
+        tot = {k: t for k, (t, n) in prof.items()}
+        dom = max(tot, key=tot.get)
+        b = kernel_bytes(dom, N, M, K, mixed)
+        ach = b / (per[dom] * 1e-3) / 1e9
+        tr = traffic_for(dom, prec)
+        return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": tr, "alg_bytes_per_launch": b,
+                "avg_launch_us": round(per[dom] * 1e3, 2),
+                "kernels_us": {k: round(v * 1e3, 2) for k, v in per.items()}}
+
+    out = {
+        "metric": "time steps/s (FP64 predictor-corrector step) and HBM GB/s at N=64, |m|<48, |k|<64",
+        "value": round(1.0 / ms64, 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64 * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: laminar pipe flow + seeded divergence-free perturbation (10% laminar energy)",
+        "config": {"workload": f"{args.workload}: N={N} radial points, |m|<{M}, |k|<{K} "
+                               f"(grid {N}x{3 * M}x{3 * K}), alpha={w['alpha']}, Re={w['Re']}, "
+                               f"dt={w['dt']}, fixed flux, seed {w['seed']}",
+                   "parallelism": "single GPU"},
+        "alg_GBps_per_step": round(step_bytes(N, M, K, False) / ms64 / 1e9, 1),
+        "roofline": roofline(prof64, False, "fp64"),
+        "diagnostics_after_run": {k: diag64[k] for k in ("E", "D", "tau_w", "beta")},
+    }
+    if not args.fp64_only:
+        ms32, prof32, _ = run_gpu(w, opf.OPF_MIXED, args.steps, args.warmup, args.profile_steps)
+        out["mixed"] = {"steps_per_s": round(1.0 / ms32, 2), "ms_per_step": round(ms32 * 1e3, 4),
+                        "speedup_vs_fp64": round(ms64 / ms32, 3),
+                        "alg_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
+                        "roofline": roofline(prof32, True, "mixed")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/* opf.h -- C ABI of the MI355X pipe-flow time-step library.
+ *
+ * The library advances the incompressible Navier-Stokes equations in a
+ * periodic pipe, discretised as in Section 2 of Willis, "The Openpipeflow
+ * Navier-Stokes solver" (SoftwareX 6, 2017):
+ *   A(r,theta,z) = sum_{|k|<K} sum_{|m|<M} A_km(r_n) exp(i(alpha k z + mp m theta))   (Eq. 1)
+ * with finite differences on N radial points (9-point stencils), 3/2
+ * dealiasing on a 3K x 3M grid, pseudospectral nonlinear terms, a
+ * pressure-Poisson equation with an influence-matrix boundary correction,
+ * banded LU per Fourier mode for the implicit viscous terms and a
+ * second-order predictor-corrector time step.
+ *
+ * Units: pipe radius R = 1, laminar centre-line speed U_cl = 1; Re = U_cl R / nu
+ * (equal to the bulk-velocity / diameter Reynolds number of the paper).
+ *
+ * Conventions common to every call
+ *  - Return value: opf_status, 0 (OPF_OK) on success.  No call aborts or throws.
+ *  - Device pointers ("_dev") are HIP device memory owned by the caller; the
+ *    library never frees them and keeps no pointer to them after the call,
+ *    except the workspace given to opf_create, which it uses until
+ *    opf_destroy.  Host pointers ("_host") are read or written synchronously.
+ *  - Work is enqueued on the HIP stream given to opf_create and is
+ *    asynchronous unless a call returns host values (stated per call).
+ *  - External spectral layout of a vector field (state, nonlinear term,
+ *    right-hand side): complex128, interleaved (re, im), shape
+ *    [3][M][2K-1][N], components (u_r, u_theta, u_z), azimuthal index
+ *    m = 0..M-1 (wavenumber mp*m), axial index k = -(K-1)..K-1 stored at
+ *    position k+K-1, radial node n = 0..N-1 ascending (r[N-1] = 1).  Negative m
+ *    follow from reality, A(-m,-k) = conj(A(m,k)).  A scalar field (pressure)
+ *    has shape [M][2K-1][N].
+ */
+#ifndef OPF_H
+#define OPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OPF_OK = 0,
+    OPF_E_INVALID = -1,     /* bad argument or parameter set                      */
+    OPF_E_NOMEM = -2,       /* workspace too small                                */
+    OPF_E_HIP = -3,         /* a HIP runtime call failed (message: opf_last_error) */
+    OPF_E_UNSUPPORTED = -4, /* size or option not implemented                      */
+    OPF_E_NUMERIC = -5,     /* non-finite values, or an unstable factorisation     */
+    OPF_E_STATE = -6        /* called before opf_set_state                         */
+} opf_status;
+
+enum { OPF_FP64 = 0, OPF_MIXED = 1 };
+enum { OPF_SOLVE_PRED = 0, OPF_SOLVE_CORR = 1, OPF_SOLVE_RAW = 2 };
+
+/* Problem definition (Section 2: domain [0,1] x [0,2pi/mp) x [0,2pi/alpha),
+ * N radial points, |m| < M, |k| < K).
+ *  N        radial points, 12 <= N <= 64
+ *  M, K     Fourier modes |m| < M, |k| < K; 3M and 3K must factor into 2s and
+ *           3s (the dealiased grid is 3K x 3M), 2 <= M <= 48, 2 <= K <= 64
+ *  mp       azimuthal periodicity (rotational symmetry order), >= 1
+ *  stencil  finite-difference points, must be 9
+ *  alpha    axial wavenumber (pipe length 2pi/alpha), > 0
+ *  Re       Reynolds number, > 0
+ *  dt       time step, > 0
+ *  c        implicitness of the viscous terms, 0.5 gives second order
+ *  n_corr   corrector iterations per step, >= 1
+ *  fixed_flux  1: hold the flux at its laminar value 1/4 (pressure gradient
+ *           4(1+beta)/Re adjusts); 0: fixed pressure gradient 4/Re
+ *  precision OPF_FP64, or OPF_MIXED (transforms and products in FP32, radial
+ *           solves and influence correction in FP64)
+ *  nonlinear 1; 0 drops u x omega (linear Stokes step, for tests)
+ *  r_nodes  host array of N increasing nodes in (0,1] with r[N-1] = 1, or NULL
+ *           for the default Chebyshev points r_n = cos(pi (N-n)/(2N-1)), n=1..N
+ *           (read during opf_create only). */
+typedef struct {
+    int32_t N, M, K, mp, stencil;
+    double alpha, Re, dt, c;
+    int32_t n_corr, fixed_flux, precision, nonlinear;
+    const double* r_nodes;
+} opf_params;
+
+/* Global diagnostics (Section 3.2: kinetic energy E, energy input from the
+ * driving pressure gradient I, dissipation D; laminar values for
+ * normalisation), plus wall shear tau_w = -du_z/dr of the mean flow at r = 1,
+ * flux = int_0^1 u_z,00 r dr and the pressure-gradient excess beta.  g_norm is
+ * the largest boundary-condition residual |g| over all modes after the last
+ * radial solve (Section 2: at machine-epsilon level). */
+typedef struct {
+    double E, I, D, tau_w, flux, beta;
+    double E_lam, I_lam, D_lam;
+    double g_norm;
+} opf_diag;
+
+typedef struct opf_ctx opf_ctx;
+
+/* Fill *p with the tiny test case defaults (N=24, M=K=8, mp=1, alpha=1.25,
+ * Re=2400, dt=0.01, c=0.5, n_corr=1, fixed flux, FP64, nonlinear). */
+opf_status opf_default_params(opf_params* p);
+
+/* Create-time radial tables computed on the host only (no device needed):
+ * nodes r[N], quadrature weights quad[N] of int_0^1 g(r) r dr for g even in
+ * r, folded 9-point first / second derivative weights d1, d2 [2][N][9]
+ * (index 0: even axis parity, 1: odd) acting on columns s0[n]..s0[n]+8.
+ * Any output pointer may be NULL.  Section 2: radial finite differences on a
+ * 9-point stencil, nodes bunched towards the wall. */
+opf_status opf_tables(const opf_params* p, double* r, double* quad, double* d1, double* d2,
+                      int32_t* s0);
+
+/* Bytes of device workspace opf_create needs for *p (tables, state, buffers). */
+opf_status opf_workspace_size(const opf_params* p, size_t* bytes);
+
+/* Build grid, finite-difference weights, quadrature, banded LU factors of every
+ * radial operator, influence-matrix data and FFT tables, upload them into the
+ * caller's workspace (>= opf_workspace_size bytes, 256-byte aligned) on
+ * `hip_stream` (a hipStream_t; NULL = default stream).  Synchronises.
+ * Returns OPF_E_NUMERIC if an LU factor shows element growth (unstable without
+ * pivoting).  *out is valid until opf_destroy. */
+opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes,
+                      void* hip_stream, opf_ctx** out);
+opf_status opf_destroy(opf_ctx* ctx);
+
+/* Radial nodes in use (host array of N doubles). */
+opf_status opf_get_nodes(const opf_ctx* ctx, double* r_host);
+
+/* Copy a state (external layout, complex128) into / out of the context. */
+opf_status opf_set_state(opf_ctx* ctx, const void* u_dev);
+opf_status opf_get_state(opf_ctx* ctx, void* u_dev);
+
+/* Advance the state by nsteps predictor-corrector steps (Section 2):
+ * N^n = (u x omega)(u^n); u^p = S(R0); N^p = (u x omega)(u^p); u^{n+1} = S(R1),
+ * R0 = [1/dt + (1-c)L/Re] u^n + N^n + f, R1 = [..] u^n + c N^p + (1-c) N^n + f.
+ * One hipGraph launch per step. */
+opf_status opf_step(opf_ctx* ctx, int32_t nsteps);
+
+/* Dealiased nonlinear term N = u x omega, omega = curl u (Section 2.2:
+ * pseudospectral, 3/2 rule).  u_dev, n_dev: external layout, complex128.
+ * Uses the context's scratch buffers; the state is not changed. */
+opf_status opf_nonlinear(opf_ctx* ctx, const void* u_dev, void* n_dev);
+
+/* omega = curl u by the radial finite differences (external layout). */
+opf_status opf_vorticity(opf_ctx* ctx, const void* u_dev, void* w_dev);
+
+/* One substep solve S (Section 2.2: pressure-Poisson equation, banded LU per
+ * Fourier mode, influence-matrix correction so that g = 0; fixed flux on the
+ * (0,0) mode; m = 0 made Hermitian).
+ *  kind OPF_SOLVE_RAW : rhs_dev = R (3 fields, external layout); u = S(R)
+ *  kind OPF_SOLVE_PRED: rhs_dev = N^n; R = [1/dt + (1-c)L/Re] u^n + N^n + f
+ *                       with u^n the context's state
+ *  kind OPF_SOLVE_CORR: rhs_dev = [N^n ; N^p] (6 fields);
+ *                       R = [..] u^n + c N^p + (1-c) N^n + f
+ * u_out_dev: 3 fields (external layout); p_out_dev: pressure head
+ * [M][2K-1][N] complex128 or NULL.  The state is not changed. */
+opf_status opf_radial_solve(opf_ctx* ctx, int32_t kind, const void* rhs_dev,
+                            void* u_out_dev, void* p_out_dev);
+
+/* Travelling-wave residual (Section 2: Newton-Krylov for invariant solutions;
+ * a travelling wave is an equilibrium in a frame moving at its phase speed):
+ *   F(x) = shift(Phi_T(x), -s) - x,
+ * Phi_T = round(T/dt) steps, shift(A, s)_k = A_k exp(-i alpha k s) moves the
+ * pattern downstream by s.  x_dev, F_dev: external layout; the context's
+ * state is overwritten.  *norm_out (host, synchronises): energy norm of F,
+ * sqrt(sum_k sum_{m>=0} c_m sum_n w_n |F_mk(r_n)|^2), c_0 = 1, c_m = 2. */
+opf_status opf_newton_residual(opf_ctx* ctx, const void* x_dev, double T,
+                               double shift, void* F_dev, double* norm_out);
+
+/* Advance nsteps steps like opf_step but with every kernel launched on its
+ * own and bracketed by HIP events on the context's stream (for measurement).
+ * ms[5] / launches[5] receive the summed device time and launch count of the
+ * z-inverse transform, theta transform + product, z-forward transform,
+ * predictor solve and corrector solve kernels.  Synchronises. */
+opf_status opf_profile_steps(opf_ctx* ctx, int32_t nsteps, double* ms, int32_t* launches);
+
+/* Diagnostics of the current state (host struct; synchronises). */
+opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
+
+const char* opf_status_string(opf_status s);
+const char* opf_last_error(const opf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPF_H */

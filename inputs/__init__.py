@@ -11,6 +11,7 @@ from .synth import (  # noqa: F401
     normals,
     uniforms,
     make_state,
+    workload_state,
     laminar_state,
     ensemble_members,
     WORKLOADS,

@@ -1,0 +1,250 @@
+"""Python binding of the MI355X pipe-flow time-step library (libopf.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (the workspace and state tensors)
+and the HIP stream.  The binding fails loudly when the library is missing;
+there is no CPU fallback.
+
+Names follow include/opf.h; see that header for layouts and semantics.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libopf.so")
+
+OPF_OK, OPF_E_INVALID, OPF_E_NOMEM, OPF_E_HIP, OPF_E_UNSUPPORTED, OPF_E_NUMERIC, OPF_E_STATE = (
+    0, -1, -2, -3, -4, -5, -6)
+OPF_FP64, OPF_MIXED = 0, 1
+OPF_SOLVE_PRED, OPF_SOLVE_CORR, OPF_SOLVE_RAW = 0, 1, 2
+
+EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create", "opf_destroy",
+           "opf_get_nodes", "opf_set_state", "opf_get_state", "opf_step", "opf_nonlinear",
+           "opf_vorticity", "opf_radial_solve", "opf_newton_residual", "opf_profile_steps",
+           "opf_diagnostics",
+           "opf_status_string", "opf_last_error"]
+
+
+class opf_params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("mp", ctypes.c_int32), ("stencil", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("Re", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c", ctypes.c_double),
+                ("n_corr", ctypes.c_int32), ("fixed_flux", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("nonlinear", ctypes.c_int32),
+                ("r_nodes", ctypes.c_void_p)]
+
+
+class opf_diag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("E", "I", "D", "tau_w", "flux", "beta", "E_lam", "I_lam", "D_lam", "g_norm")]
+
+
+class OpfError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"opf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libopf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OpfError(OPF_E_UNSUPPORTED, f"{path} not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "opf_default_params": ([P(opf_params)], i32),
+        "opf_tables": ([P(opf_params), vp, vp, vp, vp, vp], i32),
+        "opf_workspace_size": ([P(opf_params), P(ctypes.c_size_t)], i32),
+        "opf_create": ([P(opf_params), vp, ctypes.c_size_t, vp, P(vp)], i32),
+        "opf_destroy": ([vp], i32),
+        "opf_get_nodes": ([vp, P(ctypes.c_double)], i32),
+        "opf_set_state": ([vp, vp], i32),
+        "opf_get_state": ([vp, vp], i32),
+        "opf_step": ([vp, i32], i32),
+        "opf_nonlinear": ([vp, vp, vp], i32),
+        "opf_vorticity": ([vp, vp, vp], i32),
+        "opf_radial_solve": ([vp, i32, vp, vp, vp], i32),
+        "opf_newton_residual": ([vp, vp, dbl, dbl, vp, P(ctypes.c_double)], i32),
+        "opf_profile_steps": ([vp, i32, P(ctypes.c_double), P(ctypes.c_int32)], i32),
+        "opf_diagnostics": ([vp, P(opf_diag)], i32),
+        "opf_status_string": ([i32], ctypes.c_char_p),
+        "opf_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def make_params(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01, c=0.5, n_corr=1,
+                fixed_flux=True, precision=OPF_FP64, nonlinear=True, stencil=9):
+    p = opf_params()
+    p.N, p.M, p.K, p.mp, p.stencil = N, M, K, mp, stencil
+    p.alpha, p.Re, p.dt, p.c = alpha, Re, dt, c
+    p.n_corr, p.fixed_flux = n_corr, int(bool(fixed_flux))
+    p.precision, p.nonlinear = precision, int(bool(nonlinear))
+    p.r_nodes = None
+    return p
+
+
+def host_tables(**kw):
+    """Create-time radial tables computed on the host (no device needed):
+    nodes r, quadrature weights, folded D1 / D2 weights [2][N][9] and the
+    stencil start columns."""
+    import numpy as np
+    lib = load_library()
+    p = make_params(**kw)
+    N = p.N
+    r, q = np.zeros(N), np.zeros(N)
+    d1, d2 = np.zeros((2, N, 9)), np.zeros((2, N, 9))
+    s0 = np.zeros(N, dtype=np.int32)
+    st = lib.opf_tables(ctypes.byref(p), r.ctypes.data, q.ctypes.data, d1.ctypes.data,
+                        d2.ctypes.data, s0.ctypes.data)
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+    return r, q, d1, d2, s0
+
+
+class Solver:
+    """One time-step context on the current CUDA/HIP device.
+
+    State tensors are complex128 of shape [3][M][2K-1][N] on the device.
+    """
+
+    def __init__(self, r_nodes=None, stream=None, **kw):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.p = make_params(**kw)
+        self._nodes = None
+        if r_nodes is not None:
+            self._nodes = np.ascontiguousarray(r_nodes, dtype=np.float64)
+            self.p.r_nodes = self._nodes.ctypes.data
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.opf_workspace_size(ctypes.byref(self.p), ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.opf_create(ctypes.byref(self.p), ctypes.c_void_p(self._ws_ptr),
+                                        ctypes.c_size_t(self.ws_bytes),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.N, self.M, self.K = self.p.N, self.p.M, self.p.K
+        self.shape = (3, self.M, 2 * self.K - 1, self.N)
+
+    def _check(self, st, ctx=None):
+        if st != OPF_OK:
+            msg = self.lib.opf_status_string(st).decode()
+            c = ctx if ctx is not None else getattr(self, "ctx", None)
+            if c is not None:
+                detail = self.lib.opf_last_error(c)
+                if detail:
+                    msg += ": " + detail.decode()
+            raise OpfError(st, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.opf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --------------------------------------------------------
+    def _dev(self, t, shape=None, dtype=None):
+        torch = self.torch
+        t = torch.as_tensor(t)
+        if dtype is None:
+            dtype = torch.complex128
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise OpfError(OPF_E_INVALID, f"expected shape {shape}, got {tuple(t.shape)}")
+        return t
+
+    def nodes(self):
+        import numpy as np
+        r = np.zeros(self.N)
+        self._check(self.lib.opf_get_nodes(self.ctx, r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return r
+
+    # -- ABI calls ------------------------------------------------------
+    def set_state(self, u):
+        u = self._dev(u, self.shape)
+        self._check(self.lib.opf_set_state(self.ctx, ctypes.c_void_p(u.data_ptr())))
+        self.stream.synchronize()
+
+    def get_state(self):
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_get_state(self.ctx, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def step(self, n=1):
+        self._check(self.lib.opf_step(self.ctx, int(n)))
+
+    def nonlinear(self, u):
+        u = self._dev(u, self.shape)
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_nonlinear(self.ctx, ctypes.c_void_p(u.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def vorticity(self, u):
+        u = self._dev(u, self.shape)
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_vorticity(self.ctx, ctypes.c_void_p(u.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def radial_solve(self, kind, rhs, want_pressure=False):
+        nf = 6 if kind == OPF_SOLVE_CORR else 3
+        rhs = self._dev(rhs, (nf,) + self.shape[1:])
+        out = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        p = None
+        if want_pressure:
+            p = self.torch.zeros(self.shape[1:], dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_radial_solve(
+            self.ctx, int(kind), ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(p.data_ptr() if p is not None else 0)))
+        return (out, p) if want_pressure else out
+
+    def newton_residual(self, x, T, shift):
+        x = self._dev(x, self.shape)
+        F = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        nrm = ctypes.c_double()
+        self._check(self.lib.opf_newton_residual(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T),
+                                                 float(shift), ctypes.c_void_p(F.data_ptr()),
+                                                 ctypes.byref(nrm)))
+        return F, nrm.value
+
+    KERNELS = ("zinv", "theta", "zfwd", "solve_pred", "solve_corr")
+
+    def profile_steps(self, n):
+        """Per-kernel device time (ms, summed) and launch counts over n
+        eagerly launched steps, from HIP events on the context's stream."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int32 * 5)()
+        self._check(self.lib.opf_profile_steps(self.ctx, int(n), ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def diagnostics(self):
+        d = opf_diag()
+        self._check(self.lib.opf_diagnostics(self.ctx, ctypes.byref(d)))
+        return {name: getattr(d, name) for name, _ in opf_diag._fields_}

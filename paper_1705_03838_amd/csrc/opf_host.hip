@@ -1,0 +1,965 @@
+// Host side of the pipe-flow time-step library: C ABI, create-time tables
+// (nodes, finite-difference weights, quadrature, banded LU factors,
+// influence-matrix data, FFT twiddles), workspace layout and the captured
+// step graph.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "opf_internal.h"
+
+using namespace opf;
+using cd = std::complex<double>;
+
+struct opf_ctx {
+    opf_params p{};
+    std::vector<double> r, rinv, quad, d1, d2, green;  // host copies
+    std::vector<int> s0;
+    int nk = 0, MU = 0, nfac = 0;
+    double qG_inv = 0.0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph = nullptr;
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Tables t{};
+    // buffers (device)
+    double *u = nullptr, *up = nullptr, *w64 = nullptr, *beta = nullptr, *partial = nullptr;
+    void *w = nullptr, *Nn = nullptr, *Np = nullptr, *H = nullptr, *G = nullptr;
+    float *u32 = nullptr, *up32 = nullptr;
+    void *twz = nullptr, *twt = nullptr;
+    bool have_state = false;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// ---- parameter checks ---------------------------------------------------
+bool factor23(int L) {
+    if (L <= 0) return false;
+    while (L % 2 == 0) L /= 2;
+    while (L % 3 == 0) L /= 3;
+    return L == 1;
+}
+
+opf_status validate(const opf_params* p, std::string* why) {
+    auto bad = [&](const char* s) { if (why) *why = s; return OPF_E_INVALID; };
+    if (!p) return bad("null parameters");
+    if (p->stencil != W9) return bad("stencil must be 9");
+    if (p->N < 12) return bad("N must be >= 12");
+    if (p->N > NMAX) { if (why) *why = "N > 64 not supported"; return OPF_E_UNSUPPORTED; }
+    if (p->M < 2 || p->K < 2 || p->M > 48 || p->K > 64) return bad("M must be in [2, 48], K in [2, 64]");
+    if (!factor23(3 * p->M) || !factor23(3 * p->K) || !nonlinear_supported(p->M, p->K)) {
+        if (why) *why = "3M and 3K must be supported FFT lengths (2^a 3^b <= 192)";
+        return OPF_E_UNSUPPORTED;
+    }
+    if (p->mp < 1) return bad("mp must be >= 1");
+    if (!(p->alpha > 0) || !(p->Re > 0) || !(p->dt > 0)) return bad("alpha, Re, dt must be > 0");
+    if (!(p->c > 0 && p->c <= 1)) return bad("c must be in (0, 1]");
+    if (p->n_corr < 1) return bad("n_corr must be >= 1");
+    if (p->precision != OPF_FP64 && p->precision != OPF_MIXED) return bad("unknown precision");
+    if (p->r_nodes) {
+        const double* r = p->r_nodes;
+        if (!(r[0] > 0) || r[p->N - 1] != 1.0) return bad("nodes must lie in (0,1] with r[N-1] = 1");
+        for (int i = 1; i < p->N; ++i)
+            if (!(r[i] > r[i - 1])) return bad("nodes must increase");
+    }
+    return OPF_OK;
+}
+
+// ---- finite-difference weights (Fornberg's recursion, Math. Comp. 51, 1988)
+// Weights c[d][j] with f^(d)(z) ~ sum_j c[d][j] f(x_j), d <= 2.
+void fornberg(double z, const double* x, int n, double c[3][W9]) {
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < n; ++j) c[d][j] = 0.0;
+    double c1 = 1.0, c4 = x[0] - z;
+    c[0][0] = 1.0;
+    for (int i = 1; i < n; ++i) {
+        const int mn = std::min(i, 2);
+        double c2 = 1.0;
+        const double c5 = c4;
+        c4 = x[i] - z;
+        for (int j = 0; j < i; ++j) {
+            const double c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {
+                for (int d = mn; d >= 1; --d) c[d][i] = c1 * (d * c[d - 1][i - 1] - c5 * c[d][i - 1]) / c2;
+                c[0][i] = -c1 * c5 * c[0][i - 1] / c2;
+            }
+            for (int d = mn; d >= 1; --d) c[d][j] = (c4 * c[d][j] - d * c[d - 1][j]) / c3;
+            c[0][j] = c4 * c[0][j] / c3;
+        }
+        c1 = c2;
+    }
+}
+
+// Extended node: index e >= 0 is r[e]; e < 0 is the mirror point -r[-e-1].
+double ext(const std::vector<double>& r, int e) { return e >= 0 ? r[e] : -r[-e - 1]; }
+int window_start(int n, int N) { return std::min(n - HALF, N - W9); }
+
+// Gauss-Legendre nodes / weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (t * p1 - p0) / (t * t - 1.0);
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+// ---- banded operators and LU ------------------------------------------
+// Dense N x N radial Laplacian L_{mu,kappa} (row N-1 left for the caller).
+void build_lap(const opf_ctx& c, int mu, double kap, std::vector<double>& A) {
+    const int N = c.p.N, par = std::abs(mu) & 1;
+    A.assign((size_t)N * N, 0.0);
+    for (int n = 0; n < N; ++n) {
+        for (int j = 0; j < W9; ++j) {
+            const int col = c.s0[n] + j;
+            A[(size_t)n * N + col] += c.d2[(par * N + n) * W9 + j] + c.rinv[n] * c.d1[(par * N + n) * W9 + j];
+        }
+        A[(size_t)n * N + n] -= double(mu) * mu * c.rinv[n] * c.rinv[n] + kap * kap;
+    }
+}
+
+// LU without pivoting of a matrix with at most 8 sub- and 4 super-diagonals;
+// writes the FACW-wide factor rows.  Returns false on element growth.
+bool band_lu(std::vector<double>& A, int N, double* F) {
+    double amax = 0.0;
+    for (double v : A) amax = std::max(amax, std::fabs(v));
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            if ((j < i - 8 || j > i + 4) && A[(size_t)i * N + j] != 0.0) return false;
+    for (int j = 0; j < N; ++j) {
+        const double piv = A[(size_t)j * N + j];
+        if (!(std::fabs(piv) > 1e-14 * amax)) return false;
+        for (int i = j + 1; i <= std::min(N - 1, j + 8); ++i) {
+            const double l = A[(size_t)i * N + j] / piv;
+            A[(size_t)i * N + j] = l;
+            for (int col = j + 1; col <= std::min(N - 1, j + 4); ++col) A[(size_t)i * N + col] -= l * A[(size_t)j * N + col];
+        }
+    }
+    double umax = 0.0, lmax = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            const double v = std::fabs(A[(size_t)i * N + j]);
+            if (j >= i) umax = std::max(umax, v);
+            else lmax = std::max(lmax, v);
+        }
+    if (umax > 1e3 * amax || lmax > 1e3) return false;
+    for (int i = 0; i < N; ++i) {
+        double* f = F + (size_t)i * FACW;
+        for (int j = 0; j < FACW; ++j) f[j] = 0.0;
+        for (int j = 0; j < 8; ++j)
+            if (i - 1 - j >= 0) f[j] = A[(size_t)i * N + (i - 1 - j)];
+        for (int j = 0; j < 4; ++j)
+            if (i + 1 + j < N) f[8 + j] = A[(size_t)i * N + (i + 1 + j)];
+        f[12] = 1.0 / A[(size_t)i * N + i];
+    }
+    return true;
+}
+
+// Host solve with a factor (same arithmetic order as the device).
+void band_solve(const double* F, int N, double* v) {
+    for (int i = 0; i < N; ++i) {
+        const double* f = F + (size_t)i * FACW;
+        double acc = v[i];
+        for (int j = 7; j >= 0; --j)
+            if (i - 1 - j >= 0) acc -= f[j] * v[i - 1 - j];
+        v[i] = acc;
+    }
+    for (int i = N - 1; i >= 0; --i) {
+        const double* f = F + (size_t)i * FACW;
+        double acc = v[i];
+        for (int j = 3; j >= 0; --j)
+            if (i + 1 + j < N) acc -= f[8 + j] * v[i + 1 + j];
+        v[i] = acc * f[12];
+    }
+}
+
+bool invert4(cd A[4][4], cd X[4][4]) {
+    cd M[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            M[i][j] = A[i][j];
+            M[i][4 + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 4; ++i)
+            if (std::abs(M[i][c]) > std::abs(M[piv][c])) piv = i;
+        if (std::abs(M[piv][c]) == 0.0) return false;
+        for (int j = 0; j < 8; ++j) std::swap(M[c][j], M[piv][j]);
+        const cd d = M[c][c];
+        for (int j = 0; j < 8; ++j) M[c][j] /= d;
+        for (int i = 0; i < 4; ++i)
+            if (i != c) {
+                const cd f = M[i][c];
+                for (int j = 0; j < 8; ++j) M[i][j] -= f * M[c][j];
+            }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) X[i][j] = M[i][4 + j];
+    return true;
+}
+
+// Nodes, folded finite-difference weights and quadrature (host, create time).
+void build_grid(opf_ctx* c, const double* r_nodes) {
+    const int N = c->p.N;
+    // nodes (default: positive Gauss-Lobatto points of T_{2N-1})
+    c->r.resize(N);
+    for (int n = 0; n < N; ++n)
+        c->r[n] = r_nodes ? r_nodes[n] : std::cos(M_PI * (N - 1 - n) / (2.0 * N - 1.0));
+    c->rinv.resize(N);
+    for (int n = 0; n < N; ++n) c->rinv[n] = 1.0 / c->r[n];
+
+    // finite-difference weights folded onto nodes with axis parity
+    c->s0.resize(N);
+    c->d1.assign(2 * N * W9, 0.0);
+    c->d2.assign(2 * N * W9, 0.0);
+    for (int n = 0; n < N; ++n) {
+        const int e0 = window_start(n, N);
+        c->s0[n] = std::max(e0, 0);
+        double x[W9], w[3][W9];
+        for (int j = 0; j < W9; ++j) x[j] = ext(c->r, e0 + j);
+        fornberg(c->r[n], x, W9, w);
+        for (int par = 0; par < 2; ++par) {
+            const double sgn = par == 0 ? 1.0 : -1.0;
+            for (int j = 0; j < W9; ++j) {
+                const int e = e0 + j;
+                const int col = e >= 0 ? e : -e - 1;
+                const double f = e >= 0 ? 1.0 : sgn;
+                c->d1[(par * N + n) * W9 + (col - c->s0[n])] += f * w[1][j];
+                c->d2[(par * N + n) * W9 + (col - c->s0[n])] += f * w[2][j];
+            }
+        }
+    }
+
+    // quadrature: exact integral of each interval's stencil interpolant times r
+    {
+        std::vector<double> gx, gw;
+        gauss_legendre(8, gx, gw);
+        c->quad.assign(N, 0.0);
+        for (int j = 0; j < N; ++j) {
+            const double lo = j == 0 ? 0.0 : c->r[j - 1], hi = c->r[j];
+            const int e0 = window_start(j, N);
+            double x[W9], w[3][W9];
+            for (int i = 0; i < W9; ++i) x[i] = ext(c->r, e0 + i);
+            for (int q = 0; q < 8; ++q) {
+                const double rq = 0.5 * (hi - lo) * gx[q] + 0.5 * (hi + lo);
+                const double wq = 0.5 * (hi - lo) * gw[q] * rq;
+                fornberg(rq, x, W9, w);  // w[0] = Lagrange basis values at rq
+                for (int i = 0; i < W9; ++i) {
+                    const int e = e0 + i;
+                    c->quad[e >= 0 ? e : -e - 1] += wq * w[0][i];
+                }
+            }
+        }
+    }
+
+}
+
+struct Layout {
+    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, twz, twt;
+    size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, total;
+};
+
+Layout layout(const opf_params& p) {
+    const size_t N = p.N, M = p.M, K = p.K, nk = 2 * K - 1;
+    const size_t MU = (size_t)p.mp * (M - 1) + 2;
+    const size_t nfac = MU * K + M * K;
+    const size_t S = M * nk * N;  // complex entries per field
+    const size_t Hn = N * M * 3 * K;
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.r = take(N * 8);
+    L.rinv = take(N * 8);
+    L.quad = take(N * 8);
+    L.d1 = take(2 * N * W9 * 8);
+    L.d2 = take(2 * N * W9 * 8);
+    L.s0 = take(N * 4);
+    L.fac = take(nfac * N * FACW * 8);
+    L.hom = take(M * K * NHOM * N * 8);
+    L.ainv = take(M * nk * 16 * 16);
+    L.green = take(N * 8);
+    L.twz = take(3 * K * 16);
+    L.twt = take(3 * M * 16);
+    L.u = take(3 * S * 16);
+    L.up = take(3 * S * 16);
+    L.w64 = take(3 * S * 16);
+    L.w = take(3 * S * 16);
+    L.Nn = take(3 * S * 16);
+    L.Np = take(3 * S * 16);
+    L.H = take(6 * Hn * 16);
+    L.G = take(3 * Hn * 16);
+    L.u32 = take(3 * S * 8);
+    L.up32 = take(3 * S * 8);
+    L.beta = take(8);
+    L.partial = take(2 * M * 8);
+    L.total = o;
+    return L;
+}
+
+#define HIPCHK(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);             \
+            return OPF_E_HIP;                                                           \
+        }                                                                               \
+    } while (0)
+
+template <typename T>
+__global__ void k_convert(const double* __restrict__ in, T* __restrict__ out, size_t n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = T(in[i]);
+}
+__global__ void k_widen(const float* __restrict__ in, double* __restrict__ out, size_t n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = double(in[i]);
+}
+
+hipError_t to_f32(const double* in, float* out, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert<float>, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t to_f64(const float* in, double* out, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_widen, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+size_t field_entries(const opf_ctx* c) { return (size_t)c->p.M * c->nk * c->p.N; }
+
+NLArgs nl_args(const opf_ctx* c, const void* u, const void* w, void* out) {
+    NLArgs a{};
+    a.N = c->p.N;
+    a.M = c->p.M;
+    a.K = c->p.K;
+    a.nk = c->nk;
+    const size_t S = field_entries(c);
+    const size_t esz = c->p.precision == OPF_MIXED ? 8 : 16;
+    for (int f = 0; f < 3; ++f) {
+        a.in[f] = static_cast<const unsigned char*>(u) + f * S * esz;
+        a.in[3 + f] = static_cast<const unsigned char*>(w) + f * S * esz;
+        a.out[f] = static_cast<unsigned char*>(out) + f * S * esz;
+    }
+    a.H = c->H;
+    a.G = c->G;
+    a.twz = c->twz;
+    a.twt = c->twt;
+    a.scale = 1.0 / (9.0 * c->p.K * c->p.M);
+    return a;
+}
+
+SolveArgs solve_args(const opf_ctx* c, int kind) {
+    SolveArgs a{};
+    a.N = c->p.N;
+    a.M = c->p.M;
+    a.K = c->p.K;
+    a.nk = c->nk;
+    a.mp = c->p.mp;
+    a.MU = c->MU;
+    a.kind = kind;
+    a.fixed_flux = c->p.fixed_flux;
+    a.alpha = c->p.alpha;
+    a.Re = c->p.Re;
+    a.c = c->p.c;
+    a.inv_dt = 1.0 / c->p.dt;
+    a.aexp = (1.0 - c->p.c) / c->p.Re;
+    a.force = 4.0 / c->p.Re;
+    a.beta_out = c->beta;
+    a.t = c->t;
+    return a;
+}
+
+// Enqueue one predictor-corrector step (captured into the step graph).
+opf_status enqueue_step(opf_ctx* c, hipStream_t s) {
+    const bool mixed = c->p.precision == OPF_MIXED;
+    const void* uin = mixed ? (const void*)c->u32 : (const void*)c->u;
+    const void* upin = mixed ? (const void*)c->up32 : (const void*)c->up;
+    if (c->p.nonlinear) HIPCHK(c, launch_nonlinear(nl_args(c, uin, c->w, c->Nn), c->p.precision, s));
+    SolveArgs a = solve_args(c, OPF_SOLVE_PRED);
+    a.u0 = c->u;
+    a.n0 = c->Nn;
+    a.u_out = mixed ? nullptr : c->up;
+    a.u_out32 = mixed ? c->up32 : nullptr;
+    a.w_out = c->w;
+    HIPCHK(c, launch_solve(a, c->p.precision, s));
+    for (int it = 0; it < c->p.n_corr; ++it) {
+        if (c->p.nonlinear) HIPCHK(c, launch_nonlinear(nl_args(c, upin, c->w, c->Np), c->p.precision, s));
+        SolveArgs b = solve_args(c, OPF_SOLVE_CORR);
+        b.u0 = c->u;
+        b.n0 = c->Nn;
+        b.n1 = c->Np;
+        const bool last = it == c->p.n_corr - 1;
+        b.u_out = last ? c->u : (mixed ? nullptr : c->up);
+        b.u_out32 = mixed ? (last ? c->u32 : c->up32) : nullptr;
+        b.w_out = c->w;
+        HIPCHK(c, launch_solve(b, c->p.precision, s));
+    }
+    return OPF_OK;
+}
+
+// omega of the state, and the FP32 shadows in mixed precision.
+opf_status refresh_derived(opf_ctx* c) {
+    const size_t n = 2 * 3 * field_entries(c);
+    AuxArgs x{};
+    x.N = c->p.N;
+    x.M = c->p.M;
+    x.K = c->p.K;
+    x.nk = c->nk;
+    x.mp = c->p.mp;
+    x.alpha = c->p.alpha;
+    x.u = c->u;
+    x.t = c->t;
+    x.mirror = 1;
+    if (c->p.precision == OPF_MIXED) {
+        x.w = c->w64;
+        HIPCHK(c, launch_vorticity(x, c->stream));
+        HIPCHK(c, to_f32(c->w64, static_cast<float*>(c->w), n, c->stream));
+        HIPCHK(c, to_f32(c->u, c->u32, n, c->stream));
+    } else {
+        x.w = static_cast<double*>(c->w);
+        HIPCHK(c, launch_vorticity(x, c->stream));
+    }
+    return OPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* opf_status_string(opf_status s) {
+    switch (s) {
+        case OPF_OK: return "ok";
+        case OPF_E_INVALID: return "invalid argument";
+        case OPF_E_NOMEM: return "workspace too small";
+        case OPF_E_HIP: return "HIP runtime error";
+        case OPF_E_UNSUPPORTED: return "unsupported size or option";
+        case OPF_E_NUMERIC: return "numerical failure";
+        case OPF_E_STATE: return "no state set";
+    }
+    return "unknown status";
+}
+
+const char* opf_last_error(const opf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+opf_status opf_default_params(opf_params* p) {
+    if (!p) return OPF_E_INVALID;
+    *p = opf_params{};
+    p->N = 24;
+    p->M = 8;
+    p->K = 8;
+    p->mp = 1;
+    p->stencil = 9;
+    p->alpha = 1.25;
+    p->Re = 2400.0;
+    p->dt = 0.01;
+    p->c = 0.5;
+    p->n_corr = 1;
+    p->fixed_flux = 1;
+    p->precision = OPF_FP64;
+    p->nonlinear = 1;
+    p->r_nodes = nullptr;
+    return OPF_OK;
+}
+
+opf_status opf_tables(const opf_params* p, double* r, double* quad, double* d1, double* d2, int32_t* s0) {
+    const opf_status st = validate(p, nullptr);
+    if (st != OPF_OK) return st;
+    opf_ctx c;
+    c.p = *p;
+    build_grid(&c, p->r_nodes);
+    const int N = p->N;
+    if (r) std::copy(c.r.begin(), c.r.end(), r);
+    if (quad) std::copy(c.quad.begin(), c.quad.end(), quad);
+    if (d1) std::copy(c.d1.begin(), c.d1.end(), d1);
+    if (d2) std::copy(c.d2.begin(), c.d2.end(), d2);
+    if (s0) for (int n = 0; n < N; ++n) s0[n] = c.s0[n];
+    return OPF_OK;
+}
+
+opf_status opf_workspace_size(const opf_params* p, size_t* bytes) {
+    if (!bytes) return OPF_E_INVALID;
+    const opf_status st = validate(p, nullptr);
+    if (st != OPF_OK) return st;
+    *bytes = layout(*p).total;
+    return OPF_OK;
+}
+
+opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                      opf_ctx** out) {
+    if (!out) return OPF_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    const opf_status st = validate(p, &why);
+    if (st != OPF_OK) return st;
+    const Layout Lo = layout(*p);
+    if (!dev_workspace || bytes < Lo.total) return OPF_E_NOMEM;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN != 0) return OPF_E_INVALID;
+    opf_ctx* c = new (std::nothrow) opf_ctx();
+    if (!c) return OPF_E_NOMEM;
+    c->p = *p;
+    c->p.r_nodes = nullptr;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<unsigned char*>(dev_workspace);
+    c->ws_bytes = bytes;
+    const int N = p->N, M = p->M, K = p->K, nk = 2 * K - 1;
+    c->nk = nk;
+    c->MU = p->mp * (M - 1) + 2;
+    c->nfac = c->MU * K + M * K;
+
+    build_grid(c, p->r_nodes);
+
+    // banded LU factors: H_{|mu|,|k|} then L_{m,|k|} (pressure, P(1) = 0)
+    std::vector<double> fac((size_t)c->nfac * N * FACW);
+    std::vector<double> A;
+    const double cr = p->c / p->Re;
+    for (int mu = 0; mu < c->MU; ++mu)
+        for (int k = 0; k < K; ++k) {
+            build_lap(*c, mu, p->alpha * k, A);
+            for (size_t i = 0; i < A.size(); ++i) A[i] = -cr * A[i];
+            for (int n = 0; n < N; ++n) A[(size_t)n * N + n] += 1.0 / p->dt;
+            for (int j = 0; j < N; ++j) A[(size_t)(N - 1) * N + j] = j == N - 1 ? 1.0 : 0.0;
+            if (!band_lu(A, N, &fac[((size_t)mu * K + k) * N * FACW])) {
+                c->err = "Helmholtz factor unstable without pivoting";
+                delete c;
+                return OPF_E_NUMERIC;
+            }
+        }
+    for (int mi = 0; mi < M; ++mi)
+        for (int k = 0; k < K; ++k) {
+            double* F = &fac[((size_t)c->MU * K + (size_t)mi * K + k) * N * FACW];
+            if (mi == 0 && k == 0) {  // unused: (0,0) has no pressure solve
+                for (int n = 0; n < N; ++n) F[(size_t)n * FACW + 12] = 1.0;
+                continue;
+            }
+            build_lap(*c, p->mp * mi, p->alpha * k, A);
+            for (int j = 0; j < N; ++j) A[(size_t)(N - 1) * N + j] = j == N - 1 ? 1.0 : 0.0;
+            if (!band_lu(A, N, F)) {
+                c->err = "pressure factor unstable without pivoting";
+                delete c;
+                return OPF_E_NUMERIC;
+            }
+        }
+    auto Hf = [&](int mu, int k) { return &fac[((size_t)std::abs(mu) * K + k) * N * FACW]; };
+    auto Lf = [&](int mi, int k) { return &fac[((size_t)c->MU * K + (size_t)mi * K + k) * N * FACW]; };
+
+    // influence data per (m,|k|) and inverse influence matrices per (m,k)
+    std::vector<double> hom((size_t)M * K * NHOM * N, 0.0);
+    std::vector<double> ainv((size_t)M * nk * 32, 0.0);
+    const int e = N - 1;
+    auto d1row = [&](int par, const std::vector<double>& v) {
+        double acc = 0.0;
+        for (int j = 0; j < W9; ++j) acc += c->d1[(par * N + e) * W9 + j] * v[c->s0[e] + j];
+        return acc;
+    };
+    for (int mi = 0; mi < M; ++mi) {
+        const int m = p->mp * mi;
+        for (int ka = 0; ka < K; ++ka) {
+            if (mi == 0 && ka == 0) continue;
+            double* h = &hom[((size_t)mi * K + ka) * NHOM * N];
+            std::vector<double> P1(N, 0.0), gp(N), gm(N), v(N);
+            P1[N - 1] = 1.0;
+            band_solve(Lf(mi, ka), N, P1.data());
+            for (int n = 0; n < N; ++n) {
+                double dP = 0.0;
+                for (int j = 0; j < W9; ++j) dP += c->d1[((m & 1) * N + n) * W9 + j] * P1[c->s0[n] + j];
+                gp[n] = dP - m * P1[n] * c->rinv[n];
+                gm[n] = dP + m * P1[n] * c->rinv[n];
+            }
+            std::vector<double> h1p(N), h1m(N), q(N), h2(N, 0.0), h3(N, 0.0), h4(N, 0.0);
+            for (int n = 0; n < N; ++n) { h1p[n] = -gp[n]; h1m[n] = -gm[n]; q[n] = P1[n]; }
+            h1p[N - 1] = h1m[N - 1] = q[N - 1] = 0.0;
+            h2[N - 1] = h3[N - 1] = h4[N - 1] = 1.0;
+            band_solve(Hf(m + 1, ka), N, h1p.data());
+            band_solve(Hf(m - 1, ka), N, h1m.data());
+            band_solve(Hf(m, ka), N, q.data());
+            band_solve(Hf(m + 1, ka), N, h2.data());
+            band_solve(Hf(m - 1, ka), N, h3.data());
+            band_solve(Hf(m, ka), N, h4.data());
+            for (int n = 0; n < N; ++n) {
+                h[n] = h1p[n];
+                h[N + n] = h1m[n];
+                h[2 * N + n] = q[n];
+                h[3 * N + n] = h2[n];
+                h[4 * N + n] = h3[n];
+                h[5 * N + n] = h4[n];
+                h[6 * N + n] = P1[n];
+            }
+            const int po = (m + 1) & 1;
+            const double re = c->rinv[e];
+            for (int sg = -1; sg <= 1; sg += 2) {
+                const int k = sg * ka;
+                if (ka == 0 && sg < 0) continue;
+                const double kap = p->alpha * k;
+                // g(v) = (v+(1), v-(1), v_z(1), div v(1)) for each homogeneous solution
+                auto divw = [&](const std::vector<double>& vp, const std::vector<double>& vm) {
+                    return 0.5 * (d1row(po, vp) + (1 + m) * vp[e] * re) + 0.5 * (d1row(po, vm) + (1 - m) * vm[e] * re);
+                };
+                const std::vector<double> zero(N, 0.0);
+                cd Am[4][4], Ai[4][4];
+                const cd I(0.0, 1.0);
+                // h1: (h1p, h1m, -i kappa q)
+                Am[0][0] = h1p[e];
+                Am[1][0] = h1m[e];
+                Am[2][0] = -I * kap * q[e];
+                Am[3][0] = divw(h1p, h1m) + I * kap * (-I * kap * q[e]);
+                Am[0][1] = h2[e]; Am[1][1] = 0.0; Am[2][1] = 0.0; Am[3][1] = divw(h2, zero);
+                Am[0][2] = 0.0; Am[1][2] = h3[e]; Am[2][2] = 0.0; Am[3][2] = divw(zero, h3);
+                Am[0][3] = 0.0; Am[1][3] = 0.0; Am[2][3] = h4[e]; Am[3][3] = I * kap * h4[e];
+                if (!invert4(Am, Ai)) {
+                    c->err = "singular influence matrix";
+                    delete c;
+                    return OPF_E_NUMERIC;
+                }
+                double* dst = &ainv[(((size_t)mi * nk + (k + K - 1)) * 16) * 2];
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        dst[2 * (4 * i + j)] = Ai[i][j].real();
+                        dst[2 * (4 * i + j) + 1] = Ai[i][j].imag();
+                    }
+            }
+        }
+    }
+    // flux Green's function: H_0 u_G = 1 (interior), u_G(1) = 0
+    c->green.assign(N, 1.0);
+    c->green[N - 1] = 0.0;
+    band_solve(Hf(0, 0), N, c->green.data());
+    {
+        double qg = 0.0;
+        for (int n = 0; n < N; ++n) qg += c->quad[n] * c->green[n];
+        c->qG_inv = 1.0 / qg;
+    }
+
+    // FFT twiddles e^{-2 pi i t / L}
+    const bool mixed = p->precision == OPF_MIXED;
+    auto twiddles = [&](int L, std::vector<double>& d, std::vector<float>& f) {
+        d.resize(2 * L);
+        f.resize(2 * L);
+        for (int t = 0; t < L; ++t) {
+            const double ang = -2.0 * M_PI * t / L;
+            d[2 * t] = std::cos(ang);
+            d[2 * t + 1] = std::sin(ang);
+            f[2 * t] = float(d[2 * t]);
+            f[2 * t + 1] = float(d[2 * t + 1]);
+        }
+    };
+    std::vector<double> twz, twt;
+    std::vector<float> twz32, twt32;
+    twiddles(3 * K, twz, twz32);
+    twiddles(3 * M, twt, twt32);
+
+    // carve the workspace and upload
+    unsigned char* ws = c->ws;
+    auto up = [&](size_t off, const void* src, size_t n) {
+        return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, c->stream);
+    };
+    hipError_t he = hipSuccess;
+    if (he == hipSuccess) he = up(Lo.r, c->r.data(), N * 8);
+    if (he == hipSuccess) he = up(Lo.rinv, c->rinv.data(), N * 8);
+    if (he == hipSuccess) he = up(Lo.quad, c->quad.data(), N * 8);
+    if (he == hipSuccess) he = up(Lo.d1, c->d1.data(), c->d1.size() * 8);
+    if (he == hipSuccess) he = up(Lo.d2, c->d2.data(), c->d2.size() * 8);
+    if (he == hipSuccess) he = up(Lo.s0, c->s0.data(), N * 4);
+    if (he == hipSuccess) he = up(Lo.fac, fac.data(), fac.size() * 8);
+    if (he == hipSuccess) he = up(Lo.hom, hom.data(), hom.size() * 8);
+    if (he == hipSuccess) he = up(Lo.ainv, ainv.data(), ainv.size() * 8);
+    if (he == hipSuccess) he = up(Lo.green, c->green.data(), N * 8);
+    if (he == hipSuccess) he = mixed ? up(Lo.twz, twz32.data(), twz32.size() * 4) : up(Lo.twz, twz.data(), twz.size() * 8);
+    if (he == hipSuccess) he = mixed ? up(Lo.twt, twt32.data(), twt32.size() * 4) : up(Lo.twt, twt.data(), twt.size() * 8);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        c->err = std::string("upload: ") + hipGetErrorString(he);
+        delete c;
+        return OPF_E_HIP;
+    }
+    c->t.r = reinterpret_cast<const double*>(ws + Lo.r);
+    c->t.rinv = reinterpret_cast<const double*>(ws + Lo.rinv);
+    c->t.quad = reinterpret_cast<const double*>(ws + Lo.quad);
+    c->t.d1 = reinterpret_cast<const double*>(ws + Lo.d1);
+    c->t.d2 = reinterpret_cast<const double*>(ws + Lo.d2);
+    c->t.s0 = reinterpret_cast<const int*>(ws + Lo.s0);
+    c->t.fac = reinterpret_cast<const double*>(ws + Lo.fac);
+    c->t.hom = reinterpret_cast<const double*>(ws + Lo.hom);
+    c->t.ainv = reinterpret_cast<const double*>(ws + Lo.ainv);
+    c->t.green = reinterpret_cast<const double*>(ws + Lo.green);
+    c->t.qG_inv = c->qG_inv;
+    c->twz = ws + Lo.twz;
+    c->twt = ws + Lo.twt;
+    c->u = reinterpret_cast<double*>(ws + Lo.u);
+    c->up = reinterpret_cast<double*>(ws + Lo.up);
+    c->w64 = reinterpret_cast<double*>(ws + Lo.w64);
+    c->w = ws + Lo.w;
+    c->Nn = ws + Lo.Nn;
+    c->Np = ws + Lo.Np;
+    c->H = ws + Lo.H;
+    c->G = ws + Lo.G;
+    c->u32 = reinterpret_cast<float*>(ws + Lo.u32);
+    c->up32 = reinterpret_cast<float*>(ws + Lo.up32);
+    c->beta = reinterpret_cast<double*>(ws + Lo.beta);
+    c->partial = reinterpret_cast<double*>(ws + Lo.partial);
+    *out = c;
+    return OPF_OK;
+}
+
+opf_status opf_destroy(opf_ctx* c) {
+    if (!c) return OPF_E_INVALID;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+    return OPF_OK;
+}
+
+opf_status opf_get_nodes(const opf_ctx* c, double* r) {
+    if (!c || !r) return OPF_E_INVALID;
+    std::copy(c->r.begin(), c->r.end(), r);
+    return OPF_OK;
+}
+
+opf_status opf_set_state(opf_ctx* c, const void* u) {
+    if (!c || !u) return OPF_E_INVALID;
+    HIPCHK(c, hipMemcpyAsync(c->u, u, 3 * field_entries(c) * 16, hipMemcpyDeviceToDevice, c->stream));
+    const opf_status st = refresh_derived(c);
+    if (st != OPF_OK) return st;
+    c->have_state = true;
+    return OPF_OK;
+}
+
+opf_status opf_get_state(opf_ctx* c, void* u) {
+    if (!c || !u) return OPF_E_INVALID;
+    if (!c->have_state) return OPF_E_STATE;
+    HIPCHK(c, hipMemcpyAsync(u, c->u, 3 * field_entries(c) * 16, hipMemcpyDeviceToDevice, c->stream));
+    return OPF_OK;
+}
+
+opf_status opf_step(opf_ctx* c, int32_t nsteps) {
+    if (!c || nsteps < 0) return OPF_E_INVALID;
+    if (!c->have_state) return OPF_E_STATE;
+    if (!c->graph) {
+        if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        const opf_status st = enqueue_step(c, c->cap);
+        hipError_t he = hipStreamEndCapture(c->cap, &g);
+        if (st != OPF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (he != hipSuccess) {
+            c->err = std::string("capture: ") + hipGetErrorString(he);
+            return OPF_E_HIP;
+        }
+        he = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (he != hipSuccess) {
+            c->graph = nullptr;
+            c->err = std::string("instantiate: ") + hipGetErrorString(he);
+            return OPF_E_HIP;
+        }
+    }
+    for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    return OPF_OK;
+}
+
+opf_status opf_profile_steps(opf_ctx* c, int32_t nsteps, double* ms, int32_t* launches) {
+    if (!c || !ms || !launches || nsteps < 1) return OPF_E_INVALID;
+    if (!c->have_state) return OPF_E_STATE;
+    const bool mixed = c->p.precision == OPF_MIXED;
+    const int nk = 5;  // zinv, theta, zfwd, solve (predictor), solve (corrector)
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    auto mark = [&](int k) -> hipError_t {
+        hipEvent_t e;
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) return he;
+        ev.push_back(e);
+        kind.push_back(k);
+        return hipEventRecord(e, c->stream);
+    };
+    hipError_t he = hipSuccess;
+    const void* uin = mixed ? (const void*)c->u32 : (const void*)c->u;
+    const void* upin = mixed ? (const void*)c->up32 : (const void*)c->up;
+    for (int st = 0; st < nsteps && he == hipSuccess; ++st) {
+        for (int half = 0; half < 2 && he == hipSuccess; ++half) {
+            if (c->p.nonlinear) {
+                NLArgs a = nl_args(c, half ? upin : uin, c->w, half ? c->Np : c->Nn);
+                he = mark(-1);
+                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 0, c->stream);
+                if (he == hipSuccess) he = mark(0);
+                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 1, c->stream);
+                if (he == hipSuccess) he = mark(1);
+                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 2, c->stream);
+                if (he == hipSuccess) he = mark(2);
+            } else {
+                he = mark(-1);
+            }
+            if (he != hipSuccess) break;
+            SolveArgs b = solve_args(c, half ? OPF_SOLVE_CORR : OPF_SOLVE_PRED);
+            b.u0 = c->u;
+            b.n0 = c->Nn;
+            b.n1 = c->Np;
+            b.u_out = half ? c->u : (mixed ? nullptr : c->up);
+            b.u_out32 = mixed ? (half ? c->u32 : c->up32) : nullptr;
+            b.w_out = c->w;
+            he = launch_solve(b, c->p.precision, c->stream);
+            if (he == hipSuccess) he = mark(3 + half);
+        }
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    for (int k = 0; k < nk; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    for (size_t i = 1; i < ev.size() && he == hipSuccess; ++i) {
+        if (kind[i] < 0) continue;
+        float t = 0.0f;
+        he = hipEventElapsedTime(&t, ev[i - 1], ev[i]);
+        ms[kind[i]] += t;
+        launches[kind[i]] += 1;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (he != hipSuccess) {
+        c->err = std::string("profile: ") + hipGetErrorString(he);
+        return OPF_E_HIP;
+    }
+    return OPF_OK;
+}
+
+opf_status opf_vorticity(opf_ctx* c, const void* u, void* w) {
+    if (!c || !u || !w) return OPF_E_INVALID;
+    AuxArgs x{};
+    x.N = c->p.N;
+    x.M = c->p.M;
+    x.K = c->p.K;
+    x.nk = c->nk;
+    x.mp = c->p.mp;
+    x.alpha = c->p.alpha;
+    x.u = static_cast<const double*>(u);
+    x.w = static_cast<double*>(w);
+    x.t = c->t;
+    HIPCHK(c, launch_vorticity(x, c->stream));
+    return OPF_OK;
+}
+
+opf_status opf_nonlinear(opf_ctx* c, const void* u, void* n) {
+    if (!c || !u || !n) return OPF_E_INVALID;
+    const size_t cnt = 2 * 3 * field_entries(c);
+    // omega into w64, then the transforms in the working precision; the
+    // 'up' / 'up32' buffers hold the input copy
+    opf_status st = opf_vorticity(c, u, c->w64);
+    if (st != OPF_OK) return st;
+    if (c->p.precision == OPF_MIXED) {
+        float* uin = c->up32;
+        float* win = static_cast<float*>(c->w);
+        float* nout = reinterpret_cast<float*>(c->Np);
+        HIPCHK(c, to_f32(static_cast<const double*>(u), uin, cnt, c->stream));
+        HIPCHK(c, to_f32(c->w64, win, cnt, c->stream));
+        HIPCHK(c, launch_nonlinear(nl_args(c, uin, win, nout), OPF_MIXED, c->stream));
+        HIPCHK(c, to_f64(nout, static_cast<double*>(n), cnt, c->stream));
+        if (c->have_state) return refresh_derived(c);  // w was overwritten
+        return OPF_OK;
+    }
+    HIPCHK(c, launch_nonlinear(nl_args(c, u, c->w64, n), OPF_FP64, c->stream));
+    return OPF_OK;
+}
+
+opf_status opf_radial_solve(opf_ctx* c, int32_t kind, const void* rhs, void* u_out, void* p_out) {
+    if (!c || !rhs || !u_out) return OPF_E_INVALID;
+    if (kind != OPF_SOLVE_PRED && kind != OPF_SOLVE_CORR && kind != OPF_SOLVE_RAW) return OPF_E_INVALID;
+    if (kind != OPF_SOLVE_RAW && !c->have_state) return OPF_E_STATE;
+    SolveArgs a = solve_args(c, kind);
+    a.u0 = c->u;
+    const size_t S3 = 3 * field_entries(c);
+    a.n0 = rhs;
+    a.n1 = kind == OPF_SOLVE_CORR ? static_cast<const double*>(rhs) + 2 * S3 : nullptr;
+    a.u_out = static_cast<double*>(u_out);
+    a.p_out = static_cast<double*>(p_out);
+    a.w_out = c->w64;
+    // nonlinear inputs are complex128 here whatever the working precision
+    HIPCHK(c, launch_solve(a, OPF_FP64, c->stream));
+    return OPF_OK;
+}
+
+opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
+    if (!c || !d) return OPF_E_INVALID;
+    if (!c->have_state) return OPF_E_STATE;
+    const int N = c->p.N, M = c->p.M, K = c->p.K;
+    AuxArgs x{};
+    x.N = N;
+    x.M = M;
+    x.K = K;
+    x.nk = c->nk;
+    x.mp = c->p.mp;
+    x.alpha = c->p.alpha;
+    x.u = c->u;
+    x.w = c->w64;
+    x.partial = c->partial;
+    x.t = c->t;
+    HIPCHK(c, launch_vorticity(x, c->stream));
+    HIPCHK(c, launch_energy(x, c->stream));
+    std::vector<double> part(2 * M), uz(2 * N);
+    double beta = 0.0;
+    const size_t S = field_entries(c);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, 2 * M * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uz.data(), c->u + 2 * (2 * S + (size_t)(K - 1) * N), 2 * N * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&beta, c->beta, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double su = 0.0, sw = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const double cm = m == 0 ? 1.0 : 2.0;
+        su += cm * part[2 * m];
+        sw += cm * part[2 * m + 1];
+    }
+    const double lz = 2.0 * M_PI / c->p.alpha;
+    const double vol = 2.0 * M_PI * lz / c->p.mp;
+    double flux = 0.0, dz = 0.0;
+    for (int n = 0; n < N; ++n) flux += c->quad[n] * uz[2 * n];
+    for (int j = 0; j < W9; ++j) dz += c->d1[(N - 1) * W9 + j] * uz[2 * (c->s0[N - 1] + j)];
+    *d = opf_diag{};
+    d->E = 0.5 * vol * su;
+    d->D = vol * sw / c->p.Re;
+    d->flux = flux;
+    d->beta = beta;
+    d->I = 4.0 / c->p.Re * (1.0 + beta) * vol * flux;
+    d->tau_w = -dz;
+    d->E_lam = M_PI * lz / (6.0 * c->p.mp);
+    d->I_lam = d->D_lam = 2.0 * M_PI * lz / (c->p.mp * c->p.Re);
+    if (!std::isfinite(d->E) || !std::isfinite(d->D)) return OPF_E_NUMERIC;
+    return OPF_OK;
+}
+
+opf_status opf_newton_residual(opf_ctx* c, const void* x, double T, double shift, void* F, double* norm) {
+    (void)c; (void)x; (void)T; (void)shift; (void)F; (void)norm;
+    return OPF_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal definitions shared by the host code and the HIP kernels of the
+// pipe-flow time-step library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/opf.h"
+
+namespace opf {
+
+constexpr int W9 = 9;     // finite-difference stencil width (Section 2: 9 points)
+constexpr int HALF = 4;   // points on each side of a centred stencil
+constexpr int FACW = 13;  // doubles per LU factor row: 8 of L, 4 of U, 1/U_ii
+constexpr int NHOM = 7;   // real radial lines of influence data per (m,|k|)
+constexpr int NMAX = 64;  // radial points handled by one solve workgroup
+constexpr int TILE = 8;   // radial lines per z-transform workgroup, z lines per theta workgroup
+
+// Complex number used by the kernels (interleaved re/im, same layout as
+// complex128 / complex64 in memory).
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+// Device-resident tables built at create time (all pointers into the
+// caller's workspace).
+struct Tables {
+    const double* r;      // [N] radial nodes
+    const double* rinv;   // [N] 1/r
+    const double* quad;   // [N] weights of int_0^1 g(r) r dr (g even in r)
+    const double* d1;     // [2][N][9] folded first-derivative weights, parity 0 even / 1 odd
+    const double* d2;     // [2][N][9] folded second-derivative weights
+    const int* s0;        // [N] first column of row n's 9-point window
+    const double* fac;    // [nfac][N][FACW] banded LU factors
+    const double* hom;    // [M][K][NHOM][N] influence data (h1+, h1-, q, h2, h3, h4, P1)
+    const double* ainv;   // [M][2K-1][16][2] inverse influence matrices (complex)
+    const double* green;  // [N] flux Green's function: H_0 u_G = 1, u_G(1) = 0
+    double qG_inv;        // 1 / int_0^1 u_G r dr
+};
+
+// Arguments of one nonlinear-term evaluation (three transform kernels).
+struct NLArgs {
+    int N, M, K, nk;
+    const void* in[6];  // spectral u_r,u_t,u_z,w_r,w_t,w_z  [M][nk][N] (storage type)
+    void* H;            // z-transformed fields [6][N][M][3K] (compute type)
+    void* G;            // theta-transformed products [3][N][M][3K] (compute type)
+    void* out[3];       // spectral N_r, N_t, N_z [M][nk][N] (storage type)
+    const void* twz;    // e^{-2 pi i t / 3K}, t < 3K (compute type)
+    const void* twt;    // e^{-2 pi i t / 3M}, t < 3M (compute type)
+    double scale;       // 1 / (9 K M)
+};
+
+// Arguments of one substep solve (one kernel).
+struct SolveArgs {
+    int N, M, K, nk, mp, MU;
+    int kind;           // OPF_SOLVE_PRED / CORR / RAW
+    int fixed_flux;
+    double alpha, Re, c, inv_dt, aexp, force;
+    const double* u0;   // u^n (external layout, complex128); PRED / CORR
+    const void* n0;     // N^n (nonlinear storage type), or R (complex128) for RAW
+    const void* n1;     // N^p for CORR
+    double* u_out;      // complex128 output state (nullable)
+    float* u_out32;     // complex64 shadow of the output state (nullable)
+    void* w_out;        // vorticity of the output (nonlinear storage type, nullable)
+    double* p_out;      // pressure head [M][nk][N] complex128 (nullable)
+    double* beta_out;   // flux correction beta (device scalar)
+    double* g_out;      // [M*K] largest |g| after correction, per workgroup (nullable)
+    Tables t;
+};
+
+// Arguments of the vorticity / diagnostics kernels.
+struct AuxArgs {
+    int N, M, K, nk, mp;
+    int mirror;         // vorticity: m = 0, k < 0 written as conjugates of k > 0
+    double alpha;
+    const double* u;    // complex128 external layout
+    double* w;          // complex128 output (vorticity)
+    double* partial;    // [M][2] per-m sums of |u|^2 and |omega|^2 (quadrature weighted)
+    Tables t;
+};
+
+// Launchers (return the first HIP error).
+hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s);
+// One of the three transform kernels: 0 z-inverse, 1 theta + product, 2 z-forward.
+hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s);
+bool nonlinear_supported(int M, int K);
+hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s);
+hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s);
+hipError_t launch_energy(const AuxArgs& a, hipStream_t s);
+
+}  // namespace opf

@@ -1,0 +1,230 @@
+"""GPU parity: every C-ABI call against the CPU FP64 oracle on the same seeded inputs.
+
+Tolerances: the FP64 path must agree with the oracle to <= 1e-11 relative per
+step (norm relative to the state's largest coefficient).  Pieces without a
+linear solve (transforms, vorticity) are held to 1e-13.  The radial solves
+differ from the oracle's dense LAPACK solves only by rounding; the pressure
+operator's condition (~1/h^2 at the wall) sets the 1e-11 bound.
+"""
+import numpy as np
+import pytest
+
+from inputs import WORKLOADS, laminar_state, make_state, workload_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # N, M, K, mp, alpha, Re, dt -- several tiles and ragged tails in n and z
+    "tiny": dict(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01),
+    "ragged": dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007),
+    "odd12": dict(N=13, M=3, K=3, mp=1, alpha=1.6, Re=800.0, dt=0.02),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def solver(torch_cuda, **kw):
+    import paper_1705_03838_amd as opf
+    return opf.Solver(**kw)
+
+
+def oracle_for(s, **kw):
+    from oracle import Oracle, Params
+    return Oracle(Params(r=s.nodes(), **kw))
+
+
+def state_for(kw, r, energy=1e-2, seed=3):
+    return make_state(kw["N"], kw["M"], kw["K"], kw["mp"], kw["alpha"], r, energy, 4.0, 4.0, seed)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nonlinear_and_vorticity(torch_cuda, case):
+    kw = CASES[case]
+    say("nonlinear/vorticity", case, kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = state_for(kw, s.nodes(), 5e-2, 11)
+    w = s.vorticity(torch_cuda.from_numpy(u)).cpu().numpy()
+    assert rel(w, o.vorticity(u)) < 1e-13
+    n = s.nonlinear(torch_cuda.from_numpy(u)).cpu().numpy()
+    assert rel(n, o.nonlinear(u)) < 1e-13
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_radial_solve_raw(torch_cuda, case):
+    import paper_1705_03838_amd as opf
+    from oracle.spectral import to_pm
+    kw = CASES[case]
+    say("radial_solve RAW", case, kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((3, kw["M"], 2 * kw["K"] - 1, kw["N"])) * (1 + 0j)
+    R = R + 1j * rng.standard_normal(R.shape)
+    K = kw["K"]
+    for k in range(1, K):  # a real right-hand side field
+        R[:, 0, K - 1 - k] = np.conj(R[:, 0, K - 1 + k])
+    R[:, 0, K - 1] = R[:, 0, K - 1].real
+    u, p = s.radial_solve(opf.OPF_SOLVE_RAW, torch_cuda.from_numpy(R), want_pressure=True)
+    uref, pref = o.solve(to_pm(R), want_pressure=True)
+    assert rel(u.cpu().numpy(), uref) < 1e-11
+    # pressure of (0,0) is not computed (u_r = 0 there)
+    p = p.cpu().numpy()
+    pref[0, K - 1] = 0
+    assert rel(p, pref) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged"])
+def test_radial_solve_pred_corr(torch_cuda, case):
+    import paper_1705_03838_amd as opf
+    from oracle.spectral import to_pm
+    kw = CASES[case]
+    say("radial_solve PRED/CORR", case, kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = state_for(kw, s.nodes(), 1e-2, 7)
+    s.set_state(torch_cuda.from_numpy(u))
+    n0 = o.nonlinear(u)
+    n1 = o.nonlinear(state_for(kw, s.nodes(), 1e-2, 8))
+    got = s.radial_solve(opf.OPF_SOLVE_PRED, torch_cuda.from_numpy(n0)).cpu().numpy()
+    Rlin = o.explicit(u)
+    assert rel(got, o.solve(Rlin + to_pm(n0))) < 1e-11
+    got = s.radial_solve(opf.OPF_SOLVE_CORR, torch_cuda.from_numpy(np.concatenate([n0, n1]))).cpu().numpy()
+    ref = o.solve(Rlin + o.p.c * to_pm(n1) + (1 - o.p.c) * to_pm(n0))
+    assert rel(got, ref) < 1e-11
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity_per_step(torch_cuda, case):
+    kw = CASES[case]
+    say("step parity", case, kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = state_for(kw, s.nodes(), 1e-2, 21)
+    s.set_state(torch_cuda.from_numpy(u))
+    for i in range(5):
+        s.step(1)
+        got = s.get_state().cpu().numpy()
+        ref = o.step(u)
+        err = rel(got, ref)
+        say(f"  step {i}: rel err {err:.2e}")
+        assert err < 1e-11
+        u = got  # per-step parity: next oracle step starts from the GPU state
+        assert abs(s.diagnostics()["beta"] - o.beta) < 1e-9
+
+
+def test_tiny_workload_100_steps(torch_cuda):
+    """The tiny workload (N=24, |m|,|k| < 8, Re 2400, dt 0.01, 100 steps):
+    per-step parity every 10 steps, diagnostics against the oracle's."""
+    w = WORKLOADS["tiny"]
+    kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
+    say("tiny workload 100 steps", kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = workload_state(w, s.nodes())
+    s.set_state(torch_cuda.from_numpy(u))
+    for block in range(10):
+        s.step(9)
+        u = s.get_state().cpu().numpy()
+        s.step(1)
+        got = s.get_state().cpu().numpy()
+        ref = o.step(u)
+        err = rel(got, ref)
+        say(f"  step {10 * block + 9}: rel err {err:.2e}")
+        assert err < 1e-11
+    d = s.diagnostics()
+    dref = o.diagnostics(got)
+    for key in ("E", "I", "D", "tau_w", "flux"):
+        assert abs(d[key] - dref[key]) <= 1e-11 * abs(dref[key]) + 1e-15, key
+
+
+def test_laminar_fixed_point_gpu(torch_cuda):
+    kw = dict(N=64, M=48, K=64, mp=1, alpha=0.5, Re=5300.0, dt=0.005)
+    say("laminar fixed point at N=64, M=48, K=64")
+    s = solver(torch_cuda, **kw)
+    u = laminar_state(64, 48, 64, s.nodes())
+    s.set_state(torch_cuda.from_numpy(u))
+    s.step(20)
+    got = s.get_state().cpu().numpy()
+    assert np.max(np.abs(got - u)) < 1e-13
+    d = s.diagnostics()
+    assert abs(d["E"] / d["E_lam"] - 1) < 1e-13 and abs(d["tau_w"] - 2) < 1e-11
+
+
+def test_pipe64_step_parity(torch_cuda):
+    """Full-size workload N=64, |m| < 48, |k| < 64, Re 5300, dt 0.005 with the
+    launch configuration the benchmark times: 10 steps, then one step compared
+    in full with the oracle."""
+    w = WORKLOADS["pipe64"]
+    kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
+    say("pipe64 step parity", kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = workload_state(w, s.nodes())
+    s.set_state(torch_cuda.from_numpy(u))
+    s.step(10)
+    u = s.get_state().cpu().numpy()
+    s.step(1)
+    got = s.get_state().cpu().numpy()
+    ref = o.step(u)
+    err = rel(got, ref)
+    say(f"  pipe64 rel err {err:.2e}")
+    assert err < 1e-11
+
+
+def test_deterministic_and_resumable(torch_cuda):
+    kw = CASES["tiny"]
+    say("determinism / resume", kw)
+    s = solver(torch_cuda, **kw)
+    u = state_for(kw, s.nodes(), 1e-2, 4)
+    s.set_state(torch_cuda.from_numpy(u))
+    s.step(6)
+    a = s.get_state().cpu().numpy()
+    s.set_state(torch_cuda.from_numpy(u))
+    s.step(3)
+    mid = s.get_state()
+    s2 = solver(torch_cuda, **kw)
+    s2.set_state(mid)
+    s2.step(3)
+    b = s2.get_state().cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_mixed_precision_error(torch_cuda):
+    """FP32 transforms and products, FP64 solves: error against the FP64
+    oracle after 10 and 100 steps on the tiny workload (<= 1e-5 relative in
+    velocity, energy and wall shear)."""
+    import paper_1705_03838_amd as opf
+    w = WORKLOADS["tiny"]
+    kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
+    say("mixed precision 10/100 steps", kw)
+    s = solver(torch_cuda, precision=opf.OPF_MIXED, **kw)
+    o = oracle_for(s, **kw)
+    u = workload_state(w, s.nodes())
+    s.set_state(torch_cuda.from_numpy(u))
+    ref = u
+    done = 0
+    for target in (10, 100):
+        s.step(target - done)
+        ref = o.run(ref, target - done)
+        done = target
+        got = s.get_state().cpu().numpy()
+        ev = o.energy_norm(got - ref) / o.energy_norm(ref)
+        d, dref = s.diagnostics(), o.diagnostics(ref)
+        eE = abs(d["E"] - dref["E"]) / dref["E"]
+        et = abs(d["tau_w"] - dref["tau_w"]) / dref["tau_w"]
+        say(f"  {target} steps: velocity {ev:.2e} energy {eE:.2e} wall shear {et:.2e}")
+        assert ev < 1e-5 and eE < 1e-5 and et < 1e-5
