@@ -176,33 +176,32 @@ bool band_lu(std::vector<double>& A, int N, double* F) {
             else lmax = std::max(lmax, v);
         }
     if (umax > 1e3 * amax || lmax > 1e3) return false;
+    // column records: row i of F holds column i of L below the diagonal
+    // (L[i+1..i+8][i]), column i of U above it (U[i-1..i-4][i]) and 1/U_ii
     for (int i = 0; i < N; ++i) {
         double* f = F + (size_t)i * FACW;
         for (int j = 0; j < FACW; ++j) f[j] = 0.0;
-        for (int j = 0; j < 8; ++j)
-            if (i - 1 - j >= 0) f[j] = A[(size_t)i * N + (i - 1 - j)];
-        for (int j = 0; j < 4; ++j)
-            if (i + 1 + j < N) f[8 + j] = A[(size_t)i * N + (i + 1 + j)];
+        for (int d = 0; d < 8; ++d)
+            if (i + 1 + d < N) f[d] = A[(size_t)(i + 1 + d) * N + i];
+        for (int d = 0; d < 4; ++d)
+            if (i - 1 - d >= 0) f[8 + d] = A[(size_t)(i - 1 - d) * N + i];
         f[12] = 1.0 / A[(size_t)i * N + i];
     }
     return true;
 }
 
-// Host solve with a factor (same arithmetic order as the device).
+// Host solve with a column-record factor (right-looking, as on the device).
 void band_solve(const double* F, int N, double* v) {
     for (int i = 0; i < N; ++i) {
         const double* f = F + (size_t)i * FACW;
-        double acc = v[i];
-        for (int j = 7; j >= 0; --j)
-            if (i - 1 - j >= 0) acc -= f[j] * v[i - 1 - j];
-        v[i] = acc;
+        for (int d = 0; d < 8; ++d)
+            if (i + 1 + d < N) v[i + 1 + d] -= f[d] * v[i];
     }
     for (int i = N - 1; i >= 0; --i) {
         const double* f = F + (size_t)i * FACW;
-        double acc = v[i];
-        for (int j = 3; j >= 0; --j)
-            if (i + 1 + j < N) acc -= f[8 + j] * v[i + 1 + j];
-        v[i] = acc * f[12];
+        v[i] *= f[12];
+        for (int d = 0; d < 4; ++d)
+            if (i - 1 - d >= 0) v[i - 1 - d] -= f[8 + d] * v[i];
     }
 }
 

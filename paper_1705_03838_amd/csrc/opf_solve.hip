@@ -21,7 +21,6 @@
 namespace opf {
 
 constexpr int LSTR = NMAX + 2;            // LDS line stride (complex): avoids bank aliasing
-constexpr int FSTR = NMAX * FACW + 2;     // LDS factor stride (doubles)
 
 struct dcplx {
     double x, y;
@@ -40,39 +39,23 @@ __device__ __forceinline__ dcplx stencil(const double* w, const dcplx* line, int
     return acc;
 }
 
-// Solve A x = b in place for one real right-hand side (element i at v[2*i]),
-// A = LU without pivoting; factor row i: F[0..7] multiply x[i-1..i-8] in the
-// forward pass, F[8..11] multiply x[i+1..i+4] in the backward pass,
-// F[12] = 1 / U_ii.  Out-of-band entries are zero.
-__device__ __forceinline__ void lu_solve(const double* F, double* v, int N) {
-    double w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, w7 = 0;
-    for (int i = 0; i < N; ++i) {
-        const double* f = F + i * FACW;
-        double acc = v[2 * i];
-        acc -= f[7] * w7;
-        acc -= f[6] * w6;
-        acc -= f[5] * w5;
-        acc -= f[4] * w4;
-        acc -= f[3] * w3;
-        acc -= f[2] * w2;
-        acc -= f[1] * w1;
-        acc -= f[0] * w0;
-        v[2 * i] = acc;
-        w7 = w6; w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = acc;
+// Row weights of both axis parities held in registers (one lane = one row).
+struct RowW {
+    double e[W9], o[W9];
+    __device__ __forceinline__ void load(const double* tab, int N, int n) {
+#pragma unroll
+        for (int j = 0; j < W9; ++j) {
+            e[j] = tab[n * W9 + j];
+            o[j] = tab[(N + n) * W9 + j];
+        }
     }
-    double x0 = 0, x1 = 0, x2 = 0, x3 = 0;
-    for (int i = N - 1; i >= 0; --i) {
-        const double* f = F + i * FACW;
-        double acc = v[2 * i];
-        acc -= f[11] * x3;
-        acc -= f[10] * x2;
-        acc -= f[9] * x1;
-        acc -= f[8] * x0;
-        acc *= f[12];
-        v[2 * i] = acc;
-        x3 = x2; x2 = x1; x1 = x0; x0 = acc;
+    __device__ __forceinline__ dcplx apply(int par, const dcplx* line, int s0) const {
+        dcplx acc = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < W9; ++j) acc = acc + (par ? o[j] : e[j]) * line[s0 + j];
+        return acc;
     }
-}
+};
 
 template <typename T>
 __device__ __forceinline__ dcplx load_c(const void* base, size_t idx) {
@@ -106,60 +89,210 @@ __device__ __forceinline__ void vort_row(const Tables& t, int N, int n, int m, d
     wz = 0.5 * ix(am - ap);
 }
 
-template <typename TNL>
-__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
-    __shared__ dcplx sU[2][3][LSTR];  // u^n (+,-,z)
-    __shared__ dcplx sR[2][3][LSTR];  // right-hand side -> solution
-    __shared__ dcplx sP[2][LSTR];     // div R -> pressure
-    __shared__ double sF[3][FSTR];    // LU factors
-    __shared__ dcplx sA[2][4];        // influence coefficients a_j
-    __shared__ double sRed[64];
+// Substitution for one real right-hand side living in LDS (`col`, element i
+// at col[2 i]) with a factor in LDS whose row record i holds column i of L
+// below the diagonal (8 values), column i of U above it (4 values) and
+// 1/U_ii.  Right-looking: once y_i is known it updates the next 8 entries,
+// kept in registers, so only one FMA per row lies on the dependency chain;
+// factor records and right-hand-side entries are fetched PF rows ahead.
+// Rows N..NB-1 of the factor and of `col` are zero (the padded tail stays
+// zero; no branches).
+template <int NB>
+__device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* col) {
+    constexpr int PF = 3;
+    double2 L[PF][4];
+    double nb[PF];  // col[i + 8] for the coming rows
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const double2* f = reinterpret_cast<const double2*>(F + p * FACW);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) L[p][j] = f[j];
+        nb[p] = 8 + p < NB ? col[2 * (8 + p)] : 0.0;
+    }
+    double b0 = col[0], b1 = col[2], b2 = col[4], b3 = col[6];
+    double b4 = col[8], b5 = col[10], b6 = col[12], b7 = col[14];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int p = i % PF;
+        const double2 l01 = L[p][0], l23 = L[p][1], l45 = L[p][2], l67 = L[p][3];
+        const double next = nb[p];
+        if (i + PF < NB) {
+            const double2* f = reinterpret_cast<const double2*>(F + (i + PF) * FACW);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) L[p][j] = f[j];
+            nb[p] = i + PF + 8 < NB ? col[2 * (i + PF + 8)] : 0.0;
+        }
+        const double y = b0;
+        col[2 * i] = y;
+        b0 = b1 - l01.x * y;
+        b1 = b2 - l01.y * y;
+        b2 = b3 - l23.x * y;
+        b3 = b4 - l23.y * y;
+        b4 = b5 - l45.x * y;
+        b5 = b6 - l45.y * y;
+        b6 = b7 - l67.x * y;
+        b7 = next - l67.y * y;
+    }
+    double2 U[PF][3];  // (u1, u2), (u3, u4), (1/U_ii, pad)
+    double nc[PF];     // col[i - 4] for the coming rows
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int i = NB - 1 - p;
+        const double2* f = reinterpret_cast<const double2*>(F + i * FACW + 8);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) U[p][j] = f[j];
+        nc[p] = i - 4 >= 0 ? col[2 * (i - 4)] : 0.0;
+    }
+    double c0 = col[2 * (NB - 1)], c1 = col[2 * (NB - 2)], c2 = col[2 * (NB - 3)], c3 = col[2 * (NB - 4)];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int i = NB - 1 - t, p = t % PF;
+        const double2 u12 = U[p][0], u34 = U[p][1], dv = U[p][2];
+        const double next = nc[p];
+        if (t + PF < NB) {
+            const double2* f = reinterpret_cast<const double2*>(F + (i - PF) * FACW + 8);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) U[p][j] = f[j];
+            nc[p] = i - PF - 4 >= 0 ? col[2 * (i - PF - 4)] : 0.0;
+        }
+        const double x = c0 * dv.x;
+        col[2 * i] = x;
+        c0 = c1 - u12.x * x;
+        c1 = c2 - u12.y * x;
+        c2 = c3 - u34.x * x;
+        c3 = next - u34.y * x;
+    }
+}
+
+// Factors moving from global memory to LDS in two halves: load() issues all
+// 16-byte loads of this thread into registers (branch-free, clamped
+// indices), store() writes them to LDS slots of stride FS doubles and zeroes
+// rows N..NB-1.  Factor f has global index base + f * stride.
+template <int NB, int NFMAX, int NTHR>
+struct FactorStage {
+    static constexpr int MAXIT = (NFMAX * NB * FACW / 2 + NTHR - 1) / NTHR;
+    double2 tmp[MAXIT];
+    __device__ __forceinline__ void load(const double* fac, size_t base, size_t stride, int nf, int N, int t) {
+        const int per = N * FACW / 2, total = nf * per;
+        const size_t FSZ = (size_t)N * FACW;
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int e = min(t + it * NTHR, total - 1);
+            tmp[it] = reinterpret_cast<const double2*>(fac + (base + (e / per) * stride) * FSZ)[e % per];
+        }
+    }
+    __device__ __forceinline__ void store(double* sF, int FS, int nf, int N, int t) const {
+        const int per = N * FACW / 2, total = nf * per;
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int e = t + it * NTHR;
+            if (e < total) reinterpret_cast<double2*>(sF + (e / per) * FS)[e % per] = tmp[it];
+        }
+        const int zper = (NB - N) * FACW;
+        for (int e = t; e < nf * zper; e += NTHR) sF[(e / zper) * FS + N * FACW + e % zper] = 0.0;
+    }
+};
+
+constexpr int NSLOT = 8;     // modes per workgroup: up to 4 values of m, both signs of k
+constexpr int NFH = 6;       // Helmholtz factors staged at once
+
+// One workgroup = 4 waves handles |k| = kabs and GM consecutive m
+// (GM = 4, 2, 1 for mp = 1, 2, >= 3 so that the Helmholtz wavenumbers
+// mp*m-1 .. mp*m+1 of the block form one contiguous range of <= 6 values,
+// shared between neighbouring m).  Slot q = 2 j + s is mode (m0 + j, s ? -k : +k).
+// Wave w does the radial-line work of slots 2w, 2w+1; wave 0 does the
+// substitutions with one lane per real right-hand side.
+__device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, int n, int m, double kap,
+                                           const dcplx* up, const dcplx* um, const dcplx* uz,
+                                           dcplx& wp, dcplx& wm, dcplx& wz) {
+    const int pe = m & 1, po = (m + 1) & 1;
+    const dcplx duz = w1.apply(pe, uz, s0);
+    const dcplx dup = w1.apply(po, up, s0);
+    const dcplx dum = w1.apply(po, um, s0);
+    const dcplx imz = (double(m) * rinv) * ix(uz[n]);
+    wp = imz - ix(duz) - kap * up[n];
+    wm = imz + ix(duz) + kap * um[n];
+    const dcplx ap = dup + (double(1 + m) * rinv) * up[n];
+    const dcplx am = dum + (double(1 - m) * rinv) * um[n];
+    wz = 0.5 * ix(am - ap);
+}
+
+template <typename TNL, int NB>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
+    constexpr int FS = NB * FACW + 4;  // factor stride (doubles): spreads LDS banks
+    constexpr int XS = NB + 1;         // radial line stride (complex)
+    __shared__ __align__(16) double sF[NFH * FS];
+    __shared__ __align__(16) dcplx sX[NSLOT][3][XS];
+    __shared__ dcplx sY[NSLOT][XS];
+    __shared__ dcplx sA[NSLOT][4];
+    __shared__ double sGam;
+    dcplx(*sU)[3][XS] = reinterpret_cast<dcplx(*)[3][XS]>(sF);  // u^n staging (aliases factors)
 
     const Tables& t = a.t;
-    const int N = a.N, K = a.K, nk = a.nk;
-    const int mi = blockIdx.x / K, kabs = blockIdx.x % K;
-    const int m = a.mp * mi;
-    const bool zero_mode = (mi == 0 && kabs == 0);
-    const int nsig = (mi > 0 && kabs > 0) ? 2 : 1;
-    const int tid = threadIdx.x;
-    const int n = tid;
-    const size_t S = (size_t)a.M * nk * N;                 // one field
-    const int hp = abs(m + 1), hm = abs(m - 1), hz = m;    // Helmholtz |mu|
+    const int N = a.N, K = a.K, nk = a.nk, mp = a.mp;
+    const int GM = mp == 1 ? 4 : (mp == 2 ? 2 : 1);
+    const int nblk = (a.M + GM - 1) / GM;
+    const int kabs = blockIdx.x / nblk;
+    const int m0 = (blockIdx.x % nblk) * GM;
+    const int tid = threadIdx.x, n = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+    const size_t S = (size_t)a.M * nk * N;
     const size_t FSZ = (size_t)N * FACW;
+    const int mu_lo = max(mp * m0 - 1, 0);
+    const int nr = n < N ? n : N - 1;  // lanes past the last row read a valid row
+    RowW W1;  // first-derivative weights of this lane's row, both parities
+    W1.load(t.d1, N, nr);
+    const int s0r = t.s0[nr];
+    const double rinvr = t.rinv[nr];
 
-    // ---- stage the pressure factor; load u^n or R -----------------------
-    if (!zero_mode) {
-        const double* src = t.fac + ((size_t)a.MU * K + (size_t)mi * K + kabs) * FSZ;
-        for (int i = tid; i < N * FACW; i += 64) sF[0][i] = src[i];
+    const int nfp = min(GM, a.M - m0);
+    const int mu_hi = min(mp * (m0 + GM - 1) + 1, a.MU - 1);
+    const int nfh = mu_hi - mu_lo + 1;
+
+    auto slot_ok = [&](int q) {
+        const int j = q >> 1, s = q & 1, mi = m0 + j;
+        return j < GM && mi < a.M && (s == 0 || (kabs > 0 && mi > 0));
+    };
+    auto slot_k = [&](int q) { return (q & 1) ? -kabs : kabs; };
+    auto slot_off = [&](int q) {  // offset of row 0 of slot q in one field
+        return ((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * N;
+    };
+
+    // rows N..NB-1 of the line buffers stay zero (branch-free substitution)
+    for (int i = tid; i < NSLOT * (NB + 1 - N); i += 256) {
+        const int q = i / (NB + 1 - N), r = N + i % (NB + 1 - N);
+        sY[q][r] = dcplx{0.0, 0.0};
+        sX[q][0][r] = sX[q][1][r] = sX[q][2][r] = dcplx{0.0, 0.0};
     }
-    for (int s = 0; s < nsig; ++s) {
-        const int kk = s == 0 ? K - 1 + kabs : K - 1 - kabs;
-        const size_t off = ((size_t)mi * nk + kk) * N + n;
-        if (n < N) {
-            if (a.kind == OPF_SOLVE_RAW) {
-                const dcplx rr = load_c<double>(a.n0, off), rt = load_c<double>(a.n0, S + off);
-                sR[s][0][n] = rr + ix(rt);
-                sR[s][1][n] = rr - ix(rt);
-                sR[s][2][n] = load_c<double>(a.n0, 2 * S + off);
-            } else {
-                const dcplx ur = load_c<double>(a.u0, off), ut = load_c<double>(a.u0, S + off);
-                sU[s][0][n] = ur + ix(ut);
-                sU[s][1][n] = ur - ix(ut);
-                sU[s][2][n] = load_c<double>(a.u0, 2 * S + off);
-            }
+    // ---- load u^n (or R) of this wave's slots ---------------------------
+    for (int q = 2 * w; q < 2 * w + 2; ++q) {
+        if (!slot_ok(q) || n >= N) continue;
+        const size_t off = slot_off(q) + n;
+        if (a.kind == OPF_SOLVE_RAW) {
+            const dcplx rr = load_c<double>(a.n0, off), rt = load_c<double>(a.n0, S + off);
+            sX[q][0][n] = rr + ix(rt);
+            sX[q][1][n] = rr - ix(rt);
+            sX[q][2][n] = load_c<double>(a.n0, 2 * S + off);
+        } else {
+            const dcplx ur = load_c<double>(a.u0, off), ut = load_c<double>(a.u0, S + off);
+            sU[q][0][n] = ur + ix(ut);
+            sU[q][1][n] = ur - ix(ut);
+            sU[q][2][n] = load_c<double>(a.u0, 2 * S + off);
         }
     }
     __syncthreads();
 
-    // ---- right-hand side R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) ----
+    // ---- R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) --------------------
     if (a.kind != OPF_SOLVE_RAW && n < N) {
-        const int s0 = t.s0[n];
-        const double rinv = t.rinv[n];
-        for (int s = 0; s < nsig; ++s) {
-            const int k = s == 0 ? kabs : -kabs;
+        const int s0 = s0r;
+        const double rinv = rinvr;
+        RowW W2;  // second-derivative weights, needed here only
+        W2.load(t.d2, N, n);
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int m = mp * (m0 + (q >> 1)), k = slot_k(q);
             const double kap2 = a.alpha * k * a.alpha * k;
-            const int kk = k + K - 1;
-            const size_t off = ((size_t)mi * nk + kk) * N + n;
+            const size_t off = slot_off(q) + n;
             dcplx nr, nt, nz;
             if (a.kind == OPF_SOLVE_PRED) {
                 nr = load_c<TNL>(a.n0, off);
@@ -176,161 +309,156 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int mu = mus[c], p = abs(mu) & 1;
-                const dcplx* line = sU[s][c];
-                const dcplx d2 = stencil(t.d2 + (p * N + n) * W9, line, s0);
-                const dcplx d1 = stencil(t.d1 + (p * N + n) * W9, line, s0);
+                const dcplx* line = sU[q][c];
+                const dcplx d2 = W2.apply(p, line, s0);
+                const dcplx d1 = W1.apply(p, line, s0);
                 const double diag = double(mu) * double(mu) * rinv * rinv + kap2;
                 const dcplx Lu = d2 + rinv * d1 - diag * line[n];
-                sR[s][c][n] = a.inv_dt * line[n] + a.aexp * Lu + nl[c];
+                sX[q][c][n] = a.inv_dt * line[n] + a.aexp * Lu + nl[c];
             }
-            if (zero_mode) sR[s][2][n].x += a.force;
+            if (m == 0 && k == 0) sX[q][2][n].x += a.force;
         }
     }
     __syncthreads();
 
-    if (!zero_mode) {
-        // ---- pressure-Poisson right-hand side: div R, P(1) = 0 -----------
-        if (n < N) {
-            const int s0 = t.s0[n];
-            const double rinv = t.rinv[n];
-            const double* w1 = t.d1 + (((m + 1) & 1) * N + n) * W9;
-            for (int s = 0; s < nsig; ++s) {
-                const double kap = a.alpha * (s == 0 ? kabs : -kabs);
-                dcplx d = {0.0, 0.0};
-                if (n < N - 1) {
-                    const dcplx ap = stencil(w1, sR[s][0], s0) + (double(1 + m) * rinv) * sR[s][0][n];
-                    const dcplx am = stencil(w1, sR[s][1], s0) + (double(1 - m) * rinv) * sR[s][1][n];
-                    d = 0.5 * (ap + am) + kap * ix(sR[s][2][n]);
-                }
-                sP[s][n] = d;
+    // ---- pressure-Poisson right-hand side div R (P(1) = 0); stage L factors
+    {  // pressure factors L_{m,|k|}, m0 <= m < m0 + GM (the u^n staging area is free now)
+        FactorStage<NB, 4, 256> ppe;
+        ppe.load(t.fac, (size_t)a.MU * K + (size_t)m0 * K + kabs, K, nfp, N, tid);
+        ppe.store(sF, FS, nfp, N, tid);
+    }
+    if (n < N) {
+        const int s0 = s0r;
+        const double rinv = rinvr;
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int m = mp * (m0 + (q >> 1));
+            const double kap = a.alpha * slot_k(q);
+            const int po = (m + 1) & 1;
+            dcplx d = {0.0, 0.0};
+            if (n < N - 1 && !(m == 0 && kap == 0.0)) {
+                const dcplx ap = W1.apply(po, sX[q][0], s0) + (double(1 + m) * rinv) * sX[q][0][n];
+                const dcplx am = W1.apply(po, sX[q][1], s0) + (double(1 - m) * rinv) * sX[q][1][n];
+                d = 0.5 * (ap + am) + kap * ix(sX[q][2][n]);
+            }
+            sY[q][n] = d;
+        }
+    }
+    __syncthreads();
+    if (w == 0 && n < 2 * NSLOT) {
+        const int q = n >> 1;
+        if (slot_ok(q)) lds_solve<NB>(sF + (q >> 1) * FS, &sY[q][0].x + (n & 1));
+    }
+    __syncthreads();
+
+    // ---- R -= grad P; (0,0): u_r = 0, real R_theta and R_z; stage H factors
+    {  // Helmholtz factors H_{mu,|k|}, mu_lo <= mu <= mu_hi
+        FactorStage<NB, NFH, 256> helm;
+        helm.load(t.fac, (size_t)mu_lo * K + kabs, K, nfh, N, tid);
+        helm.store(sF, FS, nfh, N, tid);
+    }
+    if (n < N) {
+        const int s0 = s0r;
+        const double rinv = rinvr;
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int m = mp * (m0 + (q >> 1));
+            const double kap = a.alpha * slot_k(q);
+            if (n == N - 1) {
+                sX[q][0][n] = sX[q][1][n] = sX[q][2][n] = dcplx{0.0, 0.0};
+            } else if (m == 0 && kap == 0.0) {
+                const dcplx d = sX[q][0][n] - sX[q][1][n];  // 2 i R_theta
+                sX[q][0][n] = dcplx{0.5 * d.y, 0.0};
+                sX[q][1][n] = dcplx{0.0, 0.0};
+                sX[q][2][n] = dcplx{sX[q][2][n].x, 0.0};
+            } else {
+                const dcplx dP = W1.apply(m & 1, sY[q], s0);
+                const dcplx mP = (double(m) * rinv) * sY[q][n];
+                sX[q][0][n] = sX[q][0][n] - (dP - mP);
+                sX[q][1][n] = sX[q][1][n] - (dP + mP);
+                sX[q][2][n] = sX[q][2][n] - kap * ix(sY[q][n]);
             }
         }
-        __syncthreads();
-        if (tid < 2 * nsig) lu_solve(sF[0], &sP[tid >> 1][0].x + (tid & 1), N);
-        __syncthreads();
-        // ---- stage Helmholtz factors; R -= grad P --------------------------
-        {
-            const double* fp = t.fac + ((size_t)hp * K + kabs) * FSZ;
-            const double* fm = t.fac + ((size_t)hm * K + kabs) * FSZ;
-            const double* fz = t.fac + ((size_t)hz * K + kabs) * FSZ;
-            for (int i = tid; i < N * FACW; i += 64) {
-                sF[0][i] = fp[i];
-                sF[1][i] = fm[i];
-                sF[2][i] = fz[i];
-            }
+    }
+    __syncthreads();
+    if (w == 0 && n < 6 * NSLOT) {
+        const int q = n / 6, c = (n >> 1) % 3;
+        if (slot_ok(q)) {
+            const int m = mp * (m0 + (q >> 1));
+            const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
+            lds_solve<NB>(sF + (mu - mu_lo) * FS, &sX[q][c][0].x + (n & 1));
         }
-        if (n < N) {
-            const int s0 = t.s0[n];
-            const double rinv = t.rinv[n];
-            const double* w1 = t.d1 + ((m & 1) * N + n) * W9;
-            for (int s = 0; s < nsig; ++s) {
-                const double kap = a.alpha * (s == 0 ? kabs : -kabs);
-                if (n < N - 1) {
-                    const dcplx dP = stencil(w1, sP[s], s0);
-                    const dcplx mP = (double(m) * rinv) * sP[s][n];
-                    sR[s][0][n] = sR[s][0][n] - (dP - mP);
-                    sR[s][1][n] = sR[s][1][n] - (dP + mP);
-                    sR[s][2][n] = sR[s][2][n] - kap * ix(sP[s][n]);
-                } else {
-                    sR[s][0][n] = sR[s][1][n] = sR[s][2][n] = dcplx{0.0, 0.0};
-                }
-            }
-        }
-        __syncthreads();
-        // ---- Helmholtz solves ----------------------------------------------
-        if (tid < 6 * nsig) {
-            const int s = tid / 6, c = (tid >> 1) % 3;
-            lu_solve(sF[c], &sR[s][c][0].x + (tid & 1), N);
-        }
-        __syncthreads();
-        // ---- influence matrix: a = -A^{-1} g(u_b) --------------------------
-        if (tid < nsig) {
-            const int s = tid;
-            const int k = s == 0 ? kabs : -kabs;
+    }
+    __syncthreads();
+
+    // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
+    if (tid < NSLOT && slot_ok(tid)) {
+        const int q = tid;
+        const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
+        if (m == 0 && k == 0) {
+            double qs = 0.0;
+            for (int i = 0; i < N; ++i) qs += t.quad[i] * sX[q][2][i].x;
+            const double gamma = a.fixed_flux ? (0.25 - qs) * t.qG_inv : 0.0;
+            sGam = gamma;
+            if (a.beta_out) *a.beta_out = gamma * a.Re * 0.25;
+        } else {
             const double kap = a.alpha * k;
             const int e = N - 1, s0 = t.s0[e];
             const double rinv = t.rinv[e];
             const double* w1 = t.d1 + (((m + 1) & 1) * N + e) * W9;
-            const dcplx ap = stencil(w1, sR[s][0], s0) + (double(1 + m) * rinv) * sR[s][0][e];
-            const dcplx am = stencil(w1, sR[s][1], s0) + (double(1 - m) * rinv) * sR[s][1][e];
-            dcplx g[4] = {sR[s][0][e], sR[s][1][e], sR[s][2][e], 0.5 * (ap + am) + kap * ix(sR[s][2][e])};
+            const dcplx ap = stencil(w1, sX[q][0], s0) + (double(1 + m) * rinv) * sX[q][0][e];
+            const dcplx am = stencil(w1, sX[q][1], s0) + (double(1 - m) * rinv) * sX[q][1][e];
+            const dcplx g[4] = {sX[q][0][e], sX[q][1][e], sX[q][2][e], 0.5 * (ap + am) + kap * ix(sX[q][2][e])};
             const double* A = t.ainv + (((size_t)mi * nk + (k + K - 1)) * 16) * 2;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 dcplx acc = {0.0, 0.0};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc = acc + cm(dcplx{A[2 * (4 * i + j)], A[2 * (4 * i + j) + 1]}, g[j]);
-                sA[s][i] = dcplx{-acc.x, -acc.y};
+                for (int j = 0; j < 4; ++j)
+                    acc = acc + cm(dcplx{A[2 * (4 * i + j)], A[2 * (4 * i + j) + 1]}, g[j]);
+                sA[q][i] = dcplx{-acc.x, -acc.y};
             }
         }
-        __syncthreads();
-        if (n < N) {
-            const double* h = t.hom + ((size_t)mi * K + kabs) * NHOM * N;
-            const double h1p = h[n], h1m = h[N + n], q = h[2 * N + n];
-            const double h2 = h[3 * N + n], h3 = h[4 * N + n], h4 = h[5 * N + n], P1 = h[6 * N + n];
-            for (int s = 0; s < nsig; ++s) {
-                const double kap = a.alpha * (s == 0 ? kabs : -kabs);
-                const dcplx a1 = sA[s][0], a2 = sA[s][1], a3 = sA[s][2], a4 = sA[s][3];
-                sR[s][0][n] = sR[s][0][n] + h1p * a1 + h2 * a2;
-                sR[s][1][n] = sR[s][1][n] + h1m * a1 + h3 * a3;
-                // h1 has u_z = -i kappa q
-                sR[s][2][n] = sR[s][2][n] - (kap * q) * ix(a1) + h4 * a4;
-                sP[s][n] = sP[s][n] + P1 * a1;
+    }
+    __syncthreads();
+    if (n < N) {
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
+            if (m == 0 && k == 0) {
+                const double ut = sX[q][0][n].x;
+                const double uz = sX[q][2][n].x + sGam * t.green[n];
+                sX[q][0][n] = dcplx{0.0, ut};
+                sX[q][1][n] = dcplx{0.0, -ut};
+                sX[q][2][n] = dcplx{uz, 0.0};
+                sY[q][n] = dcplx{0.0, 0.0};
+            } else {
+                const double kap = a.alpha * k;
+                const double* h = t.hom + ((size_t)mi * K + kabs) * NHOM * N;
+                const double h1p = h[n], h1m = h[N + n], qv = h[2 * N + n];
+                const double h2 = h[3 * N + n], h3 = h[4 * N + n], h4 = h[5 * N + n], P1 = h[6 * N + n];
+                const dcplx a1 = sA[q][0], a2 = sA[q][1], a3 = sA[q][2], a4 = sA[q][3];
+                sX[q][0][n] = sX[q][0][n] + h1p * a1 + h2 * a2;
+                sX[q][1][n] = sX[q][1][n] + h1m * a1 + h3 * a3;
+                sX[q][2][n] = sX[q][2][n] - (kap * qv) * ix(a1) + h4 * a4;  // h1: u_z = -i kappa q
+                sY[q][n] = sY[q][n] + P1 * a1;
             }
-        }
-    } else {
-        // ---- mode (0,0): u_r = 0; H_1 u_t = R_t; H_0 u_z = R_z + gamma -------
-        {
-            const double* f1 = t.fac + ((size_t)1 * K) * FSZ;
-            const double* f0 = t.fac;
-            for (int i = tid; i < N * FACW; i += 64) {
-                sF[0][i] = f1[i];
-                sF[2][i] = f0[i];
-            }
-        }
-        if (n < N) {
-            const dcplx d = sR[0][0][n] - sR[0][1][n];  // 2 i R_t
-            const bool wall = n == N - 1;
-            sR[0][0][n] = dcplx{wall ? 0.0 : 0.5 * d.y, 0.0};
-            sR[0][2][n] = dcplx{wall ? 0.0 : sR[0][2][n].x, 0.0};
-        }
-        __syncthreads();
-        if (tid == 0) lu_solve(sF[0], &sR[0][0][0].x, N);
-        if (tid == 1) lu_solve(sF[2], &sR[0][2][0].x, N);
-        __syncthreads();
-        sRed[tid] = n < N ? t.quad[n] * sR[0][2][n].x : 0.0;
-        __syncthreads();
-        if (tid == 0) {
-            double q = 0.0;
-            for (int i = 0; i < N; ++i) q += sRed[i];
-            const double gamma = a.fixed_flux ? (0.25 - q) * t.qG_inv : 0.0;
-            sA[0][0] = dcplx{gamma, 0.0};
-            if (a.beta_out) *a.beta_out = gamma * a.Re * 0.25;
-        }
-        __syncthreads();
-        if (n < N) {
-            const double ut = sR[0][0][n].x;
-            const double uz = sR[0][2][n].x + sA[0][0].x * t.green[n];
-            sR[0][0][n] = dcplx{0.0, ut};
-            sR[0][1][n] = dcplx{0.0, -ut};
-            sR[0][2][n] = dcplx{uz, 0.0};
-            sP[0][n] = dcplx{0.0, 0.0};
         }
     }
     __syncthreads();
 
-    // ---- output u (r, theta, z); vorticity from the stored components -------
+    // ---- output u (r, theta, z); omega from the stored components --------
     // omega is computed from (u_r, u_theta, u_z) as stored, so it equals what
-    // the standalone vorticity kernel gives for the same state (bitwise
-    // resumable runs).
-    const bool mirror = (mi == 0 && kabs > 0);  // m = 0: -k is the conjugate of +k
+    // the standalone vorticity kernel gives for the same state.
     if (n < N) {
-        for (int s = 0; s < nsig; ++s) {
-            const int k = s == 0 ? kabs : -kabs;
-            const dcplx up = sR[s][0][n], um = sR[s][1][n], uz = sR[s][2][n];
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int mi = m0 + (q >> 1);
+            const bool mirror = (mi == 0 && kabs > 0);  // m = 0: -k is the conjugate of +k
+            const dcplx up = sX[q][0][n], um = sX[q][1][n], uz = sX[q][2][n];
             const dcplx ur = 0.5 * (up + um), ut = 0.5 * dcplx{(up - um).y, -(up - um).x};
             const dcplx uo[3] = {ur, ut, uz};
-            const size_t off = ((size_t)mi * nk + (k + K - 1)) * N + n;
+            const size_t off = slot_off(q) + n;
             const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -345,23 +473,24 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 }
             }
             if (a.p_out) {
-                const dcplx p = sP[s][n];
-                store_c<double>(a.p_out, off, p);
-                if (mirror) store_c<double>(a.p_out, offc, dcplx{p.x, -p.y});
+                const dcplx pp = sY[q][n];
+                store_c<double>(a.p_out, off, pp);
+                if (mirror) store_c<double>(a.p_out, offc, dcplx{pp.x, -pp.y});
             }
-            sU[s][0][n] = ur + ix(ut);
-            sU[s][1][n] = ur - ix(ut);
-            sU[s][2][n] = uz;
+            sX[q][0][n] = ur + ix(ut);
+            sX[q][1][n] = ur - ix(ut);
         }
     }
     __syncthreads();
     if (a.w_out && n < N) {
-        for (int s = 0; s < nsig; ++s) {
-            const int k = s == 0 ? kabs : -kabs;
+        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+            if (!slot_ok(q)) continue;
+            const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
+            const bool mirror = (mi == 0 && kabs > 0);
             dcplx wp, wm, wz;
-            vort_row(t, N, n, m, a.alpha * k, sU[s][0], sU[s][1], sU[s][2], wp, wm, wz);
+            vort_row_w(W1, rinvr, s0r, n, m, a.alpha * k, sX[q][0], sX[q][1], sX[q][2], wp, wm, wz);
             const dcplx wo[3] = {0.5 * (wp + wm), 0.5 * dcplx{(wp - wm).y, -(wp - wm).x}, wz};
-            const size_t off = ((size_t)mi * nk + (k + K - 1)) * N + n;
+            const size_t off = slot_off(q) + n;
             const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -441,11 +570,15 @@ __global__ __launch_bounds__(256) void k_energy(AuxArgs a) {
 }
 
 hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s) {
-    const dim3 grid(a.M * a.K), block(64);
-    if (precision == OPF_MIXED)
-        hipLaunchKernelGGL(k_solve<float>, grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL(k_solve<double>, grid, block, 0, s, a);
+    const int GM = a.mp == 1 ? 4 : (a.mp == 2 ? 2 : 1);
+    const dim3 grid(a.K * ((a.M + GM - 1) / GM)), block(256);
+    if (a.N <= 32) {
+        if (precision == OPF_MIXED) hipLaunchKernelGGL((k_solve<float, 32>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_solve<double, 32>), grid, block, 0, s, a);
+    } else {
+        if (precision == OPF_MIXED) hipLaunchKernelGGL((k_solve<float, 64>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_solve<double, 64>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

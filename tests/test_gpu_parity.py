@@ -18,6 +18,7 @@ CASES = {
     "tiny": dict(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01),
     "ragged": dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007),
     "odd12": dict(N=13, M=3, K=3, mp=1, alpha=1.6, Re=800.0, dt=0.02),
+    "mp3": dict(N=33, M=6, K=3, mp=3, alpha=1.1, Re=1200.0, dt=0.01),
 }
 
 
