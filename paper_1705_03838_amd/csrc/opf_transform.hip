@@ -139,15 +139,81 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, const cpx<T>* tw, int sign)
 template <typename TO, typename TI>
 __device__ __forceinline__ cpx<TO> cvt(cpx<TI> a) { return {TO(a.x), TO(a.y)}; }
 
-constexpr int NT = 256;
+// Small DFT of length R in registers, R in {2,3,4,6,8,9,12,16}.  Composite R
+// = R1 R2 (R1 in {3,4}) by one Cooley-Tukey split: R2 DFTs of length R1 on
+// stride-R2 subsets, twiddles W_R^{n2 k1}, R1 DFTs of length R2; output
+// index k1 + R1 k2.  tw holds e^{-2 pi i t / L} (R divides L).
+template <int R> struct Split1 { static constexpr int R1 = (R == 6 || R == 9) ? 3 : 4; };
+
+template <typename T, int R>
+__device__ __forceinline__ void dftn(cpx<T>* v, int sign, const cpx<T>* tw, int L) {
+    if constexpr (R <= 4) {
+        dft<T, R>(v, sign);
+    } else {
+        constexpr int R1 = Split1<R>::R1, R2 = R / R1;
+        cpx<T> y[R2][R1];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[R2 * n1 + n2];
+            dft<T, R1>(y[n2], sign);
+        }
+        const int step = L / R;
+#pragma unroll
+        for (int n2 = 1; n2 < R2; ++n2)
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) {
+                const cpx<T> w = tw[((n2 * k1) % R) * step];
+                y[n2][k1] = sign < 0 ? cmul(y[n2][k1], w) : cmulc(y[n2][k1], w);
+            }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cpx<T> z[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) z[n2] = y[n2][k1];
+            dft<T, R2>(z, sign);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = z[k2];
+        }
+    }
+}
+
+// Two-pass factorisation L = RA * RB of every supported transform length.
+// Pass A (radix RA): thread j < RB takes x[j + r RB], r < RA, and produces
+// y[j RA + r].  Pass B (radix RB): thread j < RA takes y[j + r RA], r < RB,
+// multiplies by W_L^{j r} and produces X[j + r RA].
+template <int L> struct TwoPass;
+template <> struct TwoPass<6> { static constexpr int RA = 2, RB = 3; };
+template <> struct TwoPass<9> { static constexpr int RA = 3, RB = 3; };
+template <> struct TwoPass<12> { static constexpr int RA = 3, RB = 4; };
+template <> struct TwoPass<18> { static constexpr int RA = 3, RB = 6; };
+template <> struct TwoPass<24> { static constexpr int RA = 4, RB = 6; };
+template <> struct TwoPass<36> { static constexpr int RA = 6, RB = 6; };
+template <> struct TwoPass<48> { static constexpr int RA = 6, RB = 8; };
+template <> struct TwoPass<54> { static constexpr int RA = 6, RB = 9; };
+template <> struct TwoPass<72> { static constexpr int RA = 8, RB = 9; };
+template <> struct TwoPass<96> { static constexpr int RA = 8, RB = 12; };
+template <> struct TwoPass<108> { static constexpr int RA = 9, RB = 12; };
+template <> struct TwoPass<144> { static constexpr int RA = 12, RB = 12; };
+template <> struct TwoPass<192> { static constexpr int RA = 12, RB = 16; };
+
+template <typename T>
+__device__ __forceinline__ cpx<T> twid(const cpx<T>* tw, int e, int sign) {
+    const cpx<T> w = tw[e];
+    return sign < 0 ? w : cpx<T>{w.x, -w.y};
+}
+
+constexpr int NT2 = 128;  // threads of a z-transform workgroup (TILE lines)
 
 // ---------------------------------------------------------------------------
-// k_zinv: spectral [M][nk][N] -> H[f][n][m][z], z = 0..3K-1.
+// k_zinv: spectral [M][nk][N] -> H[f][n][m][z], z = 0..3K-1 (inverse, zero
+// padded).  Workgroup: field f, azimuthal index m, TILE radial nodes.
 template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT) void k_zinv(NLArgs a) {
+__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) {
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // [TILE][L]
-    cpx<T>* tw = buf + TILE * L;                        // [L]
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
+    cpx<T>* buf = tw + L;                                // [TILE][LS]
     const int N = a.N, M = a.M, K = a.K, nk = a.nk;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
@@ -156,99 +222,185 @@ __global__ __launch_bounds__(NT) void k_zinv(NLArgs a) {
     const int n0 = tile * TILE;
     const int tid = threadIdx.x;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);
-    for (int t = tid; t < L; t += NT) tw[t] = twg[t];
+    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
     const cpx<TS>* src = reinterpret_cast<const cpx<TS>*>(a.in[f]) + (size_t)m * nk * N;
-    // bin-major fill, radial node fastest: coalesced reads of each k row
-    for (int t = tid; t < TILE * L; t += NT) {
-        const int bin = t / TILE, nn = t % TILE, n = n0 + nn;
-        cpx<T> v = {T(0), T(0)};
-        int kk = -1;
-        if (bin < K) kk = bin + K - 1;
-        else if (bin > L - K) kk = bin - L + K - 1;
-        if (kk >= 0 && n < N) v = cvt<T>(src[(size_t)kk * N + n]);
-        buf[nn * L + bin] = v;
+    // pass A: thread (j, nn), radial node fastest (coalesced rows of the spectral layout)
+    const int ja = tid / TILE, na = tid % TILE;
+    cpx<T> v[RA];
+    if (ja < RB) {
+        const int n = min(n0 + na, N - 1);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int bin = ja + r * RB;
+            int kk = -1;
+            if (bin < K) kk = bin + K - 1;
+            else if (bin > L - K) kk = bin - L + K - 1;
+            v[r] = kk >= 0 ? cvt<T>(src[(size_t)kk * N + n]) : cpx<T>{T(0), T(0)};
+        }
+    }
+    __syncthreads();  // twiddles
+    if (ja < RB) {
+        dftn<T, RA>(v, +1, tw, L);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
     }
     __syncthreads();
-    lds_fft<T, L, TILE, L, NT>(buf, tw, +1);
-    cpx<T>* dst = reinterpret_cast<cpx<T>*>(a.H) + (size_t)f * N * M * L;
-    for (int t = tid; t < TILE * L; t += NT) {
-        const int nn = t / L, z = t % L, n = n0 + nn;
-        if (n < N) dst[((size_t)n * M + m) * L + z] = buf[t];
+    // pass B: thread (nn, j), z fastest (coalesced z lines of H)
+    const int nb = tid / RA, jb = tid % RA;
+    if (nb < TILE && n0 + nb < N) {
+        cpx<T> u[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> x = buf[nb * LS + jb + r * RA];
+            u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+        }
+        dftn<T, RB>(u, +1, tw, L);
+        cpx<T>* dst = reinterpret_cast<cpx<T>*>(a.H) + ((size_t)f * N * M + (size_t)(n0 + nb) * M + m) * L;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) dst[jb + r * RA] = u[r];
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_theta: per (n, TILE axial points): inverse theta FFTs of the six fields
-// (two real fields per complex line), u x omega, forward FFTs, unpack.
+// k_theta: per (n, TILE axial points): inverse theta transforms of the six
+// fields packed two per complex line, u x omega, forward transforms of
+// (N_r + i N_t) and (N_z + i 0), unpack, scale by 1/(9KM), write G.
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_theta(NLArgs a) {
+__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) {
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // [3][TILE][L]
-    cpx<T>* tw = buf + 3 * TILE * L;                    // [L]
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
+    cpx<T>* buf = tw + L;                                // [TILE][LS]: one line set
     const int N = a.N, M = a.M, L3K = 3 * a.K;
     const int nzt = (L3K + TILE - 1) / TILE;
     const int n = blockIdx.x / nzt;
     const int z0 = (blockIdx.x % nzt) * TILE;
     const int tid = threadIdx.x;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
-    for (int t = tid; t < L; t += NT) tw[t] = twg[t];
+    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
     const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
     const size_t fstride = (size_t)N * M * L3K;
-    // pack pairs (u_r,u_t), (u_z,w_r), (w_t,w_z): Z = A + iB on m >= 0 and
-    // conj(A) + i conj(B) on bins L-m; zero elsewhere
-    for (int t = tid; t < 3 * L * TILE; t += NT) {
-        const int p = t / (L * TILE);
-        const int rem = t % (L * TILE);
-        const int j = rem / TILE, zz = rem % TILE, z = z0 + zz;
-        cpx<T> v = {T(0), T(0)};
-        int m = -1;
-        bool neg = false;
-        if (j < M) m = j;
-        else if (j > L - M) { m = L - j; neg = true; }
-        if (m >= 0 && z < L3K) {
-            const size_t off = ((size_t)n * M + m) * L3K + z;
-            const cpx<T> A = H[(2 * p) * fstride + off];
-            const cpx<T> B = H[(2 * p + 1) * fstride + off];
-            v = neg ? cpx<T>{A.x + B.y, B.x - A.y} : cpx<T>{A.x - B.y, A.y + B.x};
+    const size_t nbase = (size_t)n * M * L3K;
+    // inverse pass A: thread (j, zz), z fastest; bins j + r RB of the 3 lines
+    const int ja = tid / TILE, za = tid % TILE;
+    const int zc = min(z0 + za, L3K - 1);
+    cpx<T> v[3][RA];
+    if (ja < RB) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int bin = ja + r * RB;
+            int mm = -1;
+            bool neg = false;
+            if (bin < M) mm = bin;
+            else if (bin > L - M) { mm = L - bin; neg = true; }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                cpx<T> val = {T(0), T(0)};
+                if (mm >= 0) {
+                    const size_t off = nbase + (size_t)mm * L3K + zc;
+                    const cpx<T> A = H[(2 * p) * fstride + off];
+                    const cpx<T> B = H[(2 * p + 1) * fstride + off];
+                    // Z = A + i B on m >= 0; conj(A) + i conj(B) on bins L - m
+                    val = neg ? cpx<T>{A.x + B.y, B.x - A.y} : cpx<T>{A.x - B.y, A.y + B.x};
+                }
+                v[p][r] = val;
+            }
         }
-        buf[(p * TILE + zz) * L + j] = v;
     }
-    __syncthreads();
-    lds_fft<T, L, 3 * TILE, L, NT>(buf, tw, +1);
-    for (int t = tid; t < TILE * L; t += NT) {
-        const int zz = t / L, j = t % L;
-        const cpx<T> c0 = buf[(0 * TILE + zz) * L + j];
-        const cpx<T> c1 = buf[(1 * TILE + zz) * L + j];
-        const cpx<T> c2 = buf[(2 * TILE + zz) * L + j];
-        const T ur = c0.x, ut = c0.y, uz = c1.x, wr = c1.y, wt = c2.x, wz = c2.y;
-        buf[(0 * TILE + zz) * L + j] = {ut * wz - uz * wt, uz * wr - ur * wz};
-        buf[(1 * TILE + zz) * L + j] = {ur * wt - ut * wr, T(0)};
+    __syncthreads();  // twiddles
+    if (ja < RB) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) dftn<T, RA>(v[p], +1, tw, L);
     }
-    __syncthreads();
-    lds_fft<T, L, 2 * TILE, L, NT>(buf, tw, -1);
+    // transposes, one line at a time; pass B threads (zz, j)
+    const int zb = tid / RA, jb = tid % RA;
+    const bool actB = zb < TILE;
+    cpx<T> u[3][RB];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        if (ja < RB) {
+#pragma unroll
+            for (int r = 0; r < RA; ++r) buf[za * LS + ja * RA + r] = v[p][r];
+        }
+        __syncthreads();
+        if (actB) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const cpx<T> x = buf[zb * LS + jb + r * RA];
+                u[p][r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+            }
+        }
+        __syncthreads();
+    }
+    // inverse pass B, product, forward pass A' (radix RB on the same points)
+    if (actB) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) dftn<T, RB>(u[p], +1, tw, L);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const T ur = u[0][r].x, ut = u[0][r].y, uz = u[1][r].x, wr = u[1][r].y, wt = u[2][r].x, wz = u[2][r].y;
+            u[0][r] = {ut * wz - uz * wt, uz * wr - ur * wz};
+            u[1][r] = {ur * wt - ut * wr, T(0)};
+        }
+        dftn<T, RB>(u[0], -1, tw, L);
+        dftn<T, RB>(u[1], -1, tw, L);
+    }
+    // forward pass B' (radix RA, Ns = RB): thread (zz, j), j < RB, takes y[j + r RB]
+    const int zc2 = tid / RB, jc = tid % RB;
+    const bool actC = zc2 < TILE;
+    cpx<T> x2[2][RA];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        if (actB) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) buf[zb * LS + jb * RB + r] = u[p][r];
+        }
+        __syncthreads();
+        if (actC) {
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const cpx<T> x = buf[zc2 * LS + jc + r * RB];
+                x2[p][r] = r == 0 ? x : cmul(x, tw[jc * r]);
+            }
+        }
+        __syncthreads();
+    }
+    // forward result X[j + r RB] back to LDS line by line, unpack pairs
     cpx<T>* G = reinterpret_cast<cpx<T>*>(a.G);
     const T h = T(0.5) * T(a.scale);
-    for (int t = tid; t < M * TILE; t += NT) {
-        const int m = t / TILE, zz = t % TILE, z = z0 + zz;
-        if (z >= L3K) continue;
-        const int mc = m == 0 ? 0 : L - m;
-        const cpx<T> Z0 = buf[(0 * TILE + zz) * L + m], Y0 = buf[(0 * TILE + zz) * L + mc];
-        const cpx<T> Z1 = buf[(1 * TILE + zz) * L + m], Y1 = buf[(1 * TILE + zz) * L + mc];
-        const size_t off = ((size_t)n * M + m) * L3K + z;
-        // A = (Z + conj Y)/2, B = (Z - conj Y)/(2i)
-        G[off] = {h * (Z0.x + Y0.x), h * (Z0.y - Y0.y)};
-        G[fstride + off] = {h * (Z0.y + Y0.y), h * (Y0.x - Z0.x)};
-        G[2 * fstride + off] = {h * (Z1.x + Y1.x), h * (Z1.y - Y1.y)};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        if (actC) {
+            dftn<T, RA>(x2[p], -1, tw, L);
+#pragma unroll
+            for (int r = 0; r < RA; ++r) buf[zc2 * LS + jc + r * RB] = x2[p][r];
+        }
+        __syncthreads();
+        for (int t = tid; t < M * TILE; t += NT2) {
+            const int mm = t / TILE, zz = t % TILE, z = z0 + zz;
+            if (z >= L3K) continue;
+            const int mc = mm == 0 ? 0 : L - mm;
+            const cpx<T> Z = buf[zz * LS + mm], Y = buf[zz * LS + mc];
+            const size_t off = nbase + (size_t)mm * L3K + z;
+            if (p == 0) {  // A = (Z + conj Y)/2 -> N_r, B = (Z - conj Y)/(2i) -> N_t
+                G[off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
+                G[fstride + off] = {h * (Z.y + Y.y), h * (Y.x - Z.x)};
+            } else {
+                G[2 * fstride + off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_zfwd: G[f][n][m][z] -> spectral [M][nk][N], |k| < K kept.
+// k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
 template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT) void k_zfwd(NLArgs a) {
+__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) {
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // [TILE][L]
-    cpx<T>* tw = buf + TILE * L;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* buf = tw + L;
     const int N = a.N, M = a.M, K = a.K, nk = a.nk;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
@@ -257,21 +409,43 @@ __global__ __launch_bounds__(NT) void k_zfwd(NLArgs a) {
     const int n0 = tile * TILE;
     const int tid = threadIdx.x;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);
-    for (int t = tid; t < L; t += NT) tw[t] = twg[t];
+    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
     const cpx<T>* src = reinterpret_cast<const cpx<T>*>(a.G) + (size_t)f * N * M * L;
-    for (int t = tid; t < TILE * L; t += NT) {
-        const int nn = t / L, z = t % L, n = n0 + nn;
-        buf[t] = n < N ? src[((size_t)n * M + m) * L + z] : cpx<T>{T(0), T(0)};
+    // pass A: thread (nn, j), z fastest
+    const int na = tid / RB, ja = tid % RB;
+    cpx<T> v[RA];
+    if (na < TILE) {
+        const int n = min(n0 + na, N - 1);
+        const cpx<T>* line = src + ((size_t)n * M + m) * L;
+#pragma unroll
+        for (int r = 0; r < RA; ++r) v[r] = line[ja + r * RB];
     }
     __syncthreads();
-    lds_fft<T, L, TILE, L, NT>(buf, tw, -1);
-    cpx<TS>* dst = reinterpret_cast<cpx<TS>*>(a.out[f]) + (size_t)m * nk * N;
-    for (int t = tid; t < nk * TILE; t += NT) {
-        const int kk = t / TILE, nn = t % TILE, n = n0 + nn;
-        if (n >= N) continue;
-        const int k = kk - (K - 1);
-        const int bin = k >= 0 ? k : L + k;
-        dst[(size_t)kk * N + n] = cvt<TS>(buf[nn * L + bin]);
+    if (na < TILE) {
+        dftn<T, RA>(v, -1, tw, L);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
+    }
+    __syncthreads();
+    // pass B: thread (j, nn), radial node fastest (coalesced spectral rows)
+    const int jb = tid / TILE, nb = tid % TILE;
+    if (jb < RA && n0 + nb < N) {
+        cpx<T> u[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> x = buf[nb * LS + jb + r * RA];
+            u[r] = r == 0 ? x : cmul(x, tw[jb * r]);
+        }
+        dftn<T, RB>(u, -1, tw, L);
+        cpx<TS>* dst = reinterpret_cast<cpx<TS>*>(a.out[f]) + (size_t)m * nk * N + n0 + nb;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int bin = jb + r * RA;
+            int kk = -1;
+            if (bin < K) kk = bin + K - 1;
+            else if (bin > L - K) kk = bin - L + K - 1;
+            if (kk >= 0) dst[(size_t)kk * N] = cvt<TS>(u[r]);
+        }
     }
 }
 
@@ -293,13 +467,13 @@ static hipError_t launch_typed(const NLArgs& a, int stage, hipStream_t s) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
     const int ntile = (a.N + TILE - 1) / TILE;
     const int nzt = (L3K + TILE - 1) / TILE;
-    const size_t lz = (size_t)(TILE + 1) * L3K * sizeof(cpx<T>);
-    const size_t lt = (size_t)(3 * TILE + 1) * L3M * sizeof(cpx<T>);
+    const size_t lz = (size_t)(L3K + TILE * (L3K + 1)) * sizeof(cpx<T>);
+    const size_t lt = (size_t)(L3M + TILE * (L3M + 1)) * sizeof(cpx<T>);
     if (stage == 0) {
         switch (L3K) {
-#define OPF_CASE(V)                                                                          \
-    case V:                                                                                  \
-        hipLaunchKernelGGL((k_zinv<TS, T, V>), dim3(6 * a.M * ntile), dim3(NT), lz, s, a); \
+#define OPF_CASE(V)                                                                           \
+    case V:                                                                                   \
+        hipLaunchKernelGGL((k_zinv<TS, T, V>), dim3(6 * a.M * ntile), dim3(NT2), lz, s, a); \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -307,9 +481,9 @@ static hipError_t launch_typed(const NLArgs& a, int stage, hipStream_t s) {
         }
     } else if (stage == 1) {
         switch (L3M) {
-#define OPF_CASE(V)                                                                \
-    case V:                                                                        \
-        hipLaunchKernelGGL((k_theta<T, V>), dim3(a.N * nzt), dim3(NT), lt, s, a); \
+#define OPF_CASE(V)                                                                 \
+    case V:                                                                         \
+        hipLaunchKernelGGL((k_theta<T, V>), dim3(a.N * nzt), dim3(NT2), lt, s, a); \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -317,9 +491,9 @@ static hipError_t launch_typed(const NLArgs& a, int stage, hipStream_t s) {
         }
     } else {
         switch (L3K) {
-#define OPF_CASE(V)                                                                          \
-    case V:                                                                                  \
-        hipLaunchKernelGGL((k_zfwd<TS, T, V>), dim3(3 * a.M * ntile), dim3(NT), lz, s, a); \
+#define OPF_CASE(V)                                                                           \
+    case V:                                                                                   \
+        hipLaunchKernelGGL((k_zfwd<TS, T, V>), dim3(3 * a.M * ntile), dim3(NT2), lz, s, a); \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
