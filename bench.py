@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--workload", default="pipe64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (a known byte count "
+                         "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,6 +134,13 @@ def main():
 
     w = WORKLOADS[args.workload]
     N, M, K = w["N"], w["M"], w["K"]
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms64, prof64, diag64 = run_gpu(w, opf.OPF_FP64, args.steps, args.warmup, args.profile_steps)
 
     def roofline(prof, mixed, prec):
