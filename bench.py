@@ -104,6 +104,27 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     return (t1 - t0) / steps, prof, diag
 
 
+def run_nk(w, gmres_m=40):
+    """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
+    with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
+    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||."""
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import workload_state
+
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
+    x0 = workload_state(w, s.nodes())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = s.nk_solve(torch.from_numpy(x0), w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3)
+    torch.cuda.synchronize()
+    rep["wall_s"] = round(time.perf_counter() - t0, 3)
+    rep["steps_per_residual"] = int(round(w["T"] / w["dt"]))
+    s.close()
+    return rep
+
+
 def cpu_baseline(w, nsteps=2):
     """The oracle as it stands, on this host: one untimed step to build its
     caches, then nsteps timed steps of the same workload."""
@@ -135,6 +156,7 @@ def main():
     ap.add_argument("--workload", default="pipe64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--no-nk", action="store_true", help="skip the Newton-Krylov search")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (a known byte count "
                          "for scaling HBM counters)")
@@ -209,6 +231,10 @@ def main():
                         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, True) / ms32 / 1e9, 1),
                         "kernel_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
                         "roofline": roofline(prof32, True, "mixed")}
+    if not args.no_nk:
+        out["newton_krylov"] = {"workload": "nk: N=48, |m|<24 (mp=2), |k|<32, alpha=1.25, Re=2400, "
+                                            "dt=0.01, T=20, near-laminar seed 5000",
+                                "gmres": run_nk(WORKLOADS["nk"])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -170,6 +170,42 @@ opf_status opf_newton_residual(opf_ctx* ctx, const void* x_dev, double T,
  * predictor solve and corrector solve kernels.  Synchronises. */
 opf_status opf_profile_steps(opf_ctx* ctx, int32_t nsteps, double* ms, int32_t* launches);
 
+/* Energy inner product of two external-layout fields (host result,
+ * synchronises): sum_k sum_{m>=0} c_m sum_n w_n Re(a conj b), c_0 = 1,
+ * c_m = 2, w_n the radial quadrature weights of int_0^1 f r dr. */
+opf_status opf_vec_dot(opf_ctx* ctx, const void* a_dev, const void* b_dev, double* out_host);
+
+/* y = a x + b y over a whole external-layout field (complex128, real a, b). */
+opf_status opf_vec_axpby(opf_ctx* ctx, double a, const void* x_dev, double b, void* y_dev);
+
+/* Newton-Krylov search for a travelling wave of a fixed phase shift
+ * (Section 2: Newton solver for invariant solutions; Section 3.2: a
+ * travelling wave is an equilibrium in a frame moving with its phase
+ * speed): solves F(x) = shift(Phi_T(x), -shift) - x = 0 by Newton steps,
+ * each with restarted GMRES(gmres_m) on J dx = -F (J v by the forward
+ * difference (F(x + eps v) - F(x)) / eps, eps = fd_eps max(||x||,1)/||v||),
+ * and a backtracking line search.  x_dev (in/out, external layout) holds the
+ * guess and receives the solution; krylov_dev is caller device memory of at
+ * least opf_nk_workspace_size bytes.  The context's state is overwritten. */
+typedef struct {
+    int32_t gmres_m;     /* Krylov dimension per restart, e.g. 40             */
+    int32_t max_newton;  /* Newton iterations                                  */
+    int32_t max_jvps;    /* cap on Jacobian-vector products per Newton step    */
+    double tol;          /* stop when ||F|| / ||x|| <= tol (e.g. 1e-8)        */
+    double gmres_tol;    /* relative GMRES tolerance per Newton step           */
+    double fd_eps;       /* relative finite-difference step, e.g. 1e-7        */
+} opf_nk_opts;
+
+typedef struct {
+    int32_t newton_iterations, gmres_iterations, jvps, converged;
+    double residual;               /* final ||F|| / ||x||                    */
+    double residual_history[32];   /* ||F|| / ||x|| after each Newton step   */
+} opf_nk_report;
+
+opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, size_t* bytes);
+opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
+                        void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
+
 /* Diagnostics of the current state (host struct; synchronises). */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
 

@@ -21,6 +21,7 @@ OPF_SOLVE_PRED, OPF_SOLVE_CORR, OPF_SOLVE_RAW = 0, 1, 2
 EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create", "opf_destroy",
            "opf_get_nodes", "opf_set_state", "opf_get_state", "opf_step", "opf_nonlinear",
            "opf_vorticity", "opf_radial_solve", "opf_newton_residual", "opf_profile_steps",
+           "opf_vec_dot", "opf_vec_axpby", "opf_nk_workspace_size", "opf_nk_solve",
            "opf_diagnostics",
            "opf_status_string", "opf_last_error"]
 
@@ -38,6 +39,18 @@ class opf_params(ctypes.Structure):
 class opf_diag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("E", "I", "D", "tau_w", "flux", "beta", "E_lam", "I_lam", "D_lam", "g_norm")]
+
+
+class opf_nk_opts(ctypes.Structure):
+    _fields_ = [("gmres_m", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("max_jvps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("gmres_tol", ctypes.c_double), ("fd_eps", ctypes.c_double)]
+
+
+class opf_nk_report(ctypes.Structure):
+    _fields_ = [("newton_iterations", ctypes.c_int32), ("gmres_iterations", ctypes.c_int32),
+                ("jvps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("residual_history", ctypes.c_double * 32)]
 
 
 class OpfError(RuntimeError):
@@ -74,6 +87,10 @@ def load_library(path=LIB_PATH):
         "opf_radial_solve": ([vp, i32, vp, vp, vp], i32),
         "opf_newton_residual": ([vp, vp, dbl, dbl, vp, P(ctypes.c_double)], i32),
         "opf_profile_steps": ([vp, i32, P(ctypes.c_double), P(ctypes.c_int32)], i32),
+        "opf_vec_dot": ([vp, vp, vp, P(ctypes.c_double)], i32),
+        "opf_vec_axpby": ([vp, dbl, vp, dbl, vp], i32),
+        "opf_nk_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
+        "opf_nk_solve": ([vp, vp, dbl, dbl, P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
@@ -243,6 +260,31 @@ class Solver:
         cnt = (ctypes.c_int32 * 5)()
         self._check(self.lib.opf_profile_steps(self.ctx, int(n), ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def vec_dot(self, a, b):
+        a, b = self._dev(a, self.shape), self._dev(b, self.shape)
+        out = ctypes.c_double()
+        self._check(self.lib.opf_vec_dot(self.ctx, ctypes.c_void_p(a.data_ptr()),
+                                         ctypes.c_void_p(b.data_ptr()), ctypes.byref(out)))
+        return out.value
+
+    def nk_solve(self, x, T, shift, gmres_m=40, max_newton=20, max_jvps=400, tol=1e-8,
+                 gmres_tol=1e-3, fd_eps=1e-7):
+        """Newton-Krylov travelling-wave search; returns (solution, report dict)."""
+        x = self._dev(x, self.shape).clone()
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.opf_nk_workspace_size(self.ctx, int(gmres_m), ctypes.byref(nbytes)))
+        kry = self.torch.empty(nbytes.value, dtype=self.torch.uint8, device=self.device)
+        o = opf_nk_opts(int(gmres_m), int(max_newton), int(max_jvps), float(tol), float(gmres_tol),
+                        float(fd_eps))
+        rep = opf_nk_report()
+        self._check(self.lib.opf_nk_solve(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
+                                          ctypes.byref(o), ctypes.c_void_p(kry.data_ptr()),
+                                          ctypes.c_size_t(nbytes.value), ctypes.byref(rep)))
+        n = rep.newton_iterations
+        return x, {"newton_iterations": n, "gmres_iterations": rep.gmres_iterations,
+                   "jvps": rep.jvps, "converged": bool(rep.converged), "residual": rep.residual,
+                   "history": [rep.residual_history[i] for i in range(min(n + 1, 32))]}
 
     def diagnostics(self):
         d = opf_diag()

@@ -348,6 +348,53 @@ __global__ void k_widen(const float* __restrict__ in, double* __restrict__ out, 
     if (i < n) out[i] = double(in[i]);
 }
 
+// F = shift(u, -s) - x: F_k = u_k exp(+i alpha k s) - x_k (complex128 external layout).
+__global__ void k_shift_sub(const double* __restrict__ u, const double* __restrict__ x, double* __restrict__ F,
+                            int N, int nk, int K, size_t total, double alpha, double sft) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int kk = (int)((i / N) % nk);
+    const double ph = alpha * (kk - (K - 1)) * sft;
+    const double c = cos(ph), sn = sin(ph);
+    const double ur = u[2 * i], ui = u[2 * i + 1];
+    F[2 * i] = ur * c - ui * sn - x[2 * i];
+    F[2 * i + 1] = ur * sn + ui * c - x[2 * i + 1];
+}
+
+// Per-m partial sums of w_n Re(a conj(b)) over components, k and n (the
+// energy inner product before the m weights); fixed summation order.
+__global__ __launch_bounds__(256) void k_wdot(const double* __restrict__ a, const double* __restrict__ b,
+                                              const double* __restrict__ quad, double* __restrict__ partial,
+                                              int N, int M, int nk) {
+    __shared__ double red[256];
+    const int mi = blockIdx.x;
+    const size_t S = (size_t)M * nk * N;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nk * N; i += 256) {
+        const int n = i % N;
+        const size_t off = (size_t)mi * nk * N + i;
+        double sum = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const size_t j = 2 * (c * S + off);
+            sum += a[j] * b[j] + a[j + 1] * b[j + 1];
+        }
+        acc += quad[n] * sum;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[mi] = red[0];
+}
+
+// y = a x + b y over n doubles.
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, size_t n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
 hipError_t to_f32(const double* in, float* out, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_convert<float>, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
     return hipGetLastError();
@@ -956,9 +1003,183 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     return OPF_OK;
 }
 
+opf_status opf_vec_dot(opf_ctx* c, const void* a, const void* b, double* out) {
+    if (!c || !a || !b || !out) return OPF_E_INVALID;
+    const int M = c->p.M;
+    hipLaunchKernelGGL(k_wdot, dim3(M), dim3(256), 0, c->stream, static_cast<const double*>(a),
+                       static_cast<const double*>(b), c->t.quad, c->partial, c->p.N, M, c->nk);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> part(M);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, M * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += (m == 0 ? 1.0 : 2.0) * part[m];
+    *out = s;
+    return std::isfinite(s) ? OPF_OK : OPF_E_NUMERIC;
+}
+
+opf_status opf_vec_axpby(opf_ctx* c, double a, const void* x, double b, void* y) {
+    if (!c || !x || !y) return OPF_E_INVALID;
+    const size_t n = 2 * 3 * field_entries(c);
+    hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, c->stream, a,
+                       static_cast<const double*>(x), b, static_cast<double*>(y), n);
+    HIPCHK(c, hipGetLastError());
+    return OPF_OK;
+}
+
 opf_status opf_newton_residual(opf_ctx* c, const void* x, double T, double shift, void* F, double* norm) {
-    (void)c; (void)x; (void)T; (void)shift; (void)F; (void)norm;
-    return OPF_E_UNSUPPORTED;
+    if (!c || !x || !F) return OPF_E_INVALID;
+    if (!(T >= 0)) return OPF_E_INVALID;
+    const int nsteps = (int)std::lround(T / c->p.dt);
+    opf_status st = opf_set_state(c, x);
+    if (st != OPF_OK) return st;
+    st = opf_step(c, nsteps);
+    if (st != OPF_OK) return st;
+    const size_t total = 3 * field_entries(c);
+    hipLaunchKernelGGL(k_shift_sub, dim3((total + 255) / 256), dim3(256), 0, c->stream, c->u,
+                       static_cast<const double*>(x), static_cast<double*>(F), c->p.N, c->nk, c->p.K, total,
+                       c->p.alpha, shift);
+    HIPCHK(c, hipGetLastError());
+    if (norm) {
+        double s2 = 0.0;
+        st = opf_vec_dot(c, F, F, &s2);
+        if (st != OPF_OK) return st;
+        *norm = std::sqrt(std::max(s2, 0.0));
+    }
+    return OPF_OK;
+}
+
+opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, size_t* bytes) {
+    if (!c || !bytes || m < 1) return OPF_E_INVALID;
+    *bytes = (size_t)(m + 5) * 3 * field_entries(c) * 16;
+    return OPF_OK;
+}
+
+opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const opf_nk_opts* o,
+                        void* krylov_dev, size_t krylov_bytes, opf_nk_report* rep) {
+    if (!c || !x_dev || !o || !krylov_dev || !rep) return OPF_E_INVALID;
+    const int m = o->gmres_m;
+    size_t need = 0;
+    if (opf_nk_workspace_size(c, m, &need) != OPF_OK || krylov_bytes < need) return OPF_E_NOMEM;
+    *rep = opf_nk_report{};
+    const size_t vb = 3 * field_entries(c) * 16;  // bytes per vector
+    unsigned char* base = static_cast<unsigned char*>(krylov_dev);
+    auto vec = [&](int i) { return static_cast<void*>(base + (size_t)i * vb); };
+    void* F0 = vec(m + 1);   // F(x)
+    void* tmp = vec(m + 2);  // x + eps v, then F(x + eps v)
+    void* w = vec(m + 3);    // Arnoldi vector / J v
+    void* dx = vec(m + 4);   // Newton update
+    double* x = static_cast<double*>(x_dev);
+    auto dot = [&](const void* a, const void* b, double* out) { return opf_vec_dot(c, a, b, out); };
+    auto nrm = [&](const void* a, double* out) {
+        double s2 = 0.0;
+        const opf_status st = dot(a, a, &s2);
+        *out = std::sqrt(std::max(s2, 0.0));
+        return st;
+    };
+#define NKCHK(call)                      \
+    do {                                 \
+        const opf_status st_ = (call);   \
+        if (st_ != OPF_OK) return st_;   \
+    } while (0)
+    double fn = 0.0, xn = 0.0;
+    NKCHK(opf_newton_residual(c, x, T, shift, F0, &fn));
+    NKCHK(nrm(x, &xn));
+    rep->residual_history[0] = fn / xn;
+    rep->residual = fn / xn;
+    int it = 0;
+    for (; it < o->max_newton && rep->residual > o->tol; ++it) {
+        // J v = (F(x + eps v) - F(x)) / eps, written into w
+        auto jv = [&](const void* v, double vnorm) -> opf_status {
+            const double eps = o->fd_eps * std::max(xn, 1.0) / vnorm;
+            NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, tmp));
+            NKCHK(opf_vec_axpby(c, eps, v, 1.0, tmp));
+            HIPCHK(c, hipMemcpyAsync(w, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
+            NKCHK(opf_newton_residual(c, w, T, shift, tmp, nullptr));
+            NKCHK(opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, tmp));
+            HIPCHK(c, hipMemcpyAsync(w, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
+            rep->jvps += 1;
+            return OPF_OK;
+        };
+        // GMRES(m) for J dx = -F0, x0 = 0, one cycle per restart
+        NKCHK(opf_vec_axpby(c, 0.0, F0, 0.0, dx));
+        double bn = fn;
+        int restarts = 0;
+        while (true) {
+            // r = -F0 - J dx
+            double beta = 0.0;
+            if (restarts == 0) {
+                NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
+            } else {
+                double dxn = 0.0;
+                NKCHK(nrm(dx, &dxn));
+                NKCHK(jv(dx, dxn));
+                NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
+                NKCHK(opf_vec_axpby(c, -1.0, w, 1.0, vec(0)));
+            }
+            NKCHK(nrm(vec(0), &beta));
+            if (beta <= o->gmres_tol * bn || rep->jvps >= o->max_jvps) break;
+            NKCHK(opf_vec_axpby(c, 0.0, vec(0), 1.0 / beta, vec(0)));
+            std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+            auto Hh = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+            g[0] = beta;
+            int k = 0;
+            for (int j = 0; j < m; ++j) {
+                NKCHK(jv(vec(j), 1.0));
+                for (int i = 0; i <= j; ++i) {
+                    NKCHK(dot(w, vec(i), &Hh(i, j)));
+                    NKCHK(opf_vec_axpby(c, -Hh(i, j), vec(i), 1.0, w));
+                }
+                double hn = 0.0;
+                NKCHK(nrm(w, &hn));
+                Hh(j + 1, j) = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * Hh(i, j) + sn[i] * Hh(i + 1, j);
+                    Hh(i + 1, j) = -sn[i] * Hh(i, j) + cs[i] * Hh(i + 1, j);
+                    Hh(i, j) = t;
+                }
+                const double d = std::hypot(Hh(j, j), Hh(j + 1, j));
+                cs[j] = d == 0.0 ? 1.0 : Hh(j, j) / d;
+                sn[j] = d == 0.0 ? 0.0 : Hh(j + 1, j) / d;
+                Hh(j, j) = d;
+                Hh(j + 1, j) = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                rep->gmres_iterations += 1;
+                if (std::fabs(g[k]) <= o->gmres_tol * bn || hn == 0.0 || rep->jvps >= o->max_jvps) break;
+                NKCHK(opf_vec_axpby(c, 1.0 / hn, w, 0.0, vec(j + 1)));
+            }
+            std::vector<double> y(k, 0.0);
+            for (int i = k - 1; i >= 0; --i) {
+                double acc = g[i];
+                for (int j2 = i + 1; j2 < k; ++j2) acc -= Hh(i, j2) * y[j2];
+                y[i] = acc / Hh(i, i);
+            }
+            for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, dx));
+            ++restarts;
+            if (std::fabs(g[k]) <= o->gmres_tol * bn || rep->jvps >= o->max_jvps) break;
+        }
+        // backtracking line search on ||F||
+        double lam = 1.0, fnew = 0.0;
+        while (true) {
+            NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
+            NKCHK(opf_vec_axpby(c, lam, dx, 1.0, w));
+            NKCHK(opf_newton_residual(c, w, T, shift, tmp, &fnew));
+            if (fnew < fn || lam < 1e-3) break;
+            lam *= 0.5;
+        }
+        NKCHK(opf_vec_axpby(c, 1.0, w, 0.0, x));
+        HIPCHK(c, hipMemcpyAsync(F0, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
+        fn = fnew;
+        NKCHK(nrm(x, &xn));
+        rep->residual = fn / xn;
+        if (it + 1 < 32) rep->residual_history[it + 1] = rep->residual;
+    }
+#undef NKCHK
+    rep->newton_iterations = it;
+    rep->converged = rep->residual <= o->tol ? 1 : 0;
+    return OPF_OK;
 }
 
 }  // extern "C"

@@ -229,3 +229,38 @@ def test_mixed_precision_error(torch_cuda):
         et = abs(d["tau_w"] - dref["tau_w"]) / dref["tau_w"]
         say(f"  {target} steps: velocity {ev:.2e} energy {eE:.2e} wall shear {et:.2e}")
         assert ev < 1e-5 and eE < 1e-5 and et < 1e-5
+
+
+def test_newton_residual_and_inner_product(torch_cuda):
+    """opf_newton_residual (T/dt steps, shift, subtract) and the energy inner
+    product against the oracle's."""
+    from oracle.newton import inner, residual
+    kw = CASES["ragged"]
+    say("newton residual", kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    x = state_for(kw, s.nodes(), 1e-2, 31)
+    y = state_for(kw, s.nodes(), 1e-2, 32)
+    assert abs(s.vec_dot(torch_cuda.from_numpy(x), torch_cuda.from_numpy(y)) - inner(o, x, y)) \
+        <= 1e-13 * abs(inner(o, x, x))
+    T, sh = 0.07, 0.31
+    F, nrm = s.newton_residual(torch_cuda.from_numpy(x), T, sh)
+    Fref = residual(o, x, T, sh)
+    assert rel(F.cpu().numpy(), Fref) < 1e-10
+    assert abs(nrm - np.sqrt(inner(o, Fref, Fref))) <= 1e-9 * nrm
+
+
+def test_newton_krylov_converges_to_laminar(torch_cuda):
+    """Near laminar flow the only travelling wave is laminar flow; the GPU
+    Newton-GMRES reaches ||F||/||x|| <= 1e-10 and lands on the laminar state
+    (the oracle's Newton does the same, tests/test_oracle_newton.py)."""
+    kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
+    say("newton-krylov small", kw)
+    s = solver(torch_cuda, **kw)
+    x = make_state(12, 2, 2, 2, 1.25, s.nodes(), 1e-4, 4.0, 4.0, 6)
+    xs, rep = s.nk_solve(torch_cuda.from_numpy(x), 1.0, 0.0, tol=1e-10, gmres_tol=1e-6)
+    say("  ", rep)
+    assert rep["converged"] and rep["residual"] <= 1e-10
+    lam = laminar_state(12, 2, 2, s.nodes())
+    d = xs.cpu().numpy() - lam
+    assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(d), torch_cuda.from_numpy(d))) < 1e-8
