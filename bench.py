@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -125,6 +127,42 @@ def run_nk(w, gmres_m=40):
     return rep
 
 
+def run_ensemble(steps=500, warmup=5):
+    """96 independent trajectories in three resolution classes (32 x N=32,
+    |m|<16, |k|<24; 32 x N=48, |m|<24, |k|<32; 32 x N=64, |m|<32, |k|<48),
+    Re ~ U[1800, 2600], alpha ~ U[0.8, 1.6], perturbation energy log-uniform
+    in [1e-4, 1e-1], mixed precision, one graph launch per step; the radial
+    solve tile of each class chosen by the autotuner."""
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import ensemble_members, make_state
+
+    mem = ensemble_members()
+    kws = [dict(N=m["N"], M=m["M"], K=m["K"], mp=m["mp"], alpha=m["alpha"], Re=m["Re"], dt=m["dt"],
+                precision=opf.OPF_MIXED) for m in mem]
+    e = opf.Ensemble(kws)
+    states = [make_state(m["N"], m["M"], m["K"], m["mp"], m["alpha"], e.members[i].nodes(),
+                         m["energy_frac"], m["decay_m"], m["decay_k"], m["seed"], axis_power=1)
+              for i, m in enumerate(mem)]
+    for i, st in enumerate(states):
+        e.members[i].set_state(torch.from_numpy(st))
+    tune = e.tune(5)
+    for i, st in enumerate(states):
+        e.members[i].set_state(torch.from_numpy(st))
+    e.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.step(steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    finite = all(np.isfinite(e.members[i].diagnostics()["E"]) for i in (0, 32, 64))
+    e.close()
+    return {"members": len(mem), "steps": steps, "ms_per_step": round(dt * 1e3, 4),
+            "member_steps_per_s": round(len(mem) / dt, 1), "precision": "mixed",
+            "finite_after_run": finite, "autotune": tune}
+
+
 def cpu_baseline(w, nsteps=2):
     """The oracle as it stands, on this host: one untimed step to build its
     caches, then nsteps timed steps of the same workload."""
@@ -157,6 +195,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-nk", action="store_true", help="skip the Newton-Krylov search")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 96-member ensemble")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (a known byte count "
                          "for scaling HBM counters)")
@@ -231,6 +270,8 @@ def main():
                         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, True) / ms32 / 1e9, 1),
                         "kernel_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
                         "roofline": roofline(prof32, True, "mixed")}
+    if not args.no_ensemble:
+        out["ensemble"] = run_ensemble()
     if not args.no_nk:
         out["newton_krylov"] = {"workload": "nk: N=48, |m|<24 (mp=2), |k|<32, alpha=1.25, Re=2400, "
                                             "dt=0.01, T=20, near-laminar seed 5000",

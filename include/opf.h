@@ -209,6 +209,31 @@ opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const
 /* Diagnostics of the current state (host struct; synchronises). */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
 
+/* ---- Ensembles of independent trajectories -------------------------------
+ * Members with equal (N, M, K, mp, precision) form a class; every kernel of
+ * the step runs once per class over all its members, and one step of every
+ * class is a single captured graph launch.  Members may differ in Re, alpha,
+ * dt, c and initial state.  Workspace: caller device memory of at least
+ * opf_ensemble_workspace_size bytes (256-byte aligned); each member gets
+ * its own slice. */
+typedef struct opf_ensemble opf_ensemble;
+opf_status opf_ensemble_workspace_size(const opf_params* members, int32_t count, size_t* bytes);
+opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* dev_workspace,
+                               size_t bytes, void* hip_stream, opf_ensemble** out);
+opf_status opf_ensemble_destroy(opf_ensemble* ens);
+/* The context of member i (set/get state, diagnostics through the single-
+ * trajectory calls; do not destroy it). */
+opf_status opf_ensemble_member(opf_ensemble* ens, int32_t i, opf_ctx** out);
+/* nsteps predictor-corrector steps of every member; one graph launch per step. */
+opf_status opf_ensemble_step(opf_ensemble* ens, int32_t nsteps);
+/* Autotuner: for each class, time nsteps batched steps for every admissible
+ * radial-solve tile (1, 2 or 4 consecutive m per workgroup), keep the
+ * fastest, and write a JSON report into `report` (host, may be NULL).
+ * Advances the members' states by the timed steps (cost is data-independent:
+ * tune before setting the states to be used).  Synchronises. */
+opf_status opf_ensemble_tune(opf_ensemble* ens, int32_t nsteps, char* report, size_t report_bytes);
+const char* opf_ensemble_last_error(const opf_ensemble* ens);
+
 const char* opf_status_string(opf_status s);
 const char* opf_last_error(const opf_ctx* ctx);
 

@@ -22,7 +22,9 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_get_nodes", "opf_set_state", "opf_get_state", "opf_step", "opf_nonlinear",
            "opf_vorticity", "opf_radial_solve", "opf_newton_residual", "opf_profile_steps",
            "opf_vec_dot", "opf_vec_axpby", "opf_nk_workspace_size", "opf_nk_solve",
-           "opf_diagnostics",
+           "opf_diagnostics", "opf_ensemble_workspace_size", "opf_ensemble_create",
+           "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
+           "opf_ensemble_last_error",
            "opf_status_string", "opf_last_error"]
 
 
@@ -92,6 +94,13 @@ def load_library(path=LIB_PATH):
         "opf_nk_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
         "opf_nk_solve": ([vp, vp, dbl, dbl, P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
+        "opf_ensemble_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
+        "opf_ensemble_create": ([vp, i32, vp, ctypes.c_size_t, vp, P(vp)], i32),
+        "opf_ensemble_destroy": ([vp], i32),
+        "opf_ensemble_member": ([vp, i32, P(vp)], i32),
+        "opf_ensemble_step": ([vp, i32], i32),
+        "opf_ensemble_tune": ([vp, i32, ctypes.c_char_p, ctypes.c_size_t], i32),
+        "opf_ensemble_last_error": ([vp], ctypes.c_char_p),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -290,3 +299,75 @@ class Solver:
         d = opf_diag()
         self._check(self.lib.opf_diagnostics(self.ctx, ctypes.byref(d)))
         return {name: getattr(d, name) for name, _ in opf_diag._fields_}
+
+
+class _Member(Solver):
+    """A member context of an Ensemble (owned by the ensemble)."""
+
+    def __init__(self, ens, i, params):
+        import torch
+        self.torch = torch
+        self.lib = ens.lib
+        self.p = params
+        self.device = ens.device
+        self.stream = ens.stream
+        ctx = ctypes.c_void_p()
+        ens._check(self.lib.opf_ensemble_member(ens.ens, i, ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.N, self.M, self.K = params.N, params.M, params.K
+        self.shape = (3, self.M, 2 * self.K - 1, self.N)
+
+    def close(self):  # owned by the ensemble
+        self.ctx = None
+
+
+class Ensemble:
+    """Independent trajectories stepped together (one graph launch per step).
+    `members` is a list of keyword dicts for make_params."""
+
+    def __init__(self, members, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        n = len(members)
+        self.params = (opf_params * n)(*[make_params(**m) for m in members])
+        nbytes = ctypes.c_size_t()
+        self.ens = None
+        self._check(self.lib.opf_ensemble_workspace_size(self.params, n, ctypes.byref(nbytes)))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ens = ctypes.c_void_p()
+        self._check(self.lib.opf_ensemble_create(self.params, n, ctypes.c_void_p(ptr), nbytes.value,
+                                                 ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(ens)))
+        self.ens = ens
+        self.members = [_Member(self, i, self.params[i]) for i in range(n)]
+
+    def _check(self, st):
+        if st != OPF_OK:
+            msg = self.lib.opf_status_string(st).decode()
+            if getattr(self, "ens", None):
+                msg += ": " + self.lib.opf_ensemble_last_error(self.ens).decode()
+            raise OpfError(st, msg)
+
+    def step(self, n=1):
+        self._check(self.lib.opf_ensemble_step(self.ens, int(n)))
+
+    def tune(self, nsteps=5):
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self.lib.opf_ensemble_tune(self.ens, int(nsteps), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "ens", None):
+            self.lib.opf_ensemble_destroy(self.ens)
+            self.ens = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -20,7 +20,7 @@ struct opf_ctx {
     opf_params p{};
     std::vector<double> r, rinv, quad, d1, d2, green;  // host copies
     std::vector<int> s0;
-    int nk = 0, MU = 0, nfac = 0;
+    int nk = 0, MU = 0, nfac = 0, gm = 1;
     double qG_inv = 0.0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -435,6 +435,7 @@ SolveArgs solve_args(const opf_ctx* c, int kind) {
     a.nk = c->nk;
     a.mp = c->p.mp;
     a.MU = c->MU;
+    a.gm = c->gm;
     a.kind = kind;
     a.fixed_flux = c->p.fixed_flux;
     a.alpha = c->p.alpha;
@@ -584,6 +585,7 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->nk = nk;
     c->MU = p->mp * (M - 1) + 2;
     c->nfac = c->MU * K + M * K;
+    c->gm = default_gm(p->mp);
 
     build_grid(c, p->r_nodes);
 
@@ -1181,5 +1183,302 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
     rep->converged = rep->residual <= o->tol ? 1 : 0;
     return OPF_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles: members of equal (N, M, K, mp, precision) form a class; each
+// kernel of the step runs once per class over all its members (grid.y =
+// member, argument records in device memory), and the whole step of every
+// class is one captured graph.
+struct EnsClass {
+    int N = 0, M = 0, K = 0, mp = 0, precision = 0, gm = 1;
+    std::vector<int> idx;                   // member indices
+    NLArgs* nl[2] = {nullptr, nullptr};     // device argument records, NL(u^n), NL(u^p)
+    SolveArgs* sv[2] = {nullptr, nullptr};  // predictor, corrector
+    double tuned_us = 0.0;                  // per-step time of the class at its tile choice
+};
+
+struct opf_ensemble {
+    std::vector<opf_ctx*> members;
+    std::vector<EnsClass> classes;
+    hipStream_t stream = nullptr, cap = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::string err;
+};
+
+namespace {
+
+size_t ens_layout(const opf_params* mem, int count, std::vector<size_t>* offs, std::vector<size_t>* sizes) {
+    size_t o = 0;
+    for (int i = 0; i < count; ++i) {
+        size_t b = 0;
+        if (opf_workspace_size(&mem[i], &b) != OPF_OK) return 0;
+        if (offs) offs->push_back(o);
+        if (sizes) sizes->push_back(b);
+        o = align_up(o + b);
+    }
+    // argument records: at most 2 NL + 2 solve records per member
+    o = align_up(o + (size_t)count * (2 * sizeof(NLArgs) + 2 * sizeof(SolveArgs)) + 1024);
+    return o;
+}
+
+// Upload the argument records of class k with the current tile choice.
+opf_status ens_upload(opf_ensemble* e, EnsClass& k, hipStream_t s) {
+    std::vector<NLArgs> nl0, nl1;
+    std::vector<SolveArgs> sp, sc;
+    for (int i : k.idx) {
+        opf_ctx* c = e->members[i];
+        c->gm = k.gm;
+        const bool mixed = c->p.precision == OPF_MIXED;
+        const void* uin = mixed ? (const void*)c->u32 : (const void*)c->u;
+        const void* upin = mixed ? (const void*)c->up32 : (const void*)c->up;
+        nl0.push_back(nl_args(c, uin, c->w, c->Nn));
+        nl1.push_back(nl_args(c, upin, c->w, c->Np));
+        SolveArgs a = solve_args(c, OPF_SOLVE_PRED);
+        a.u0 = c->u;
+        a.n0 = c->Nn;
+        a.u_out = mixed ? nullptr : c->up;
+        a.u_out32 = mixed ? c->up32 : nullptr;
+        a.w_out = c->w;
+        sp.push_back(a);
+        SolveArgs b = solve_args(c, OPF_SOLVE_CORR);
+        b.u0 = c->u;
+        b.n0 = c->Nn;
+        b.n1 = c->Np;
+        b.u_out = c->u;
+        b.u_out32 = mixed ? c->u32 : nullptr;
+        b.w_out = c->w;
+        sc.push_back(b);
+    }
+    const size_t n = k.idx.size();
+    hipError_t he = hipMemcpyAsync(k.nl[0], nl0.data(), n * sizeof(NLArgs), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(k.nl[1], nl1.data(), n * sizeof(NLArgs), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(k.sv[0], sp.data(), n * sizeof(SolveArgs), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(k.sv[1], sc.data(), n * sizeof(SolveArgs), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);  // host vectors go out of scope
+    if (he != hipSuccess) {
+        e->err = std::string("ensemble upload: ") + hipGetErrorString(he);
+        return OPF_E_HIP;
+    }
+    return OPF_OK;
+}
+
+// One predictor-corrector step of class k (all members, batched launches).
+hipError_t ens_enqueue_class(opf_ensemble* e, const EnsClass& k, hipStream_t s) {
+    opf_ctx* c0 = e->members[k.idx[0]];
+    const int nm = (int)k.idx.size();
+    NLArgs proto = nl_args(c0, c0->u, c0->w, c0->Nn);
+    SolveArgs sproto = solve_args(c0, OPF_SOLVE_PRED);
+    sproto.gm = k.gm;
+    hipError_t he = hipSuccess;
+    for (int half = 0; half < 2 && he == hipSuccess; ++half) {
+        if (c0->p.nonlinear)
+            for (int stage = 0; stage < 3 && he == hipSuccess; ++stage)
+                he = launch_nonlinear_batch(proto, k.nl[half], nm, k.precision, stage, s);
+        if (he == hipSuccess) he = launch_solve_batch(sproto, k.sv[half], nm, k.precision, s);
+    }
+    return he;
+}
+
+}  // namespace
+
+extern "C" {
+
+opf_status opf_ensemble_workspace_size(const opf_params* members, int32_t count, size_t* bytes) {
+    if (!members || count < 1 || !bytes) return OPF_E_INVALID;
+    for (int i = 0; i < count; ++i) {
+        const opf_status st = validate(&members[i], nullptr);
+        if (st != OPF_OK) return st;
+    }
+    *bytes = ens_layout(members, count, nullptr, nullptr);
+    return *bytes ? OPF_OK : OPF_E_INVALID;
+}
+
+opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* ws, size_t bytes,
+                               void* hip_stream, opf_ensemble** out) {
+    if (!members || count < 1 || !ws || !out) return OPF_E_INVALID;
+    *out = nullptr;
+    std::vector<size_t> offs, sizes;
+    const size_t need = ens_layout(members, count, &offs, &sizes);
+    if (!need) return OPF_E_INVALID;
+    if (bytes < need) return OPF_E_NOMEM;
+    if (reinterpret_cast<uintptr_t>(ws) % ALIGN != 0) return OPF_E_INVALID;
+    opf_ensemble* e = new (std::nothrow) opf_ensemble();
+    if (!e) return OPF_E_NOMEM;
+    e->stream = static_cast<hipStream_t>(hip_stream);
+    unsigned char* base = static_cast<unsigned char*>(ws);
+    for (int i = 0; i < count; ++i) {
+        opf_ctx* c = nullptr;
+        const opf_status st = opf_create(&members[i], base + offs[i], sizes[i], hip_stream, &c);
+        if (st != OPF_OK) {
+            for (opf_ctx* m : e->members) opf_destroy(m);
+            delete e;
+            return st;
+        }
+        e->members.push_back(c);
+    }
+    for (int i = 0; i < count; ++i) {
+        const opf_params& p = e->members[i]->p;
+        EnsClass* k = nullptr;
+        for (EnsClass& q : e->classes)
+            if (q.N == p.N && q.M == p.M && q.K == p.K && q.mp == p.mp && q.precision == p.precision &&
+                e->members[q.idx[0]]->p.nonlinear == p.nonlinear)
+                k = &q;
+        if (!k) {
+            e->classes.emplace_back();
+            k = &e->classes.back();
+            k->N = p.N;
+            k->M = p.M;
+            k->K = p.K;
+            k->mp = p.mp;
+            k->precision = p.precision;
+            k->gm = default_gm(p.mp);
+        }
+        k->idx.push_back(i);
+    }
+    unsigned char* args = base + ens_layout(members, count, nullptr, nullptr) -
+                          align_up((size_t)count * (2 * sizeof(NLArgs) + 2 * sizeof(SolveArgs)) + 1024);
+    size_t o = 0;
+    for (EnsClass& k : e->classes) {
+        const size_t n = k.idx.size();
+        for (int h = 0; h < 2; ++h) {
+            k.nl[h] = reinterpret_cast<NLArgs*>(args + o);
+            o += n * sizeof(NLArgs);
+        }
+        o = (o + 63) / 64 * 64;
+        for (int h = 0; h < 2; ++h) {
+            k.sv[h] = reinterpret_cast<SolveArgs*>(args + o);
+            o += n * sizeof(SolveArgs);
+        }
+        o = (o + 63) / 64 * 64;
+        const opf_status st = ens_upload(e, k, e->stream);
+        if (st != OPF_OK) {
+            opf_ensemble_destroy(e);
+            return st;
+        }
+    }
+    *out = e;
+    return OPF_OK;
+}
+
+opf_status opf_ensemble_destroy(opf_ensemble* e) {
+    if (!e) return OPF_E_INVALID;
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    if (e->cap) (void)hipStreamDestroy(e->cap);
+    for (opf_ctx* c : e->members) opf_destroy(c);
+    delete e;
+    return OPF_OK;
+}
+
+opf_status opf_ensemble_member(opf_ensemble* e, int32_t i, opf_ctx** out) {
+    if (!e || !out || i < 0 || i >= (int)e->members.size()) return OPF_E_INVALID;
+    *out = e->members[i];
+    return OPF_OK;
+}
+
+opf_status opf_ensemble_step(opf_ensemble* e, int32_t nsteps) {
+    if (!e || nsteps < 0) return OPF_E_INVALID;
+    for (opf_ctx* c : e->members)
+        if (!c->have_state) return OPF_E_STATE;
+    if (!e->graph) {
+        auto fail = [&](const char* what, hipError_t he) {
+            e->err = std::string(what) + ": " + hipGetErrorString(he);
+            return OPF_E_HIP;
+        };
+        hipError_t he = hipSuccess;
+        if (!e->cap) he = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
+        if (he != hipSuccess) return fail("stream", he);
+        hipGraph_t g = nullptr;
+        he = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
+        if (he != hipSuccess) return fail("capture", he);
+        hipError_t ke = hipSuccess;
+        for (const EnsClass& k : e->classes)
+            if (ke == hipSuccess) ke = ens_enqueue_class(e, k, e->cap);
+        he = hipStreamEndCapture(e->cap, &g);
+        if (ke != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail("launch", ke);
+        }
+        if (he != hipSuccess) return fail("capture", he);
+        he = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (he != hipSuccess) {
+            e->graph = nullptr;
+            return fail("instantiate", he);
+        }
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        const hipError_t he = hipGraphLaunch(e->graph, e->stream);
+        if (he != hipSuccess) {
+            e->err = std::string("graph launch: ") + hipGetErrorString(he);
+            return OPF_E_HIP;
+        }
+    }
+    return OPF_OK;
+}
+
+opf_status opf_ensemble_tune(opf_ensemble* e, int32_t nsteps, char* report, size_t report_bytes) {
+    if (!e || nsteps < 1) return OPF_E_INVALID;
+    std::string js = "{\"classes\": [";
+    for (size_t ci = 0; ci < e->classes.size(); ++ci) {
+        EnsClass& k = e->classes[ci];
+        double best = 1e300;
+        int best_gm = k.gm;
+        std::string cand;
+        for (int gm = 1; gm <= 4; gm *= 2) {
+            if (!gm_ok(gm, k.mp) || gm > k.M) continue;
+            k.gm = gm;
+            opf_status st = ens_upload(e, k, e->stream);
+            if (st != OPF_OK) return st;
+            hipEvent_t a, b;
+            HIPCHK(e->members[k.idx[0]], hipEventCreate(&a));
+            HIPCHK(e->members[k.idx[0]], hipEventCreate(&b));
+            hipError_t he = ens_enqueue_class(e, k, e->stream);  // warm-up
+            if (he == hipSuccess) he = hipEventRecord(a, e->stream);
+            for (int t = 0; t < nsteps && he == hipSuccess; ++t) he = ens_enqueue_class(e, k, e->stream);
+            if (he == hipSuccess) he = hipEventRecord(b, e->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, a, b);
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (he != hipSuccess) {
+                e->err = std::string("tune: ") + hipGetErrorString(he);
+                return OPF_E_HIP;
+            }
+            const double us = 1e3 * ms / nsteps;
+            char buf[64];
+            std::snprintf(buf, sizeof buf, "%s{\"gm\": %d, \"us_per_step\": %.3f}", cand.empty() ? "" : ", ", gm, us);
+            cand += buf;
+            if (us < best) {
+                best = us;
+                best_gm = gm;
+            }
+        }
+        k.gm = best_gm;
+        k.tuned_us = best;
+        const opf_status st = ens_upload(e, k, e->stream);
+        if (st != OPF_OK) return st;
+        char head[256];
+        std::snprintf(head, sizeof head,
+                      "%s{\"N\": %d, \"M\": %d, \"K\": %d, \"mp\": %d, \"precision\": %d, \"members\": %d, "
+                      "\"gm\": %d, \"us_per_step\": %.3f, \"candidates\": [",
+                      ci ? ", " : "", k.N, k.M, k.K, k.mp, k.precision, (int)k.idx.size(), k.gm, best);
+        js += head + cand + "]}";
+    }
+    js += "]}";
+    if (e->graph) {  // recapture with the chosen tiles
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    if (report && report_bytes) {
+        std::strncpy(report, js.c_str(), report_bytes - 1);
+        report[report_bytes - 1] = 0;
+    }
+    return OPF_OK;
+}
+
+const char* opf_ensemble_last_error(const opf_ensemble* e) { return e ? e->err.c_str() : "null ensemble"; }
 
 }  // extern "C"

@@ -56,6 +56,7 @@ struct NLArgs {
 // Arguments of one substep solve (one kernel).
 struct SolveArgs {
     int N, M, K, nk, mp, MU;
+    int gm;             // consecutive m per workgroup (tile shape), see gm_ok
     int kind;           // OPF_SOLVE_PRED / CORR / RAW
     int fixed_flux;
     double alpha, Re, c, inv_dt, aexp, force;
@@ -88,6 +89,15 @@ hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s);
 hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s);
 bool nonlinear_supported(int M, int K);
 hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s);
+// Batched forms: one launch for `members` argument records in device memory
+// (grid.y = member); `proto` gives the shared sizes.
+hipError_t launch_nonlinear_batch(const NLArgs& proto, const NLArgs* dev_args, int members, int precision,
+                                  int stage, hipStream_t s);
+hipError_t launch_solve_batch(const SolveArgs& proto, const SolveArgs* dev_args, int members, int precision,
+                              hipStream_t s);
+int default_gm(int mp);
+bool gm_ok(int gm, int mp);
+constexpr int NFH = 6;  // Helmholtz factors a solve workgroup stages at once
 hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s);
 hipError_t launch_energy(const AuxArgs& a, hipStream_t s);
 

@@ -194,7 +194,6 @@ struct FactorStage {
 };
 
 constexpr int NSLOT = 8;     // modes per workgroup: up to 4 values of m, both signs of k
-constexpr int NFH = 6;       // Helmholtz factors staged at once
 
 // One workgroup = 4 waves handles |k| = kabs and GM consecutive m
 // (GM = 4, 2, 1 for mp = 1, 2, >= 3 so that the Helmholtz wavenumbers
@@ -218,7 +217,7 @@ __device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, 
 }
 
 template <typename TNL, int NB>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
+__device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     constexpr int FS = NB * FACW + 4;  // factor stride (doubles): spreads LDS banks
     constexpr int XS = NB + 1;         // radial line stride (complex)
     __shared__ __align__(16) double sF[NFH * FS];
@@ -230,7 +229,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
 
     const Tables& t = a.t;
     const int N = a.N, K = a.K, nk = a.nk, mp = a.mp;
-    const int GM = mp == 1 ? 4 : (mp == 2 ? 2 : 1);
+    const int GM = a.gm;
     const int nblk = (a.M + GM - 1) / GM;
     const int kabs = blockIdx.x / nblk;
     const int m0 = (blockIdx.x % nblk) * GM;
@@ -501,6 +500,14 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
     }
 }
 
+template <typename TNL, int NB>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a) { k_solve_body<TNL, NB>(a); }
+template <typename TNL, int NB>
+__global__ __launch_bounds__(256) void k_solve_b(const SolveArgs* __restrict__ aa) {
+    const SolveArgs a = aa[blockIdx.y];
+    k_solve_body<TNL, NB>(a);
+}
+
 // Standalone vorticity of an external-layout state.  With a.mirror set
 // (states, which are real fields) the m = 0, k < 0 modes are written as the
 // conjugates of k > 0, as the solve kernel does; otherwise every mode is
@@ -569,17 +576,30 @@ __global__ __launch_bounds__(256) void k_energy(AuxArgs a) {
     }
 }
 
-hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s) {
-    const int GM = a.mp == 1 ? 4 : (a.mp == 2 ? 2 : 1);
-    const dim3 grid(a.K * ((a.M + GM - 1) / GM)), block(256);
+int default_gm(int mp) { return mp == 1 ? 4 : (mp <= 3 ? 2 : 1); }
+
+bool gm_ok(int gm, int mp) { return gm >= 1 && gm <= 4 && mp * (gm - 1) + 3 <= NFH; }
+
+hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int members, int precision,
+                              hipStream_t s) {
+    const bool b = batch != nullptr;
+    const dim3 grid(a.K * ((a.M + a.gm - 1) / a.gm), b ? members : 1), block(256);
+#define OPF_SOLVE_LAUNCH(TNL, NB)                                                   \
+    if (b) hipLaunchKernelGGL((k_solve_b<TNL, NB>), grid, block, 0, s, batch); \
+    else hipLaunchKernelGGL((k_solve<TNL, NB>), grid, block, 0, s, a);
     if (a.N <= 32) {
-        if (precision == OPF_MIXED) hipLaunchKernelGGL((k_solve<float, 32>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_solve<double, 32>), grid, block, 0, s, a);
+        if (precision == OPF_MIXED) { OPF_SOLVE_LAUNCH(float, 32) }
+        else { OPF_SOLVE_LAUNCH(double, 32) }
     } else {
-        if (precision == OPF_MIXED) hipLaunchKernelGGL((k_solve<float, 64>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_solve<double, 64>), grid, block, 0, s, a);
+        if (precision == OPF_MIXED) { OPF_SOLVE_LAUNCH(float, 64) }
+        else { OPF_SOLVE_LAUNCH(double, 64) }
     }
+#undef OPF_SOLVE_LAUNCH
     return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s) {
+    return launch_solve_batch(a, nullptr, 1, precision, s);
 }
 
 hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s) {

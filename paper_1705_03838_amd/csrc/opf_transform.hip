@@ -209,7 +209,7 @@ constexpr int NT2 = 128;  // threads of a z-transform workgroup (TILE lines)
 // k_zinv: spectral [M][nk][N] -> H[f][n][m][z], z = 0..3K-1 (inverse, zero
 // padded).  Workgroup: field f, azimuthal index m, TILE radial nodes.
 template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) {
+__device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
@@ -261,12 +261,20 @@ __global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) {
     }
 }
 
+template <typename TS, typename T, int L>
+__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L>(a); }
+template <typename TS, typename T, int L>
+__global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
+    const NLArgs a = aa[blockIdx.y];
+    k_zinv_body<TS, T, L>(a);
+}
+
 // ---------------------------------------------------------------------------
 // k_theta: per (n, TILE axial points): inverse theta transforms of the six
 // fields packed two per complex line, u x omega, forward transforms of
 // (N_r + i N_t) and (N_z + i 0), unpack, scale by 1/(9KM), write G.
 template <typename T, int L>
-__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) {
+__device__ __forceinline__ void k_theta_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
@@ -393,10 +401,18 @@ __global__ __launch_bounds__(NT2) void k_theta(NLArgs a) {
     }
 }
 
+template <typename T, int L>
+__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) { k_theta_body<T, L>(a); }
+template <typename T, int L>
+__global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) {
+    const NLArgs a = aa[blockIdx.y];
+    k_theta_body<T, L>(a);
+}
+
 // ---------------------------------------------------------------------------
 // k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
 template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) {
+__device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -449,6 +465,14 @@ __global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) {
     }
 }
 
+template <typename TS, typename T, int L>
+__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L>(a); }
+template <typename TS, typename T, int L>
+__global__ __launch_bounds__(NT2) void k_zfwd_b(const NLArgs* __restrict__ aa) {
+    const NLArgs a = aa[blockIdx.y];
+    k_zfwd_body<TS, T, L>(a);
+}
+
 // ---------------------------------------------------------------------------
 // Host dispatch over the supported transform lengths 3K, 3M.
 #define OPF_FOR_LENGTHS(X) X(6) X(9) X(12) X(18) X(24) X(36) X(48) X(54) X(72) X(96) X(108) X(144) X(192)
@@ -463,37 +487,44 @@ static bool length_ok(int L) {
 bool nonlinear_supported(int M, int K) { return length_ok(3 * M) && length_ok(3 * K); }
 
 template <typename TS, typename T>
-static hipError_t launch_typed(const NLArgs& a, int stage, hipStream_t s) {
+static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
     const int ntile = (a.N + TILE - 1) / TILE;
     const int nzt = (L3K + TILE - 1) / TILE;
     const size_t lz = (size_t)(L3K + TILE * (L3K + 1)) * sizeof(cpx<T>);
     const size_t lt = (size_t)(L3M + TILE * (L3M + 1)) * sizeof(cpx<T>);
+    const bool b = batch != nullptr;
     if (stage == 0) {
+        const dim3 g(6 * a.M * ntile, b ? members : 1);
         switch (L3K) {
-#define OPF_CASE(V)                                                                           \
-    case V:                                                                                   \
-        hipLaunchKernelGGL((k_zinv<TS, T, V>), dim3(6 * a.M * ntile), dim3(NT2), lz, s, a); \
+#define OPF_CASE(V)                                                                  \
+    case V:                                                                          \
+        if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, V>), g, dim3(NT2), lz, s, batch); \
+        else hipLaunchKernelGGL((k_zinv<TS, T, V>), g, dim3(NT2), lz, s, a);         \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
             default: return hipErrorInvalidValue;
         }
     } else if (stage == 1) {
+        const dim3 g(a.N * nzt, b ? members : 1);
         switch (L3M) {
-#define OPF_CASE(V)                                                                 \
-    case V:                                                                         \
-        hipLaunchKernelGGL((k_theta<T, V>), dim3(a.N * nzt), dim3(NT2), lt, s, a); \
+#define OPF_CASE(V)                                                              \
+    case V:                                                                      \
+        if (b) hipLaunchKernelGGL((k_theta_b<T, V>), g, dim3(NT2), lt, s, batch); \
+        else hipLaunchKernelGGL((k_theta<T, V>), g, dim3(NT2), lt, s, a);         \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
             default: return hipErrorInvalidValue;
         }
     } else {
+        const dim3 g(3 * a.M * ntile, b ? members : 1);
         switch (L3K) {
-#define OPF_CASE(V)                                                                           \
-    case V:                                                                                   \
-        hipLaunchKernelGGL((k_zfwd<TS, T, V>), dim3(3 * a.M * ntile), dim3(NT2), lz, s, a); \
+#define OPF_CASE(V)                                                                  \
+    case V:                                                                          \
+        if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, V>), g, dim3(NT2), lz, s, batch); \
+        else hipLaunchKernelGGL((k_zfwd<TS, T, V>), g, dim3(NT2), lz, s, a);         \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -503,9 +534,15 @@ static hipError_t launch_typed(const NLArgs& a, int stage, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_nonlinear_batch(const NLArgs& proto, const NLArgs* dev_args, int members, int precision,
+                                  int stage, hipStream_t s) {
+    if (precision == OPF_MIXED) return launch_typed<float, float>(proto, dev_args, members, stage, s);
+    return launch_typed<double, double>(proto, dev_args, members, stage, s);
+}
+
 hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s) {
-    if (precision == OPF_MIXED) return launch_typed<float, float>(a, stage, s);
-    return launch_typed<double, double>(a, stage, s);
+    if (precision == OPF_MIXED) return launch_typed<float, float>(a, nullptr, 1, stage, s);
+    return launch_typed<double, double>(a, nullptr, 1, stage, s);
 }
 
 hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s) {

@@ -264,3 +264,33 @@ def test_newton_krylov_converges_to_laminar(torch_cuda):
     lam = laminar_state(12, 2, 2, s.nodes())
     d = xs.cpu().numpy() - lam
     assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(d), torch_cuda.from_numpy(d))) < 1e-8
+
+
+def test_ensemble_members_equal_single_runs(torch_cuda):
+    """Batched ensemble (two classes, uneven Re / alpha / dt, FP64 and mixed)
+    against the same members stepped one by one: bitwise equal."""
+    import paper_1705_03838_amd as opf
+    mem = [dict(N=24, M=8, K=8, alpha=1.1, Re=1900.0, dt=0.01),
+           dict(N=24, M=8, K=8, alpha=1.5, Re=2500.0, dt=0.008),
+           dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007, precision=opf.OPF_MIXED),
+           dict(N=24, M=8, K=8, alpha=0.8, Re=2100.0, dt=0.01)]
+    say("ensemble vs single", len(mem))
+    e = opf.Ensemble(mem)
+    rep = e.tune(2)
+    say("  tune", rep)
+    assert len(rep["classes"]) == 2
+    states = []
+    for i, kw in enumerate(mem):
+        full = dict(mp=1, **kw) if "mp" not in kw else dict(kw)
+        st = make_state(full["N"], full["M"], full["K"], full["mp"], full["alpha"],
+                        e.members[i].nodes(), 1e-2, 4.0, 4.0, 40 + i)
+        states.append(st)
+        e.members[i].set_state(torch_cuda.from_numpy(st))
+    e.step(4)
+    for i, kw in enumerate(mem):
+        s = solver(torch_cuda, **kw)
+        s.set_state(torch_cuda.from_numpy(states[i]))
+        s.step(4)
+        a = e.members[i].get_state().cpu().numpy()
+        b = s.get_state().cpu().numpy()
+        assert np.array_equal(a, b), i
