@@ -178,6 +178,9 @@ opf_status opf_vec_dot(opf_ctx* ctx, const void* a_dev, const void* b_dev, doubl
 /* y = a x + b y over a whole external-layout field (complex128, real a, b). */
 opf_status opf_vec_axpby(opf_ctx* ctx, double a, const void* x_dev, double b, void* y_dev);
 
+/* Learned preconditioner network (declared below). */
+typedef struct opf_mlp opf_mlp;
+
 /* Newton-Krylov search for a travelling wave of a fixed phase shift
  * (Section 2: Newton solver for invariant solutions; Section 3.2: a
  * travelling wave is an equilibrium in a frame moving with its phase
@@ -186,7 +189,14 @@ opf_status opf_vec_axpby(opf_ctx* ctx, double a, const void* x_dev, double b, vo
  * difference (F(x + eps v) - F(x)) / eps, eps = fd_eps max(||x||,1)/||v||),
  * and a backtracking line search.  x_dev (in/out, external layout) holds the
  * guess and receives the solution; krylov_dev is caller device memory of at
- * least opf_nk_workspace_size bytes.  The context's state is overwritten. */
+ * least opf_nk_workspace_size bytes.  The context's state is overwritten.
+ * precond: NULL for plain GMRES; otherwise flexible GMRES with right
+ * preconditioning (Saad 1993), z_j = P(v_j) with P = opf_precondition of
+ * that network, which must have been created for this context's grid.
+ * record_dev: NULL, or device memory for record_capacity pairs of
+ * external-layout vectors; each product J z the solver forms is stored as
+ * pair i = (z at vector 2i, J z at vector 2i+1) until the capacity is
+ * reached (training data for the network). */
 typedef struct {
     int32_t gmres_m;     /* Krylov dimension per restart, e.g. 40             */
     int32_t max_newton;  /* Newton iterations                                  */
@@ -194,17 +204,98 @@ typedef struct {
     double tol;          /* stop when ||F|| / ||x|| <= tol (e.g. 1e-8)        */
     double gmres_tol;    /* relative GMRES tolerance per Newton step           */
     double fd_eps;       /* relative finite-difference step, e.g. 1e-7        */
+    opf_mlp* precond;
+    void* record_dev;
+    int32_t record_capacity;
 } opf_nk_opts;
 
 typedef struct {
     int32_t newton_iterations, gmres_iterations, jvps, converged;
     double residual;               /* final ||F|| / ||x||                    */
     double residual_history[32];   /* ||F|| / ||x|| after each Newton step   */
+    int32_t recorded;              /* pairs written to record_dev            */
+    int32_t precond_applies;       /* applications of the preconditioner     */
 } opf_nk_report;
 
-opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, size_t* bytes);
+/* Device bytes for opf_nk_solve: (gmres_m + 5) vectors, plus gmres_m more
+ * (the preconditioned directions) when preconditioned != 0. */
+opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, int32_t preconditioned,
+                                 size_t* bytes);
 opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
+
+/* ---- Learned preconditioner (not part of the paper) ----------------------
+ * A residual MLP shared by every Fourier mode (m, k) of one grid and
+ * conditioned on it approximates J^{-1} of the Newton-Krylov solver mode by
+ * mode; opf_nk_solve applies it as the right preconditioner of flexible
+ * GMRES.  Near the laminar state the Jacobian couples no two modes, so one
+ * network acting on single radial profiles can serve all of them.
+ *   Network (L residual layers of width H):
+ *     h_0 = W_in x + b_in;  h_l = h_{l-1} + relu(W_l h_{l-1} + b_l);
+ *     y = W_out h_L + b_out.
+ *   Dense layers run on the matrix cores: weights, x, h and back-propagated
+ *   gradients enter each product rounded to bfloat16 (nearest even) and
+ *   products accumulate in FP32; master weights, biases, activations,
+ *   gradients and the Adam moments are FP32.
+ *   Rows: din = P + 32 inputs, dout = P outputs, P = 6N rounded up to a
+ *   multiple of 32.  For a profile y_c(n) (c = u_r, u_theta, u_z) of mode
+ *   (m, k): s = sqrt(sum |y|^2 / 3N), rho = sum_c sum_n y_c(n),
+ *   e = rho/|rho| (1 if |rho| <= 1e-8 3N s), yhat = conj(e) y / s;
+ *   x[2(cN+n)] = Re yhat_c(n), x[2(cN+n)+1] = Im yhat_c(n), zeros up to P,
+ *   then 32 features of (mp m, alpha k).
+ *   Preconditioner: z_mk = s e f - y_mk with f the network output read as a
+ *   complex profile (so a zero network gives z = -y); z(0, k<0) =
+ *   conj z(0, -k).  The map is positively homogeneous and commutes with a
+ *   phase rotation of one mode.
+ *   Training pair (v, J v) -> row x of y = (J v)_mk and target
+ *   conj(e) v_mk / s + yhat (so that z reproduces v), weight s^2.
+ *   Loss of a batch: sum_r w_r sum_j (y_rj - t_rj)^2 / sum_r w_r
+ *   (w_r = 1 when no weights are given). */
+typedef struct {
+    int32_t width;      /* H: multiple of 32 in [32, 512] (256)              */
+    int32_t layers;     /* L: 1..8 (4)                                       */
+    int32_t max_rows;   /* rows per call, >= M(2K-1) of the context          */
+    uint64_t seed;      /* initial weights (SplitMix64 uniforms)             */
+    float lr, beta1, beta2, adam_eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8)      */
+} opf_mlp_config;
+
+opf_status opf_mlp_default_config(opf_mlp_config* cfg);  /* max_rows = 0: set it */
+/* Device bytes a network of this configuration needs for this context's grid. */
+opf_status opf_mlp_workspace_size(const opf_ctx* ctx, const opf_mlp_config* cfg, size_t* bytes);
+/* Create a network for ctx's grid (N, M, K, mp, alpha) in caller device
+ * memory (256-byte aligned), work on ctx's stream; the context must outlive
+ * the network.  Weights: U(-a, a), a = 1/sqrt(fan_in) (0.01 of that for
+ * the output layer), biases 0.  Synchronises. */
+opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_workspace, size_t bytes,
+                          opf_mlp** out);
+opf_status opf_mlp_destroy(opf_mlp* net);
+opf_status opf_mlp_dims(const opf_mlp* net, int32_t* din, int32_t* dout, int64_t* n_params);
+/* Parameters as one FP32 host array: W_in [H][din], b_in [H], then per
+ * layer W_l [H][H], b_l [H], then W_out [dout][H], b_out [dout].  Setting
+ * them clears the Adam state.  Synchronise. */
+opf_status opf_mlp_set_params(opf_mlp* net, const float* host, int64_t n);
+opf_status opf_mlp_get_params(opf_mlp* net, float* host, int64_t n);
+/* y_dev [rows][dout] = network(x_dev [rows][din]) (FP32 device rows). */
+opf_status opf_mlp_forward(opf_mlp* net, const float* x_dev, int32_t rows, float* y_dev);
+/* Loss and parameter gradient (host, FP32, parameter order) of one batch of
+ * rows with targets t_dev [rows][dout] and weights w_dev [rows] (or NULL);
+ * no update.  Synchronises. */
+opf_status opf_mlp_gradient(opf_mlp* net, const float* x_dev, const float* t_dev, const float* w_dev,
+                            int32_t rows, double* loss_host, float* grad_host);
+/* Adam on consecutive batches of `batch` rows (the last may be short),
+ * `epochs` passes in an order shuffled per pass from shuffle_seed;
+ * loss_host[epochs] (or NULL) gets the mean batch loss of each pass.
+ * batches * epochs <= 65536.  Synchronises. */
+opf_status opf_mlp_train(opf_mlp* net, const float* x_dev, const float* t_dev, const float* w_dev,
+                         int32_t rows, int32_t batch, int32_t epochs, uint64_t shuffle_seed, float* loss_host);
+/* Rows of npairs recorded pairs (opf_nk_opts.record_dev layout): x_dev
+ * [npairs M(2K-1)][din], t_dev [..][dout], w_dev [..] (or NULL), pair-major,
+ * mode (m, k) at row m(2K-1) + k + K - 1 within a pair. */
+opf_status opf_mlp_pack_pairs(opf_ctx* ctx, const opf_mlp* net, const void* pairs_dev, int32_t npairs,
+                              float* x_dev, float* t_dev, float* w_dev);
+/* z_dev = P(v_dev) (external layout, complex128), on ctx's stream. */
+opf_status opf_precondition(opf_ctx* ctx, opf_mlp* net, const void* v_dev, void* z_dev);
+const char* opf_mlp_last_error(const opf_mlp* net);
 
 /* Diagnostics of the current state (host struct; synchronises). */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);

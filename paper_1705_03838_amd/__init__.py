@@ -22,7 +22,10 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_get_nodes", "opf_set_state", "opf_get_state", "opf_step", "opf_nonlinear",
            "opf_vorticity", "opf_radial_solve", "opf_newton_residual", "opf_profile_steps",
            "opf_vec_dot", "opf_vec_axpby", "opf_nk_workspace_size", "opf_nk_solve",
-           "opf_diagnostics", "opf_ensemble_workspace_size", "opf_ensemble_create",
+           "opf_diagnostics", "opf_mlp_default_config", "opf_mlp_workspace_size", "opf_mlp_create",
+           "opf_mlp_destroy", "opf_mlp_dims", "opf_mlp_set_params", "opf_mlp_get_params",
+           "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pack_pairs",
+           "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error",
            "opf_status_string", "opf_last_error"]
@@ -46,13 +49,22 @@ class opf_diag(ctypes.Structure):
 class opf_nk_opts(ctypes.Structure):
     _fields_ = [("gmres_m", ctypes.c_int32), ("max_newton", ctypes.c_int32),
                 ("max_jvps", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("gmres_tol", ctypes.c_double), ("fd_eps", ctypes.c_double)]
+                ("gmres_tol", ctypes.c_double), ("fd_eps", ctypes.c_double),
+                ("precond", ctypes.c_void_p), ("record_dev", ctypes.c_void_p),
+                ("record_capacity", ctypes.c_int32)]
 
 
 class opf_nk_report(ctypes.Structure):
     _fields_ = [("newton_iterations", ctypes.c_int32), ("gmres_iterations", ctypes.c_int32),
                 ("jvps", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("residual", ctypes.c_double), ("residual_history", ctypes.c_double * 32)]
+                ("residual", ctypes.c_double), ("residual_history", ctypes.c_double * 32),
+                ("recorded", ctypes.c_int32), ("precond_applies", ctypes.c_int32)]
+
+
+class opf_mlp_config(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("layers", ctypes.c_int32), ("max_rows", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
 
 
 class OpfError(RuntimeError):
@@ -91,9 +103,22 @@ def load_library(path=LIB_PATH):
         "opf_profile_steps": ([vp, i32, P(ctypes.c_double), P(ctypes.c_int32)], i32),
         "opf_vec_dot": ([vp, vp, vp, P(ctypes.c_double)], i32),
         "opf_vec_axpby": ([vp, dbl, vp, dbl, vp], i32),
-        "opf_nk_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
+        "opf_nk_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], i32),
         "opf_nk_solve": ([vp, vp, dbl, dbl, P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
+        "opf_mlp_default_config": ([P(opf_mlp_config)], i32),
+        "opf_mlp_workspace_size": ([vp, P(opf_mlp_config), P(ctypes.c_size_t)], i32),
+        "opf_mlp_create": ([vp, P(opf_mlp_config), vp, ctypes.c_size_t, P(vp)], i32),
+        "opf_mlp_destroy": ([vp], i32),
+        "opf_mlp_dims": ([vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int64)], i32),
+        "opf_mlp_set_params": ([vp, vp, ctypes.c_int64], i32),
+        "opf_mlp_get_params": ([vp, vp, ctypes.c_int64], i32),
+        "opf_mlp_forward": ([vp, vp, i32, vp], i32),
+        "opf_mlp_gradient": ([vp, vp, vp, vp, i32, P(ctypes.c_double), vp], i32),
+        "opf_mlp_train": ([vp, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp], i32),
+        "opf_mlp_pack_pairs": ([vp, vp, vp, i32, vp, vp, vp], i32),
+        "opf_precondition": ([vp, vp, vp, vp], i32),
+        "opf_mlp_last_error": ([vp], ctypes.c_char_p),
         "opf_ensemble_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
         "opf_ensemble_create": ([vp, i32, vp, ctypes.c_size_t, vp, P(vp)], i32),
         "opf_ensemble_destroy": ([vp], i32),
@@ -278,14 +303,24 @@ class Solver:
         return out.value
 
     def nk_solve(self, x, T, shift, gmres_m=40, max_newton=20, max_jvps=400, tol=1e-8,
-                 gmres_tol=1e-3, fd_eps=1e-7):
-        """Newton-Krylov travelling-wave search; returns (solution, report dict)."""
+                 gmres_tol=1e-3, fd_eps=1e-7, precond=None, record=None):
+        """Newton-Krylov travelling-wave search; returns (solution, report dict).
+        precond: an Mlp (flexible GMRES with it as right preconditioner) or None.
+        record: None, or a complex128 device tensor [n, 2, 3, M, 2K-1, N] that
+        receives the pairs (z, J z) of the products the solver forms."""
         x = self._dev(x, self.shape).clone()
         nbytes = ctypes.c_size_t()
-        self._check(self.lib.opf_nk_workspace_size(self.ctx, int(gmres_m), ctypes.byref(nbytes)))
+        self._check(self.lib.opf_nk_workspace_size(self.ctx, int(gmres_m), int(precond is not None),
+                                                    ctypes.byref(nbytes)))
         kry = self.torch.empty(nbytes.value, dtype=self.torch.uint8, device=self.device)
+        cap = 0
+        if record is not None:
+            assert record.is_cuda and record.dtype == self.torch.complex128 and record.is_contiguous()
+            assert tuple(record.shape[1:]) == (2,) + tuple(self.shape)
+            cap = record.shape[0]
         o = opf_nk_opts(int(gmres_m), int(max_newton), int(max_jvps), float(tol), float(gmres_tol),
-                        float(fd_eps))
+                        float(fd_eps), precond.handle if precond is not None else None,
+                        record.data_ptr() if record is not None else None, int(cap))
         rep = opf_nk_report()
         self._check(self.lib.opf_nk_solve(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
                                           ctypes.byref(o), ctypes.c_void_p(kry.data_ptr()),
@@ -293,7 +328,8 @@ class Solver:
         n = rep.newton_iterations
         return x, {"newton_iterations": n, "gmres_iterations": rep.gmres_iterations,
                    "jvps": rep.jvps, "converged": bool(rep.converged), "residual": rep.residual,
-                   "history": [rep.residual_history[i] for i in range(min(n + 1, 32))]}
+                   "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
+                   "recorded": rep.recorded, "precond_applies": rep.precond_applies}
 
     def diagnostics(self):
         d = opf_diag()
@@ -365,6 +401,134 @@ class Ensemble:
         if getattr(self, "ens", None):
             self.lib.opf_ensemble_destroy(self.ens)
             self.ens = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """Learned preconditioner network of a Solver's grid (see opf.h): a
+    residual MLP on the matrix cores, trained with Adam on rows packed from
+    (v, J v) pairs, applied by Solver.nk_solve(precond=...)."""
+
+    def __init__(self, solver, width=256, layers=4, max_rows=None, seed=1, lr=1e-3, beta1=0.9, beta2=0.999,
+                 adam_eps=1e-8):
+        import torch
+        self.torch = torch
+        self.solver = solver  # the context must outlive the network
+        self.lib = solver.lib
+        rows = solver.M * (2 * solver.K - 1)
+        self.mode_rows = rows
+        cfg = opf_mlp_config()
+        solver._check(self.lib.opf_mlp_default_config(ctypes.byref(cfg)))
+        cfg.width, cfg.layers, cfg.seed = int(width), int(layers), int(seed)
+        cfg.max_rows = int(max_rows if max_rows is not None else rows)
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps = lr, beta1, beta2, adam_eps
+        self.cfg = cfg
+        self.layers = int(layers)
+        nbytes = ctypes.c_size_t()
+        solver._check(self.lib.opf_mlp_workspace_size(solver.ctx, ctypes.byref(cfg), ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=solver.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        solver._check(self.lib.opf_mlp_create(solver.ctx, ctypes.byref(cfg), ctypes.c_void_p(ptr),
+                                              ctypes.c_size_t(nbytes.value), ctypes.byref(h)))
+        self.handle = h.value
+        din, dout, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.opf_mlp_dims(self.handle, ctypes.byref(din), ctypes.byref(dout), ctypes.byref(n)))
+        self.din, self.dout, self.n_params = din.value, dout.value, n.value
+
+    def _check(self, st):
+        if st != OPF_OK:
+            msg = self.lib.opf_status_string(st).decode()
+            if getattr(self, "handle", None):
+                detail = self.lib.opf_mlp_last_error(self.handle)
+                if detail:
+                    msg += ": " + detail.decode()
+            raise OpfError(st, msg)
+
+    def _rows(self, t, width):
+        t = self.torch.as_tensor(t).to(device=self.solver.device, dtype=self.torch.float32).contiguous()
+        if t.dim() != 2 or t.shape[1] != width:
+            raise OpfError(OPF_E_INVALID, f"expected rows of width {width}, got {tuple(t.shape)}")
+        return t
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(self.lib.opf_mlp_set_params(self.handle, ctypes.c_void_p(a.ctypes.data), a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.lib.opf_mlp_get_params(self.handle, ctypes.c_void_p(a.ctypes.data), a.size))
+        return a
+
+    def forward(self, x):
+        x = self._rows(x, self.din)
+        y = self.torch.empty((x.shape[0], self.dout), dtype=self.torch.float32, device=x.device)
+        self._check(self.lib.opf_mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                             ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def gradient(self, x, t, w=None):
+        import numpy as np
+        x, t = self._rows(x, self.din), self._rows(t, self.dout)
+        wp = None
+        if w is not None:
+            w = self.torch.as_tensor(w).to(device=x.device, dtype=self.torch.float32).contiguous()
+            wp = w.data_ptr()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self.lib.opf_mlp_gradient(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(wp), x.shape[0],
+                                              ctypes.byref(loss), ctypes.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def train(self, x, t, w=None, batch=None, epochs=1, seed=1):
+        import numpy as np
+        x, t = self._rows(x, self.din), self._rows(t, self.dout)
+        wp = None
+        if w is not None:
+            w = self.torch.as_tensor(w).to(device=x.device, dtype=self.torch.float32).contiguous()
+            wp = w.data_ptr()
+        batch = int(batch if batch is not None else self.mode_rows)
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        self._check(self.lib.opf_mlp_train(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(wp), x.shape[0],
+                                           batch, int(epochs), int(seed), ctypes.c_void_p(losses.ctypes.data)))
+        return losses[:epochs]
+
+    def pack_pairs(self, pairs):
+        """Rows (x, t, w) of recorded pairs [n, 2, 3, M, 2K-1, N] (complex128)."""
+        torch = self.torch
+        s = self.solver
+        pairs = s._dev(pairs).contiguous()
+        assert tuple(pairs.shape[1:]) == (2,) + tuple(s.shape)
+        n = pairs.shape[0] * self.mode_rows
+        x = torch.empty((n, self.din), dtype=torch.float32, device=s.device)
+        t = torch.empty((n, self.dout), dtype=torch.float32, device=s.device)
+        w = torch.empty((n,), dtype=torch.float32, device=s.device)
+        s._check(self.lib.opf_mlp_pack_pairs(s.ctx, self.handle, ctypes.c_void_p(pairs.data_ptr()),
+                                             pairs.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(w.data_ptr())))
+        return x, t, w
+
+    def precondition(self, v):
+        s = self.solver
+        v = s._dev(v, s.shape)
+        z = self.torch.empty_like(v)
+        s._check(self.lib.opf_precondition(s.ctx, self.handle, ctypes.c_void_p(v.data_ptr()),
+                                           ctypes.c_void_p(z.data_ptr())))
+        return z
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.opf_mlp_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

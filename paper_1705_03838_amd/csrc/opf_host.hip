@@ -37,6 +37,12 @@ struct opf_ctx {
     std::string err;
 };
 
+namespace opf {
+hipStream_t ctx_stream(const opf_ctx* c) { return c->stream; }
+const opf_params& ctx_params(const opf_ctx* c) { return c->p; }
+void ctx_set_error(opf_ctx* c, const std::string& msg) { c->err = msg; }
+}  // namespace opf
+
 namespace {
 
 constexpr size_t ALIGN = 256;
@@ -1051,9 +1057,9 @@ opf_status opf_newton_residual(opf_ctx* c, const void* x, double T, double shift
     return OPF_OK;
 }
 
-opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, size_t* bytes) {
+opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, int32_t preconditioned, size_t* bytes) {
     if (!c || !bytes || m < 1) return OPF_E_INVALID;
-    *bytes = (size_t)(m + 5) * 3 * field_entries(c) * 16;
+    *bytes = (size_t)(m + 5 + (preconditioned ? m : 0)) * 3 * field_entries(c) * 16;
     return OPF_OK;
 }
 
@@ -1061,12 +1067,17 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* rep) {
     if (!c || !x_dev || !o || !krylov_dev || !rep) return OPF_E_INVALID;
     const int m = o->gmres_m;
+    const bool pre = o->precond != nullptr;
     size_t need = 0;
-    if (opf_nk_workspace_size(c, m, &need) != OPF_OK || krylov_bytes < need) return OPF_E_NOMEM;
+    if (opf_nk_workspace_size(c, m, pre ? 1 : 0, &need) != OPF_OK || krylov_bytes < need) return OPF_E_NOMEM;
+    if (o->record_capacity < 0 || (o->record_capacity > 0 && !o->record_dev)) return OPF_E_INVALID;
     *rep = opf_nk_report{};
     const size_t vb = 3 * field_entries(c) * 16;  // bytes per vector
     unsigned char* base = static_cast<unsigned char*>(krylov_dev);
     auto vec = [&](int i) { return static_cast<void*>(base + (size_t)i * vb); };
+    // flexible GMRES keeps the preconditioned directions z_j = P(v_j)
+    auto zvec = [&](int j) { return static_cast<void*>(base + (size_t)(m + 5 + j) * vb); };
+    unsigned char* rec = static_cast<unsigned char*>(o->record_dev);
     void* F0 = vec(m + 1);   // F(x)
     void* tmp = vec(m + 2);  // x + eps v, then F(x + eps v)
     void* w = vec(m + 3);    // Arnoldi vector / J v
@@ -1101,6 +1112,12 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
             NKCHK(opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, tmp));
             HIPCHK(c, hipMemcpyAsync(w, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
             rep->jvps += 1;
+            if (rec && rep->recorded < o->record_capacity) {
+                unsigned char* slot = rec + (size_t)rep->recorded * 2 * vb;
+                HIPCHK(c, hipMemcpyAsync(slot, v, vb, hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(c, hipMemcpyAsync(slot + vb, w, vb, hipMemcpyDeviceToDevice, c->stream));
+                rep->recorded += 1;
+            }
             return OPF_OK;
         };
         // GMRES(m) for J dx = -F0, x0 = 0, one cycle per restart
@@ -1127,7 +1144,16 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
             g[0] = beta;
             int k = 0;
             for (int j = 0; j < m; ++j) {
-                NKCHK(jv(vec(j), 1.0));
+                if (pre) {
+                    double zn = 0.0;
+                    NKCHK(opf_precondition(c, o->precond, vec(j), zvec(j)));
+                    rep->precond_applies += 1;
+                    NKCHK(nrm(zvec(j), &zn));
+                    if (!(zn > 0.0)) return OPF_E_NUMERIC;
+                    NKCHK(jv(zvec(j), zn));
+                } else {
+                    NKCHK(jv(vec(j), 1.0));
+                }
                 for (int i = 0; i <= j; ++i) {
                     NKCHK(dot(w, vec(i), &Hh(i, j)));
                     NKCHK(opf_vec_axpby(c, -Hh(i, j), vec(i), 1.0, w));
@@ -1158,7 +1184,7 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
                 for (int j2 = i + 1; j2 < k; ++j2) acc -= Hh(i, j2) * y[j2];
                 y[i] = acc / Hh(i, i);
             }
-            for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, dx));
+            for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], pre ? zvec(i) : vec(i), 1.0, dx));
             ++restarts;
             if (std::fabs(g[k]) <= o->gmres_tol * bn || rep->jvps >= o->max_jvps) break;
         }

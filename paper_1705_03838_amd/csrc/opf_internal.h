@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/opf.h"
 
@@ -100,5 +101,10 @@ bool gm_ok(int gm, int mp);
 constexpr int NFH = 6;  // Helmholtz factors a solve workgroup stages at once
 hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s);
 hipError_t launch_energy(const AuxArgs& a, hipStream_t s);
+
+// Context accessors for translation units other than the host core.
+hipStream_t ctx_stream(const opf_ctx* c);
+const opf_params& ctx_params(const opf_ctx* c);
+void ctx_set_error(opf_ctx* c, const std::string& msg);
 
 }  // namespace opf

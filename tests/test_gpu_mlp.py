@@ -1,0 +1,199 @@
+"""GPU parity of the learned-preconditioner network (matrix-core GEMMs,
+backward pass, Adam, pack / unpack of mode profiles) against the oracle MLP.
+
+Tolerances.  The device rounds every GEMM operand to bfloat16 exactly as the
+oracle's bf16 mode does, but accumulates in FP32 where the oracle uses FP64.
+The accumulation differs by about K 2^-24 relative (K <= 1536 here, ~1e-4);
+where that moves a value across a bfloat16 rounding boundary before the next
+product, one element changes by one bfloat16 ulp (2^-8).  With a few percent
+of such flips per layer the norm-wise effect stays below ~3e-3, so outputs
+and gradients are held to 1e-2 relative (norm-wise) against the bf16 oracle,
+while the same outputs differ from the unrounded FP64 oracle by several times
+more (which shows that the device really computes in bfloat16).  Adam and the
+packing run in FP32 / FP64 arithmetic and are held to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from inputs import make_state
+
+pytestmark = pytest.mark.gpu
+
+GRID = dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007)  # 42 mode rows: ragged tile
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def make_net(torch_cuda, width=64, layers=3, max_rows=None, seed=7, **kw):
+    import paper_1705_03838_amd as opf
+    from oracle.mlp import flatten, init_params, unflatten
+    s = opf.Solver(**GRID)
+    net = opf.Mlp(s, width=width, layers=layers, max_rows=max_rows, **kw)
+    p = init_params(net.din, width, layers, net.dout, seed=seed)
+    rng = np.random.default_rng(seed)
+    for k in p:
+        if k.startswith("b_"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    p["W_out"] *= 0.5
+    flat = flatten(p, layers).astype(np.float32)
+    net.set_params(flat)
+    p32 = unflatten(flat.astype(np.float64), net.din, width, layers, net.dout)
+    return s, net, p32
+
+
+def nrel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rows(rng, n, d):
+    return (rng.standard_normal((n, d))).astype(np.float32)
+
+
+def test_forward_matches_bf16_oracle(torch_cuda):
+    from oracle.mlp import forward
+    s, net, p = make_net(torch_cuda, max_rows=200)
+    rng = np.random.default_rng(1)
+    for n in (1, 42, 77, 200):  # single row, ragged tiles, full
+        say("mlp forward rows", n)
+        x = rows(rng, n, net.din)
+        y = net.forward(torch_cuda.from_numpy(x)).cpu().numpy().astype(np.float64)
+        yb, _ = forward(p, x.astype(np.float64), 3, bf16=True)
+        yf, _ = forward(p, x.astype(np.float64), 3, bf16=False)
+        e_b, e_f = nrel(y, yb), nrel(y, yf)
+        say("   vs bf16 oracle", e_b, "vs fp64 oracle", e_f)
+        assert e_b <= 1e-2
+        assert e_b <= 0.3 * e_f
+
+
+def test_gradient_matches_bf16_oracle(torch_cuda):
+    from oracle.mlp import backward, flatten, forward, loss
+    s, net, p = make_net(torch_cuda, max_rows=224)  # batch rows (160 padded) < capacity (224)
+    rng = np.random.default_rng(2)
+    n = 150
+    x, t = rows(rng, n, net.din), rows(rng, n, net.dout)
+    w = rng.uniform(0.2, 2.0, n).astype(np.float32)
+    say("mlp gradient rows", n)
+    lg, g = net.gradient(torch_cuda.from_numpy(x), torch_cuda.from_numpy(t), torch_cuda.from_numpy(w))
+    x64, t64, w64 = x.astype(np.float64), t.astype(np.float64), w.astype(np.float64)
+    y, cache = forward(p, x64, 3, bf16=True)
+    gref = backward(p, cache, y, t64, 3, bf16=True, w=w64)
+    assert abs(lg - loss(y, t64, w64)) <= 1e-3 * loss(y, t64, w64)
+    gflat = flatten(gref, 3)
+    o = 0
+    for k in ["W_in", "b_in", "W_0", "b_0", "W_1", "b_1", "W_2", "b_2", "W_out", "b_out"]:
+        sz = gref[k].size
+        e = nrel(g[o:o + sz].astype(np.float64), gflat[o:o + sz])
+        say("   grad", k, e)
+        assert e <= 1e-2, k
+        o += sz
+    assert o == net.n_params
+
+
+def test_adam_step_and_weight_copies(torch_cuda):
+    from oracle.mlp import adam, forward, unflatten
+    s, net, p = make_net(torch_cuda, max_rows=64, lr=1e-2)
+    rng = np.random.default_rng(3)
+    n = 64
+    x, t = rows(rng, n, net.din), rows(rng, n, net.dout)
+    p0 = net.get_params().astype(np.float64)
+    _, g = net.gradient(torch_cuda.from_numpy(x), torch_cuda.from_numpy(t))
+    net.train(torch_cuda.from_numpy(x), torch_cuda.from_numpy(t), batch=n, epochs=1)
+    p1 = net.get_params().astype(np.float64)
+    ref, _, _ = adam(p0, g.astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), 1, lr=1e-2)
+    say("adam step max diff", np.max(np.abs(p1 - ref)))
+    assert np.max(np.abs(p1 - ref)) <= 1e-6
+    # the bfloat16 weight copies follow the update
+    y = net.forward(torch_cuda.from_numpy(x)).cpu().numpy().astype(np.float64)
+    q = unflatten(p1, net.din, 64, 3, net.dout)
+    yb, _ = forward(q, x.astype(np.float64), 3, bf16=True)
+    assert nrel(y, yb) <= 1e-2
+
+
+def field(s, seed):
+    v = make_state(GRID["N"], GRID["M"], GRID["K"], GRID["mp"], GRID["alpha"], s.nodes(), 1e-2, 3.0, 3.0,
+                   seed, laminar=False)
+    K = GRID["K"]
+    for kk in range(K - 1):  # exactly Hermitian at m = 0
+        v[:, 0, kk] = np.conj(v[:, 0, 2 * (K - 1) - kk])
+    v[:, 0, K - 1] = v[:, 0, K - 1].real
+    return v
+
+
+def test_pack_pairs_match_oracle(torch_cuda):
+    from oracle.mlp import pack
+    s, net, p = make_net(torch_cuda, max_rows=100)
+    v, jv = field(s, 21), field(s, 22)
+    pairs = np.stack([np.stack([v, jv]), np.stack([jv, v])])
+    say("pack pairs", pairs.shape)
+    x, t, w = net.pack_pairs(torch_cuda.from_numpy(pairs))
+    x, t, w = x.cpu().numpy(), t.cpu().numpy(), w.cpu().numpy()
+    rows_ = s.M * (2 * s.K - 1)
+    for i in range(2):
+        X, T, W, _, _ = pack(pairs[i, 1], GRID["mp"], GRID["alpha"], z=pairs[i, 0])
+        sl = slice(i * rows_, (i + 1) * rows_)
+        assert np.max(np.abs(x[sl] - X)) <= 1e-6 * np.max(np.abs(X))
+        assert np.max(np.abs(t[sl] - T)) <= 1e-6 * np.max(np.abs(T))
+        assert np.all(np.abs(w[sl] - W) <= 1e-6 * W + 1e-30)
+
+
+def test_precondition_matches_oracle(torch_cuda):
+    from oracle.mlp import precondition
+    s, net, p = make_net(torch_cuda)
+    v = field(s, 23)
+    say("precondition", v.shape)
+    z = net.precondition(torch_cuda.from_numpy(v)).cpu().numpy()
+    zb = precondition(p, 3, v, GRID["mp"], GRID["alpha"], bf16=True)
+    assert nrel(z + v, zb + v) <= 1e-2
+    K = GRID["K"]
+    for kk in range(K - 1):
+        assert np.array_equal(z[:, 0, kk], np.conj(z[:, 0, 2 * (K - 1) - kk]))
+    # a network with zero output layer gives z = -v exactly
+    q = net.get_params()
+    q[-(net.dout * 64 + net.dout):] = 0.0
+    net.set_params(q)
+    z0 = net.precondition(torch_cuda.from_numpy(v)).cpu().numpy()
+    assert np.array_equal(z0, -v)
+
+
+def test_flexible_gmres_with_minus_identity_matches_plain(torch_cuda):
+    """P = -I (zero output layer) makes flexible GMRES plain GMRES on -J:
+    same Newton iterations and converged result as the unpreconditioned
+    solve, and the recorded pairs are (z, J z) products."""
+    import paper_1705_03838_amd as opf
+    kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
+    say("fgmres -I", kw)
+    s = opf.Solver(**kw)
+    net = opf.Mlp(s, width=32, layers=1)
+    q = net.get_params()
+    q[-(net.dout * 32 + net.dout):] = 0.0
+    net.set_params(q)
+    x = make_state(12, 2, 2, 2, 1.25, s.nodes(), 1e-4, 4.0, 4.0, 6)
+    rec = torch_cuda.zeros((8, 2) + s.shape, dtype=torch_cuda.complex128, device="cuda")
+    x1, r1 = s.nk_solve(torch_cuda.from_numpy(x), 1.0, 0.0, tol=1e-10, gmres_tol=1e-6, record=rec)
+    x2, r2 = s.nk_solve(torch_cuda.from_numpy(x), 1.0, 0.0, tol=1e-10, gmres_tol=1e-6, precond=net)
+    say("  plain", r1, "\n  fgmres", r2)
+    assert r1["converged"] and r2["converged"]
+    assert r2["newton_iterations"] == r1["newton_iterations"]
+    assert abs(r2["jvps"] - r1["jvps"]) <= 2 and r2["precond_applies"] > 0
+    d = (x1 - x2).cpu().numpy()
+    assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(d), torch_cuda.from_numpy(d))) < 1e-8
+    assert r1["recorded"] == min(8, r1["jvps"])
+    # a recorded pair reproduces J z by a fresh finite difference
+    z, jz = rec[0, 0], rec[0, 1]
+    xs = torch_cuda.from_numpy(x).cuda()
+    F0, _ = s.newton_residual(xs, 1.0, 0.0)
+    zn = np.sqrt(s.vec_dot(z, z))
+    eps = 1e-7 * max(np.sqrt(s.vec_dot(xs, xs)), 1.0) / zn
+    F1, _ = s.newton_residual(xs + eps * z, 1.0, 0.0)
+    fd = ((F1 - F0) / eps - jz).cpu().numpy()
+    assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(fd), torch_cuda.from_numpy(fd))) <= 1e-10 * max(
+        1.0, np.sqrt(s.vec_dot(jz, jz)))
