@@ -106,25 +106,67 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     return (t1 - t0) / steps, prof, diag
 
 
-def run_nk(w, gmres_m=40):
+def run_nk(w, gmres_m=40, probes=320, rank=8, train_steps=6000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
-    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||."""
+    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain,
+    then with the learned preconditioner trained on Jacobian probes at
+    laminar flow (probing and training timed separately: they are made once
+    per grid, Re and T and serve every later search)."""
     import torch
 
     import paper_1705_03838_amd as opf
-    from inputs import workload_state
+    from inputs import laminar_state, workload_state
 
     s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
-    x0 = workload_state(w, s.nodes())
-    torch.cuda.synchronize()
+    x0 = torch.from_numpy(workload_state(w, s.nodes()))
+
+    def search(precond=None):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond)
+        torch.cuda.synchronize()
+        rep["wall_s"] = round(time.perf_counter() - t0, 3)
+        rep["history"] = [float(f"{h:.3e}") for h in rep["history"]]
+        return rep
+
+    plain = search()
     t0 = time.perf_counter()
-    _, rep = s.nk_solve(torch.from_numpy(x0), w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3)
-    torch.cuda.synchronize()
-    rep["wall_s"] = round(time.perf_counter() - t0, 3)
-    rep["steps_per_residual"] = int(round(w["T"] / w["dt"]))
+    lam = torch.from_numpy(laminar_state(w["N"], w["M"], w["K"], s.nodes()))
+    pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11)
+    probe_s = time.perf_counter() - t0
+    net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3)
+    t0 = time.perf_counter()
+    losses = net.train_pairs(pairs, batch=batch, steps=train_steps, seed=5)
+    train_s = time.perf_counter() - t0
+    del pairs
+    pre = search(net)
+    flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
+    out = {"plain": plain, "preconditioned": pre,
+           "wall_speedup": round(plain["wall_s"] / pre["wall_s"], 3),
+           "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
+           "steps_per_residual": int(round(w["T"] / w["dt"])),
+           "network": {"width": 256, "layers": 4, "rank": rank, "params": net.n_params,
+                       "probes": probes, "probe_s": round(probe_s, 2),
+                       "train_steps": train_steps, "batch_pairs": batch, "train_s": round(train_s, 2),
+                       "train_step_ms": round(train_s / train_steps * 1e3, 4),
+                       "train_gemm_TFLOPs_lower_bound": round(flops_step * train_steps / train_s / 1e12, 2),
+                       "loss_first_last": [float(f"{losses[0]:.3e}"), float(f"{losses[-100:].mean():.3e}")]},
+           "break_even_searches": round((probe_s + train_s) / max(plain["wall_s"] - pre["wall_s"], 1e-9), 2)}
+    net.close()
     s.close()
-    return rep
+    return out
+
+
+def mlp_train_flops(net, rows):
+    """GEMM flops of one training step over the mode rows (padded to 32):
+    forward 2 R (din H + L H^2 + H dout), backward twice that less the input
+    gradient of the first layer."""
+    rp = (rows + 31) // 32 * 32
+    H, L, din, dout = net.width, net.layers, net.din, net.dout
+    fwd = 2 * rp * (din * H + L * H * H + H * dout)
+    bwd = 2 * rp * (din * H + 2 * L * H * H + 2 * H * dout)
+    return fwd + bwd
 
 
 def run_ensemble(steps=500, warmup=5):
@@ -275,7 +317,7 @@ def main():
     if not args.no_nk:
         out["newton_krylov"] = {"workload": "nk: N=48, |m|<24 (mp=2), |k|<32, alpha=1.25, Re=2400, "
                                             "dt=0.01, T=20, near-laminar seed 5000",
-                                "gmres": run_nk(WORKLOADS["nk"])}
+                                **run_nk(WORKLOADS["nk"])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

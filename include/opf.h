@@ -224,48 +224,67 @@ opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, int32_t pr
 opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
 
+/* Jacobian probes of the travelling-wave residual at x_dev (training data
+ * for the learned preconditioner, in the layout opf_nk_solve records):
+ * pair i = (z_i, J z_i) at vectors 2i, 2i+1 of pairs_dev.  z_i: independent
+ * unit normals in every real and imaginary part (SplitMix64 of (seed, i) and
+ * the element counter, Box-Muller), made the spectrum of a real field
+ * (m = 0: A(0,-k) = conj A(0,k), A(0,0) real) and scaled to unit energy norm;
+ * J z = (F(x + eps z) - F(x)) / eps, eps = fd_eps max(||x||, 1).
+ * work_dev: 3 vectors of scratch.  The context's state is overwritten.
+ * Synchronises. */
+opf_status opf_probe_pairs(opf_ctx* ctx, const void* x_dev, double T, double shift, int32_t n,
+                           uint64_t seed, double fd_eps, void* pairs_dev, void* work_dev);
+
 /* ---- Learned preconditioner (not part of the paper) ----------------------
- * A residual MLP shared by every Fourier mode (m, k) of one grid and
- * conditioned on it approximates J^{-1} of the Newton-Krylov solver mode by
- * mode; opf_nk_solve applies it as the right preconditioner of flexible
- * GMRES.  Near the laminar state the Jacobian couples no two modes, so one
- * network acting on single radial profiles can serve all of them.
- *   Network (L residual layers of width H):
+ * A residual MLP, shared by every Fourier mode (m, k) of one grid and fed
+ * only the mode's features, models the Newton-Krylov Jacobian on each mode
+ * as -I plus a rank-R term,
+ *   J_mk ~ -I + U_mk V_mk^H,   U_mk, V_mk: 3N x R complex,
+ * acting on the mode's radial profile (element e = c N + n for component
+ * c = u_r, u_theta, u_z and node n).  Near laminar flow the Jacobian couples
+ * no two modes and differs from -I by a few slow, non-normal directions per
+ * mode, which the rank-R term holds.  The preconditioner is the exact
+ * inverse of that model (Sherman-Morrison-Woodbury, FP64):
+ *   P(v)_mk = -v_mk - U (I_R - V^H U)^{-1} V^H v_mk = -v_mk + A_mk (B_mk^H v_mk).
+ * Learning J rather than J^{-1} keeps the fit well conditioned: the
+ * network's bfloat16-limited errors are not multiplied by the large gains
+ * J^{-1} has along nearly neutral directions.  P is linear on every mode,
+ * so flexible GMRES with it keeps the minimal-residual property of GMRES.
+ * (m = 0, k < 0) is the conjugate of (0, -k) and (0, 0) keeps its real
+ * part, so P maps real fields to real fields.
+ *   Network (L residual layers of width H), one row per mode:
  *     h_0 = W_in x + b_in;  h_l = h_{l-1} + relu(W_l h_{l-1} + b_l);
  *     y = W_out h_L + b_out.
+ *   x = 32 features of (mu, kappa) = (mp m, alpha k): 1, mu/48, kappa/40,
+ *   |kappa|/40, sign kappa, (mu/48)^2, (kappa/40)^2, mu |kappa|/1920,
+ *   one-hot of m for m < 8, one-hot of k for |k| <= 7, [|k| > 7].
+ *   y = (U, V): U[e][j] at 2(e R + j) (+1 imaginary part), V likewise from
+ *   6 N R on; dout = 12 N R rounded up to a multiple of 32.
  *   Dense layers run on the matrix cores: weights, x, h and back-propagated
  *   gradients enter each product rounded to bfloat16 (nearest even) and
  *   products accumulate in FP32; master weights, biases, activations,
- *   gradients and the Adam moments are FP32.
- *   Rows: din = P + 32 inputs, dout = P outputs, P = 6N rounded up to a
- *   multiple of 32.  For a profile y_c(n) (c = u_r, u_theta, u_z) of mode
- *   (m, k): s = sqrt(sum |y|^2 / 3N), rho = sum_c sum_n y_c(n),
- *   e = rho/|rho| (1 if |rho| <= 1e-8 3N s), yhat = conj(e) y / s;
- *   x[2(cN+n)] = Re yhat_c(n), x[2(cN+n)+1] = Im yhat_c(n), zeros up to P,
- *   then 32 features of (mp m, alpha k).
- *   Preconditioner: z_mk = s e f - y_mk with f the network output read as a
- *   complex profile (so a zero network gives z = -y); z(0, k<0) =
- *   conj z(0, -k).  The map is positively homogeneous and commutes with a
- *   phase rotation of one mode.
- *   Training pair (v, J v) -> row x of y = (J v)_mk and target
- *   conj(e) v_mk / s + yhat (so that z reproduces v), weight s^2.
- *   Loss of a batch: sum_r w_r sum_j (y_rj - t_rj)^2 / sum_r w_r
- *   (w_r = 1 when no weights are given). */
+ *   gradients, the Adam moments and U, V are FP32.
+ *   Training pairs (z, J z) (as opf_nk_solve records them or
+ *   opf_probe_pairs makes them): for mode q and pair p with s the RMS of the
+ *   z_q profile (pairs with s = 0 skip), r = -z_q/s + U (V^H z_q/s) - (J z)_q/s;
+ *   loss = mean over modes and pairs of |r|^2. */
 typedef struct {
     int32_t width;      /* H: multiple of 32 in [32, 512] (256)              */
     int32_t layers;     /* L: 1..8 (4)                                       */
-    int32_t max_rows;   /* rows per call, >= M(2K-1) of the context          */
+    int32_t rank;       /* R: 1..32 with 48 N R <= 65536 (8)                 */
+    int32_t max_rows;   /* rows of the plain row calls (>= mode count used)  */
     uint64_t seed;      /* initial weights (SplitMix64 uniforms)             */
     float lr, beta1, beta2, adam_eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8)      */
 } opf_mlp_config;
 
-opf_status opf_mlp_default_config(opf_mlp_config* cfg);  /* max_rows = 0: set it */
+opf_status opf_mlp_default_config(opf_mlp_config* cfg);
 /* Device bytes a network of this configuration needs for this context's grid. */
 opf_status opf_mlp_workspace_size(const opf_ctx* ctx, const opf_mlp_config* cfg, size_t* bytes);
 /* Create a network for ctx's grid (N, M, K, mp, alpha) in caller device
- * memory (256-byte aligned), work on ctx's stream; the context must outlive
- * the network.  Weights: U(-a, a), a = 1/sqrt(fan_in) (0.01 of that for
- * the output layer), biases 0.  Synchronises. */
+ * memory (256-byte aligned); work goes to ctx's stream and the context must
+ * outlive the network.  Weights: U(-a, a), a = 1/sqrt(fan_in) (0.01 of that
+ * for the output layer), biases 0, so P starts near -I.  Synchronises. */
 opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_workspace, size_t bytes,
                           opf_mlp** out);
 opf_status opf_mlp_destroy(opf_mlp* net);
@@ -275,24 +294,33 @@ opf_status opf_mlp_dims(const opf_mlp* net, int32_t* din, int32_t* dout, int64_t
  * them clears the Adam state.  Synchronise. */
 opf_status opf_mlp_set_params(opf_mlp* net, const float* host, int64_t n);
 opf_status opf_mlp_get_params(opf_mlp* net, float* host, int64_t n);
-/* y_dev [rows][dout] = network(x_dev [rows][din]) (FP32 device rows). */
+/* The plain network on rows: y_dev [rows][dout] = net(x_dev [rows][din])
+ * (FP32 device rows, rows <= max(max_rows, M(2K-1))). */
 opf_status opf_mlp_forward(opf_mlp* net, const float* x_dev, int32_t rows, float* y_dev);
-/* Loss and parameter gradient (host, FP32, parameter order) of one batch of
- * rows with targets t_dev [rows][dout] and weights w_dev [rows] (or NULL);
- * no update.  Synchronises. */
+/* Squared-error loss sum_r w_r sum_j (y_rj - t_rj)^2 / sum_r w_r of one
+ * batch of rows (w_dev NULL: w = 1) and its parameter gradient (host FP32,
+ * parameter order); no update.  Synchronises. */
 opf_status opf_mlp_gradient(opf_mlp* net, const float* x_dev, const float* t_dev, const float* w_dev,
                             int32_t rows, double* loss_host, float* grad_host);
-/* Adam on consecutive batches of `batch` rows (the last may be short),
- * `epochs` passes in an order shuffled per pass from shuffle_seed;
- * loss_host[epochs] (or NULL) gets the mean batch loss of each pass.
- * batches * epochs <= 65536.  Synchronises. */
+/* Adam on that loss over consecutive batches of `batch` rows, `epochs`
+ * passes in an order shuffled per pass; loss_host[epochs] (or NULL) gets
+ * the mean batch loss of each pass; batches * epochs <= 65536.  Synchronises. */
 opf_status opf_mlp_train(opf_mlp* net, const float* x_dev, const float* t_dev, const float* w_dev,
                          int32_t rows, int32_t batch, int32_t epochs, uint64_t shuffle_seed, float* loss_host);
-/* Rows of npairs recorded pairs (opf_nk_opts.record_dev layout): x_dev
- * [npairs M(2K-1)][din], t_dev [..][dout], w_dev [..] (or NULL), pair-major,
- * mode (m, k) at row m(2K-1) + k + K - 1 within a pair. */
-opf_status opf_mlp_pack_pairs(opf_ctx* ctx, const opf_mlp* net, const void* pairs_dev, int32_t npairs,
-                              float* x_dev, float* t_dev, float* w_dev);
+/* Pair loss of the pairs idx_host[0..batch) of pairs_dev (npairs pairs,
+ * opf_nk_opts.record_dev layout) and its parameter gradient (host FP32);
+ * no update.  Synchronises. */
+opf_status opf_mlp_pair_gradient(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs,
+                                 const int32_t* idx_host, int32_t batch, double* loss_host, float* grad_host);
+/* Adam on the pair loss: `steps` steps of `batch` pairs, taken in order from
+ * per-epoch shuffles (seed) of the npairs pairs; loss_host[steps] (or NULL)
+ * gets each step's loss.  batch * steps <= 65536.  Synchronises. */
+opf_status opf_mlp_train_pairs(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs, int32_t batch,
+                               int32_t steps, uint64_t seed, float* loss_host);
+/* The preconditioner's factor rows (A, B) for the grid's modes (host FP32
+ * [M(2K-1)][dout], same layout as (U, V); host may be NULL) and the number
+ * of modes whose I - V^H U is singular (those get P = -I).  Synchronises. */
+opf_status opf_mlp_factors(opf_mlp* net, float* host, int64_t n, int32_t* singular_modes);
 /* z_dev = P(v_dev) (external layout, complex128), on ctx's stream. */
 opf_status opf_precondition(opf_ctx* ctx, opf_mlp* net, const void* v_dev, void* z_dev);
 const char* opf_mlp_last_error(const opf_mlp* net);

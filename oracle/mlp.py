@@ -68,10 +68,16 @@ def loss(y, t, w=None):
 
 def backward(p, cache, y, t, layers, bf16=False, w=None):
     """Gradients of loss(y, t, w) with respect to every parameter."""
-    r = bf16_round if bf16 else (lambda a: a)
     w = np.ones(y.shape[0]) if w is None else np.asarray(w, dtype=np.float64)
-    g = {}
     dy = 2.0 * w[:, None] * (y - t) / np.sum(w)
+    return backprop(p, cache, dy, layers, bf16)
+
+
+def backprop(p, cache, dy, layers, bf16=False):
+    """Parameter gradients of a loss whose gradient with respect to the
+    network output is dy."""
+    r = bf16_round if bf16 else (lambda a: a)
+    g = {}
     hL = cache[f"h{layers}"]
     g["W_out"] = r(dy).T @ r(hL)
     g["b_out"] = dy.sum(0)
@@ -124,14 +130,9 @@ def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 
 # ---------------------------------------------------------------------------
-# Mode profiles <-> rows (the preconditioner's input and output maps)
+# The preconditioner built from the network: per-mode low-rank corrections
 
 NCOND = 32
-
-
-def dims(N):
-    p6 = (6 * N + 31) // 32 * 32
-    return p6 + NCOND, p6
 
 
 def cond_features(mi, k, mp, alpha):
@@ -149,61 +150,107 @@ def cond_features(mi, k, mp, alpha):
     return np.array(f)
 
 
-def pack(y, mp, alpha, z=None):
-    """Rows of the modes of one vector field y [3][M][2K-1][N] (complex):
-    returns X [M(2K-1)][din], T (targets from z, or None), weights s^2 and
-    (s, e) per row.  Row of mode (m, k): yhat = conj(e) y / s with s the RMS
-    of the profile and e the phase of its plain sum; target conj(e) z / s + yhat."""
-    _, M, nk, N = y.shape
-    K = (nk + 1) // 2
-    din, p6 = dims(N)
-    rows = M * nk
-    X = np.zeros((rows, din))
-    T = np.zeros((rows, p6)) if z is not None else None
-    S = np.zeros(rows)
-    E = np.ones(rows, dtype=complex)
-    for mi in range(M):
-        for kk in range(nk):
-            q = mi * nk + kk
-            prof = y[:, mi, kk, :].reshape(-1)
-            s = np.sqrt(np.sum(np.abs(prof) ** 2) / (3 * N))
-            rho = np.sum(prof)
-            e = rho / abs(rho) if abs(rho) > 1e-8 * 3 * N * s else 1.0 + 0j
-            S[q], E[q] = s, e
-            yh = np.conj(e) * prof / s if s > 0 else np.zeros_like(prof)
-            X[q, 0:6 * N:2], X[q, 1:6 * N:2] = yh.real, yh.imag
-            X[q, p6:] = cond_features(mi, kk - (K - 1), mp, alpha)
-            if z is not None:
-                zp = z[:, mi, kk, :].reshape(-1)
-                th = (np.conj(e) * zp / s if s > 0 else np.zeros_like(zp)) + yh
-                T[q, 0:6 * N:2], T[q, 1:6 * N:2] = th.real, th.imag
-    return X, T, S ** 2, S, E
+def feature_rows(M, K, mp, alpha):
+    """Network input: one row per mode (m, k), m-major, k = -(K-1)..K-1."""
+    nk = 2 * K - 1
+    return np.array([cond_features(mi, kk - (K - 1), mp, alpha) for mi in range(M) for kk in range(nk)])
 
 
-def unpack(F, y, S, E):
-    """z_mk = s e f - y_mk, f the output row read as a complex profile;
-    z(0, k<0) = conj z(0, -k)."""
-    _, M, nk, N = y.shape
+def factor_dims(N, rank):
+    return (12 * N * rank + 31) // 32 * 32
+
+
+def factors(F, N, rank):
+    """Output rows [modes][>= 12 N rank] -> A, B [modes][3N][rank] complex:
+    A[e][j] at 2(e rank + j) (+1 imaginary), B the same from 6 N rank on."""
+    n = 3 * N * rank
+    A = F[:, 0:2 * n:2] + 1j * F[:, 1:2 * n:2]
+    B = F[:, 2 * n:4 * n:2] + 1j * F[:, 2 * n + 1:4 * n:2]
+    return A.reshape(-1, 3 * N, rank), B.reshape(-1, 3 * N, rank)
+
+
+def profiles(v):
+    """[3][M][nk][N] -> [M nk][3N] (mode rows, component-major profile)."""
+    _, M, nk, N = v.shape
+    return np.transpose(v, (1, 2, 0, 3)).reshape(M * nk, 3 * N)
+
+
+def lowrank_apply(F, v, rank):
+    """z_mk = -v_mk + A_mk (B_mk^H v_mk) for every mode; (m = 0, k < 0) is the
+    conjugate of (0, -k) and (0, 0) keeps its real part."""
+    _, M, nk, N = v.shape
     K = (nk + 1) // 2
-    z = np.zeros_like(y)
-    for mi in range(M):
-        for kk in range(nk):
-            q = mi * nk + kk
-            f = (F[q, 0:6 * N:2] + 1j * F[q, 1:6 * N:2]).reshape(3, N)
-            z[:, mi, kk, :] = S[q] * E[q] * f - y[:, mi, kk, :]
+    A, B = factors(F, N, rank)
+    y = profiles(v)
+    c = np.einsum("qej,qe->qj", np.conj(B), y)
+    z = -y + np.einsum("qej,qj->qe", A, c)
+    z = np.transpose(z.reshape(M, nk, 3, N), (2, 0, 1, 3)).copy()
     for kk in range(K - 1):
-        z[:, 0, kk, :] = np.conj(z[:, 0, 2 * (K - 1) - kk, :])
+        z[:, 0, kk] = np.conj(z[:, 0, 2 * (K - 1) - kk])
+    z[:, 0, K - 1] = z[:, 0, K - 1].real
     return z
 
 
-def precondition(p, layers, y, mp, alpha, bf16=False):
-    """Preconditioner applied to a vector field y: pack, network, unpack.
-    bf16=True rounds the GEMM operands as the device does; the FP32 rows the
-    device feeds its first product are emulated by rounding through float32."""
-    X, _, _, S, E = pack(y, mp, alpha)
-    if bf16:
-        X = X.astype(np.float32).astype(np.float64)
+def head(F, pairs, rank):
+    """Loss of the Jacobian model J_q ~ -I + U V^H (U, V = factors(F)) on a
+    batch of (z, J z) pairs [b][2][3][M][nk][N], and its gradient with
+    respect to the output rows.  Per mode and pair: s = RMS of the z profile
+    (pairs with s = 0 skip), xhat = z/s, that = (J z)/s,
+    r = -xhat + U (V^H xhat) - that; loss = sum |r|^2 / (b M nk); the gradient
+    of a real function of complex factors (Re + i Im parts) is
+    dU = 2 r c^H with c = V^H xhat, dV = 2 xhat (U^H r)^H per term."""
+    b = pairs.shape[0]
+    _, M, nk, N = pairs.shape[2:]
+    U, V = factors(F, N, rank)
+    dU, dV = np.zeros_like(U), np.zeros_like(V)
+    total = 0.0
+    for p in range(b):
+        x, y = profiles(pairs[p, 0]), profiles(pairs[p, 1])
+        s = np.sqrt(np.mean(np.abs(x) ** 2, axis=1))
+        live = s > 0
+        inv = np.where(live, 1.0 / np.where(live, s, 1.0), 0.0)
+        xh, th = x * inv[:, None], y * inv[:, None]
+        c = np.einsum("qej,qe->qj", np.conj(V), xh)
+        r = -xh + np.einsum("qej,qj->qe", U, c) - th
+        total += np.sum(np.abs(r) ** 2)
+        g = np.einsum("qej,qe->qj", np.conj(U), r)
+        dU += 2 * np.einsum("qe,qj->qej", r, np.conj(c))
+        dV += 2 * np.einsum("qe,qj->qej", xh, np.conj(g))
+    scale = 1.0 / (b * M * nk)
+    dF = np.zeros_like(F)
+    n = 3 * N * rank
+    dU, dV = dU.reshape(-1, n) * scale, dV.reshape(-1, n) * scale
+    dF[:, 0:2 * n:2], dF[:, 1:2 * n:2] = dU.real, dU.imag
+    dF[:, 2 * n:4 * n:2], dF[:, 2 * n + 1:4 * n:2] = dV.real, dV.imag
+    return total * scale, dF
+
+
+def woodbury(F, N, rank):
+    """Preconditioner rows (A, B) from Jacobian-model rows (U, V): the exact
+    inverse of -I + U V^H is -(I + U G^{-1} V^H), G = I - V^H U, so A = -U G^{-1},
+    B = V (a singular G gives A = 0).  Same row layout as F."""
+    U, V = factors(F, N, rank)
+    out = np.zeros_like(F)
+    n = 3 * N * rank
+    for q in range(F.shape[0]):
+        G = np.eye(rank) - np.conj(V[q]).T @ U[q]
+        try:
+            A = -U[q] @ np.linalg.inv(G)
+        except np.linalg.LinAlgError:
+            A = np.zeros_like(U[q])
+        a = A.reshape(-1)
+        out[q, 0:2 * n:2], out[q, 1:2 * n:2] = a.real, a.imag
+    out[:, 2 * n:4 * n] = F[:, 2 * n:4 * n]
+    return out
+
+
+def precondition(p, layers, v, mp, alpha, rank, bf16=False):
+    """The network's preconditioner applied to v: Jacobian-model rows from the
+    mode features, Woodbury inverse, then the low-rank map (bf16=True rounds
+    as the device does; the device keeps the rows in FP32)."""
+    _, M, nk, N = v.shape
+    X = feature_rows(M, (nk + 1) // 2, mp, alpha)
     F, _ = forward(p, X, layers, bf16=bf16)
     if bf16:
         F = F.astype(np.float32).astype(np.float64)
-    return unpack(F, y, S, E)
+    return lowrank_apply(woodbury(F, N, rank), v, rank)

@@ -22,10 +22,10 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_get_nodes", "opf_set_state", "opf_get_state", "opf_step", "opf_nonlinear",
            "opf_vorticity", "opf_radial_solve", "opf_newton_residual", "opf_profile_steps",
            "opf_vec_dot", "opf_vec_axpby", "opf_nk_workspace_size", "opf_nk_solve",
-           "opf_diagnostics", "opf_mlp_default_config", "opf_mlp_workspace_size", "opf_mlp_create",
+           "opf_diagnostics", "opf_probe_pairs", "opf_mlp_default_config", "opf_mlp_workspace_size", "opf_mlp_create",
            "opf_mlp_destroy", "opf_mlp_dims", "opf_mlp_set_params", "opf_mlp_get_params",
-           "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pack_pairs",
-           "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
+           "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pair_gradient",
+           "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error",
            "opf_status_string", "opf_last_error"]
@@ -62,8 +62,8 @@ class opf_nk_report(ctypes.Structure):
 
 
 class opf_mlp_config(ctypes.Structure):
-    _fields_ = [("width", ctypes.c_int32), ("layers", ctypes.c_int32), ("max_rows", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+    _fields_ = [("width", ctypes.c_int32), ("layers", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("max_rows", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
 
 
@@ -106,6 +106,7 @@ def load_library(path=LIB_PATH):
         "opf_nk_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], i32),
         "opf_nk_solve": ([vp, vp, dbl, dbl, P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
+        "opf_probe_pairs": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp, vp], i32),
         "opf_mlp_default_config": ([P(opf_mlp_config)], i32),
         "opf_mlp_workspace_size": ([vp, P(opf_mlp_config), P(ctypes.c_size_t)], i32),
         "opf_mlp_create": ([vp, P(opf_mlp_config), vp, ctypes.c_size_t, P(vp)], i32),
@@ -116,7 +117,9 @@ def load_library(path=LIB_PATH):
         "opf_mlp_forward": ([vp, vp, i32, vp], i32),
         "opf_mlp_gradient": ([vp, vp, vp, vp, i32, P(ctypes.c_double), vp], i32),
         "opf_mlp_train": ([vp, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp], i32),
-        "opf_mlp_pack_pairs": ([vp, vp, vp, i32, vp, vp, vp], i32),
+        "opf_mlp_pair_gradient": ([vp, vp, vp, i32, vp, i32, P(ctypes.c_double), vp], i32),
+        "opf_mlp_train_pairs": ([vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp], i32),
+        "opf_mlp_factors": ([vp, vp, ctypes.c_int64, P(ctypes.c_int32)], i32),
         "opf_precondition": ([vp, vp, vp, vp], i32),
         "opf_mlp_last_error": ([vp], ctypes.c_char_p),
         "opf_ensemble_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
@@ -331,6 +334,17 @@ class Solver:
                    "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
                    "recorded": rep.recorded, "precond_applies": rep.precond_applies}
 
+    def probe_pairs(self, x, T, shift, n, seed=1, fd_eps=1e-7):
+        """n Jacobian probes (z, J z) of the travelling-wave residual at x:
+        complex128 device tensor [n, 2, 3, M, 2K-1, N]."""
+        x = self._dev(x, self.shape)
+        pairs = self.torch.empty((int(n), 2) + tuple(self.shape), dtype=self.torch.complex128, device=self.device)
+        work = self.torch.empty((3,) + tuple(self.shape), dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_probe_pairs(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
+                                             int(n), int(seed), float(fd_eps), ctypes.c_void_p(pairs.data_ptr()),
+                                             ctypes.c_void_p(work.data_ptr())))
+        return pairs
+
     def diagnostics(self):
         d = opf_diag()
         self._check(self.lib.opf_diagnostics(self.ctx, ctypes.byref(d)))
@@ -410,25 +424,25 @@ class Ensemble:
 
 
 class Mlp:
-    """Learned preconditioner network of a Solver's grid (see opf.h): a
-    residual MLP on the matrix cores, trained with Adam on rows packed from
-    (v, J v) pairs, applied by Solver.nk_solve(precond=...)."""
+    """Learned preconditioner of a Solver's grid (see opf.h): a residual MLP
+    on the matrix cores turns each mode's features into the factors of a
+    rank-R correction of -I; trained with Adam on recorded (z, J z) pairs and
+    applied by Solver.nk_solve(precond=...)."""
 
-    def __init__(self, solver, width=256, layers=4, max_rows=None, seed=1, lr=1e-3, beta1=0.9, beta2=0.999,
-                 adam_eps=1e-8):
+    def __init__(self, solver, width=256, layers=4, rank=8, max_rows=0, seed=1, lr=1e-3, beta1=0.9,
+                 beta2=0.999, adam_eps=1e-8):
         import torch
         self.torch = torch
         self.solver = solver  # the context must outlive the network
         self.lib = solver.lib
-        rows = solver.M * (2 * solver.K - 1)
-        self.mode_rows = rows
+        self.mode_rows = solver.M * (2 * solver.K - 1)
         cfg = opf_mlp_config()
         solver._check(self.lib.opf_mlp_default_config(ctypes.byref(cfg)))
-        cfg.width, cfg.layers, cfg.seed = int(width), int(layers), int(seed)
-        cfg.max_rows = int(max_rows if max_rows is not None else rows)
+        cfg.width, cfg.layers, cfg.rank, cfg.seed = int(width), int(layers), int(rank), int(seed)
+        cfg.max_rows = int(max_rows)
         cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps = lr, beta1, beta2, adam_eps
         self.cfg = cfg
-        self.layers = int(layers)
+        self.layers, self.rank, self.width = int(layers), int(rank), int(width)
         nbytes = ctypes.c_size_t()
         solver._check(self.lib.opf_mlp_workspace_size(solver.ctx, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=solver.device)
@@ -455,6 +469,13 @@ class Mlp:
         if t.dim() != 2 or t.shape[1] != width:
             raise OpfError(OPF_E_INVALID, f"expected rows of width {width}, got {tuple(t.shape)}")
         return t
+
+    def _pairs(self, pairs):
+        s = self.solver
+        pairs = s._dev(pairs).contiguous()
+        if tuple(pairs.shape[1:]) != (2,) + tuple(s.shape):
+            raise OpfError(OPF_E_INVALID, f"pairs must be [n, 2, {s.shape}], got {tuple(pairs.shape)}")
+        return pairs
 
     def set_params(self, flat):
         import numpy as np
@@ -495,27 +516,46 @@ class Mlp:
         if w is not None:
             w = self.torch.as_tensor(w).to(device=x.device, dtype=self.torch.float32).contiguous()
             wp = w.data_ptr()
-        batch = int(batch if batch is not None else self.mode_rows)
+        batch = int(batch if batch is not None else x.shape[0])
         losses = np.zeros(max(epochs, 1), dtype=np.float32)
         self._check(self.lib.opf_mlp_train(self.handle, ctypes.c_void_p(x.data_ptr()),
                                            ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(wp), x.shape[0],
                                            batch, int(epochs), int(seed), ctypes.c_void_p(losses.ctypes.data)))
         return losses[:epochs]
 
-    def pack_pairs(self, pairs):
-        """Rows (x, t, w) of recorded pairs [n, 2, 3, M, 2K-1, N] (complex128)."""
-        torch = self.torch
+    def pair_gradient(self, pairs, idx):
+        """Pair loss of pairs[idx] and its parameter gradient (no update)."""
+        import numpy as np
         s = self.solver
-        pairs = s._dev(pairs).contiguous()
-        assert tuple(pairs.shape[1:]) == (2,) + tuple(s.shape)
-        n = pairs.shape[0] * self.mode_rows
-        x = torch.empty((n, self.din), dtype=torch.float32, device=s.device)
-        t = torch.empty((n, self.dout), dtype=torch.float32, device=s.device)
-        w = torch.empty((n,), dtype=torch.float32, device=s.device)
-        s._check(self.lib.opf_mlp_pack_pairs(s.ctx, self.handle, ctypes.c_void_p(pairs.data_ptr()),
-                                             pairs.shape[0], ctypes.c_void_p(x.data_ptr()),
-                                             ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(w.data_ptr())))
-        return x, t, w
+        pairs = self._pairs(pairs)
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        s._check(self.lib.opf_mlp_pair_gradient(s.ctx, self.handle, ctypes.c_void_p(pairs.data_ptr()),
+                                                pairs.shape[0], ctypes.c_void_p(idx.ctypes.data), idx.size,
+                                                ctypes.byref(loss), ctypes.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def train_pairs(self, pairs, batch=16, steps=1000, seed=1):
+        """Adam on recorded (z, J z) pairs [n, 2, 3, M, 2K-1, N]; returns the
+        per-step losses."""
+        import numpy as np
+        s = self.solver
+        pairs = self._pairs(pairs)
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        s._check(self.lib.opf_mlp_train_pairs(s.ctx, self.handle, ctypes.c_void_p(pairs.data_ptr()),
+                                              pairs.shape[0], int(batch), int(steps), int(seed),
+                                              ctypes.c_void_p(losses.ctypes.data)))
+        return losses[:steps]
+
+    def factors(self):
+        """Preconditioner factor rows (A, B) and the count of modes left at -I."""
+        import numpy as np
+        f = np.zeros((self.mode_rows, self.dout), dtype=np.float32)
+        bad = ctypes.c_int32()
+        self._check(self.lib.opf_mlp_factors(self.handle, ctypes.c_void_p(f.ctypes.data), f.size,
+                                             ctypes.byref(bad)))
+        return f, bad.value
 
     def precondition(self, v):
         s = self.solver

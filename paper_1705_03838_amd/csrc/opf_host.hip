@@ -401,6 +401,42 @@ __global__ void k_axpby(double a, const double* __restrict__ x, double b, double
     if (i < n) y[i] = a * x[i] + b * y[i];
 }
 
+// Independent unit normals in every real and imaginary part of a field:
+// entry i takes two uniforms from SplitMix64 (Steele, Lea & Flood 2014) at
+// counters 2i, 2i+1 of the seed's stream and turns them into a pair of
+// normals by the Box-Muller transform.
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__global__ void k_noise(double* __restrict__ z, size_t n, uint64_t seed) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t base = seed + 0x9E3779B97F4A7C15ull * (2 * (uint64_t)i + 1);
+    const double u1 = ((double)(mix64(base) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = (double)(mix64(base + 0x9E3779B97F4A7C15ull) >> 11) * (1.0 / 9007199254740992.0);
+    const double rad = sqrt(-2.0 * log(u1)), th = 2.0 * M_PI * u2;
+    z[2 * i] = rad * cos(th);
+    z[2 * i + 1] = rad * sin(th);
+}
+
+// Spectrum of a real field at m = 0: A(0, -k) = conj A(0, k), A(0, 0) real.
+__global__ void k_realfield(double* __restrict__ z, int N, int M, int nk, int K) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * K * N) return;
+    const int c = i / (K * N), kp = (i / N) % K, n = i % N;  // kp = k >= 0
+    const size_t S = (size_t)M * nk * N;
+    const size_t pos = c * S + (size_t)(K - 1 + kp) * N + n;
+    if (kp == 0) {
+        z[2 * pos + 1] = 0.0;
+        return;
+    }
+    const size_t neg = c * S + (size_t)(K - 1 - kp) * N + n;
+    z[2 * neg] = z[2 * pos];
+    z[2 * neg + 1] = -z[2 * pos + 1];
+}
+
 hipError_t to_f32(const double* in, float* out, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_convert<float>, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
     return hipGetLastError();
@@ -1207,6 +1243,43 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
 #undef NKCHK
     rep->newton_iterations = it;
     rep->converged = rep->residual <= o->tol ? 1 : 0;
+    return OPF_OK;
+}
+
+opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n, uint64_t seed,
+                           double fd_eps, void* pairs_dev, void* work_dev) {
+    if (!c || !x_dev || !pairs_dev || !work_dev || n < 1 || !(fd_eps > 0.0)) return OPF_E_INVALID;
+    const size_t total = 3 * field_entries(c);
+    const size_t vb = total * 16;
+    unsigned char* w = static_cast<unsigned char*>(work_dev);
+    void* F0 = w;
+    void* tmp = w + vb;
+    void* F1 = w + 2 * vb;
+    opf_status st = opf_newton_residual(c, x_dev, T, shift, F0, nullptr);
+    if (st != OPF_OK) return st;
+    double xn2 = 0.0;
+    if ((st = opf_vec_dot(c, x_dev, x_dev, &xn2)) != OPF_OK) return st;
+    const double eps = fd_eps * std::max(std::sqrt(xn2), 1.0);
+    unsigned char* out = static_cast<unsigned char*>(pairs_dev);
+    for (int i = 0; i < n; ++i) {
+        double* z = reinterpret_cast<double*>(out + (size_t)i * 2 * vb);
+        void* jz = out + (size_t)i * 2 * vb + vb;
+        hipLaunchKernelGGL(k_noise, dim3((total + 255) / 256), dim3(256), 0, c->stream, z, total,
+                           seed * 0x2545F4914F6CDD1Dull + (uint64_t)i * 0xD1B54A32D192ED03ull);
+        hipLaunchKernelGGL(k_realfield, dim3((3 * c->p.K * c->p.N + 255) / 256), dim3(256), 0, c->stream, z, c->p.N,
+                           c->p.M, c->nk, c->p.K);
+        HIPCHK(c, hipGetLastError());
+        double zn2 = 0.0;
+        if ((st = opf_vec_dot(c, z, z, &zn2)) != OPF_OK) return st;
+        if (!(zn2 > 0.0)) return OPF_E_NUMERIC;
+        if ((st = opf_vec_axpby(c, 0.0, z, 1.0 / std::sqrt(zn2), z)) != OPF_OK) return st;
+        if ((st = opf_vec_axpby(c, 1.0, x_dev, 0.0, tmp)) != OPF_OK) return st;
+        if ((st = opf_vec_axpby(c, eps, z, 1.0, tmp)) != OPF_OK) return st;
+        if ((st = opf_newton_residual(c, tmp, T, shift, F1, nullptr)) != OPF_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(jz, F1, vb, hipMemcpyDeviceToDevice, c->stream));
+        if ((st = opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, jz)) != OPF_OK) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return OPF_OK;
 }
 

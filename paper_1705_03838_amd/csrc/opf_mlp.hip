@@ -1,7 +1,9 @@
 // Learned preconditioner of the Newton-Krylov solver: a residual MLP whose
 // dense layers run on the matrix cores (bfloat16 operands, FP32
-// accumulation), its backward pass, Adam, and the packing of Fourier-mode
-// radial profiles into network rows and back.
+// accumulation), its backward pass and Adam; the network turns the features
+// of each Fourier mode into the factors of a rank-R correction of -I, which
+// k_lowrank_apply applies to the mode's radial profile, and k_head is the
+// loss of that map on recorded (z, J z) pairs.
 //
 // Network (weights [out][in] row-major, L residual layers of width H):
 //   h_0 = W_in x + b_in;  h_l = h_{l-1} + relu(W_l h_{l-1} + b_l);  y = W_out h_L + b_out.
@@ -42,8 +44,6 @@ __host__ __device__ inline bf16_t f2bf(float f) {
     return (bf16_t)(u >> 16);
 }
 
-__device__ inline uint32_t pack2(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
-
 enum { EPI_PLAIN = 0, EPI_RELU_RES = 1, EPI_ADD = 2 };
 
 // What the GEMM epilogue does with v = acc (+ bias[col]):
@@ -74,8 +74,7 @@ struct Epi {
 // row l%32 of the B slice, elements 8*(l/32)..+7 (the operand layout of the
 // instruction); accumulator entry i of lane l is C[8(i/4) + 4(l/32) + i%4][l%32].
 // Requires rows, cols multiples of 32, K of 16, lda, ldb multiples of 8.
-template <bool AF32>
-__global__ __launch_bounds__(256) void k_gemm(const void* __restrict__ A, int lda, const bf16_t* __restrict__ B,
+__global__ __launch_bounds__(256) void k_gemm(const bf16_t* __restrict__ A, int lda, const bf16_t* __restrict__ B,
                                               int ldb, int K, Epi e) {
     __shared__ float red[4][16][64];
     const int lane = threadIdx.x & 63;
@@ -83,23 +82,10 @@ __global__ __launch_bounds__(256) void k_gemm(const void* __restrict__ A, int ld
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int rr = lane & 31, kq = (lane >> 5) * 8;
     f32x16 acc = {};
+    const bf16_t* ap = A + (size_t)(m0 + rr) * lda + kq;
     const bf16_t* bp = B + (size_t)(n0 + rr) * ldb + kq;
     for (int k0 = wv * 16; k0 < K; k0 += 64) {
-        bf16x8 a;
-        if constexpr (AF32) {
-            const float* ap = static_cast<const float*>(A) + (size_t)(m0 + rr) * lda + kq + k0;
-            const float4 x0 = *reinterpret_cast<const float4*>(ap);
-            const float4 x1 = *reinterpret_cast<const float4*>(ap + 4);
-            u32x4 p;
-            p[0] = pack2(x0.x, x0.y);
-            p[1] = pack2(x0.z, x0.w);
-            p[2] = pack2(x1.x, x1.y);
-            p[3] = pack2(x1.z, x1.w);
-            a = __builtin_bit_cast(bf16x8, p);
-        } else {
-            const bf16_t* ap = static_cast<const bf16_t*>(A) + (size_t)(m0 + rr) * lda + kq + k0;
-            a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap));
-        }
+        const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + k0));
         const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bp + k0));
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
@@ -271,8 +257,10 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Mode profiles <-> network rows.
+// The preconditioner: per-mode low-rank corrections generated by the network.
 namespace {
+
+constexpr int RMAX = 32;  // largest rank
 
 // Conditioning features of mode (m, k): mu = mp m (azimuthal wavenumber),
 // kappa = alpha k (axial wavenumber).
@@ -294,109 +282,329 @@ __device__ inline float cond_feature(int j, int mi, int k, int mp, double alpha)
     return (k > 7 || k < -7) ? 1.0f : 0.0f;
 }
 
-struct PackArgs {
-    const double* y;  // profiles to precondition: pair p at y + p * pstride (external layout)
-    const double* z;  // targets (training) or null
-    long pstride;     // doubles between consecutive pairs
-    int N, M, nk, K, mp;
-    double alpha;
-    int p6, din;
-    int rows;    // pairs * M * nk
-    float* X;    // [rows][din]
-    float* T;    // [rows][p6] or null
-    float* om;   // [rows] squared RMS s^2, or null
-    double* sc;  // [rows][3] (s, Re e, Im e), or null
-};
-
-// One wave per row (pair p, mode q = mi * nk + kk).  With y_c(n) the mode's
-// profile (c = r, theta, z): s = sqrt(sum |y|^2 / 3N), rho = sum y,
-// e = rho / |rho| (1 when |rho| <= 1e-8 3N s), yhat = conj(e) y / s;
-// row = [Re, Im of yhat_c(n) at 2(cN + n)], zeros to p6, then the features.
-// Target row: conj(e) z / s + yhat.  Rows with s = 0 have zero profile parts.
-__global__ __launch_bounds__(256) void k_pack(PackArgs a) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= a.rows) return;
-    const int mnk = a.M * a.nk;
-    const int p = row / mnk, q = row % mnk;
-    const int mi = q / a.nk, kk = q % a.nk;
-    const long S = (long)mnk * a.N;
-    const double* yb = a.y + (long)p * a.pstride;
-    const double* zb = a.z ? a.z + (long)p * a.pstride : nullptr;
-    const int n3 = 3 * a.N;
-    double s2 = 0.0, rr = 0.0, ri = 0.0;
-    for (int e = lane; e < n3; e += 64) {
-        const int c = e / a.N, n = e % a.N;
-        const long idx = c * S + (long)q * a.N + n;
-        const double re = yb[2 * idx], im = yb[2 * idx + 1];
-        s2 += re * re + im * im;
-        rr += re;
-        ri += im;
-    }
-    s2 = wave_sum(s2);
-    rr = wave_sum(rr);
-    ri = wave_sum(ri);
-    const double s = sqrt(s2 / n3);
-    const double rho = sqrt(rr * rr + ri * ri);
-    double er = 1.0, ei = 0.0;
-    if (rho > 1e-8 * n3 * s) {
-        er = rr / rho;
-        ei = ri / rho;
-    }
-    const double inv = s > 0.0 ? 1.0 / s : 0.0;
-    float* xr = a.X + (long)row * a.din;
-    float* tr = a.T ? a.T + (long)row * a.p6 : nullptr;
-    for (int e = lane; e < n3; e += 64) {
-        const int c = e / a.N, n = e % a.N;
-        const long idx = c * S + (long)q * a.N + n;
-        const double re = yb[2 * idx], im = yb[2 * idx + 1];
-        const double hr = (er * re + ei * im) * inv, hi = (er * im - ei * re) * inv;
-        xr[2 * e] = (float)hr;
-        xr[2 * e + 1] = (float)hi;
-        if (tr) {
-            const double zr = zb[2 * idx], zi = zb[2 * idx + 1];
-            tr[2 * e] = (float)((er * zr + ei * zi) * inv + hr);
-            tr[2 * e + 1] = (float)((er * zi - ei * zr) * inv + hi);
-        }
-    }
-    for (int j = 2 * n3 + lane; j < a.p6; j += 64) {
-        xr[j] = 0.0f;
-        if (tr) tr[j] = 0.0f;
-    }
-    for (int j = lane; j < a.din - a.p6; j += 64)
-        xr[a.p6 + j] = j < NCOND ? cond_feature(j, mi, kk - (a.K - 1), a.mp, a.alpha) : 0.0f;
-    if (lane == 0) {
-        if (a.om) a.om[row] = (float)(s * s);
-        if (a.sc) {
-            a.sc[3 * row] = s;
-            a.sc[3 * row + 1] = er;
-            a.sc[3 * row + 2] = ei;
-        }
-    }
+// One row of NCOND features per mode q = m (2K-1) + k + K-1; rows past M(2K-1)
+// are zero.
+__global__ void k_features(float* __restrict__ fx, int rows, int rp, int nk, int K, int mp, double alpha) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= rp * NCOND) return;
+    const int q = i / NCOND, j = i % NCOND;
+    fx[i] = q < rows ? cond_feature(j, q / nk, q % nk - (K - 1), mp, alpha) : 0.0f;
 }
 
-// z = s e f - y per mode, f the network output read as a complex profile;
-// (m = 0, k < 0) is the conjugate of (0, -k).
-__global__ void k_unpack(const float* __restrict__ F, int dout, const double* __restrict__ sc,
-                         const double* __restrict__ y, double* __restrict__ z, int N, int M, int nk, int K) {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    const long S = (long)M * nk * N;
-    if (i >= 3 * S) return;
-    const int c = (int)(i / S);
-    const long rem = i % S;
-    const int n = (int)(rem % N);
-    const int q0 = (int)(rem / N);
+// Output row of mode q: A[e][j] at 2(e R + j) (+1 imaginary), e < 3N, j < R;
+// B at the same places from offset 6 N R on.
+
+// z_q = -v_q + A_q (B_q^H v_q) with v_q the profile of mode q (e = c N + n);
+// (m = 0, k < 0) is the conjugate of (0, -k), (0, 0) keeps its real part.
+// One wave per output mode; the waves of a workgroup share nothing.
+__global__ __launch_bounds__(256) void k_lowrank_apply(const float* __restrict__ fac, int dout, int rank,
+                                                       const double* __restrict__ v, double* __restrict__ z, int N,
+                                                       int M, int nk, int K) {
+    __shared__ double cs[4][2 * RMAX];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q0 = blockIdx.x * 4 + w;
+    if (q0 >= M * nk) return;
     const int mi = q0 / nk, kk = q0 % nk;
     const bool mir = mi == 0 && kk < K - 1;
     const int q = mir ? 2 * (K - 1) - kk : q0;
-    const double s = sc[3 * q], er = sc[3 * q + 1], ei = sc[3 * q + 2];
-    const long src = c * S + (long)q * N + n;
-    const float* f = F + (long)q * dout + 2 * (c * N + n);
-    const double fr = f[0], fi = f[1];
-    const double wr = s * (er * fr - ei * fi) - y[2 * src];
-    const double wi = s * (er * fi + ei * fr) - y[2 * src + 1];
-    z[2 * i] = wr;
-    z[2 * i + 1] = mir ? -wi : wi;
+    const long S = (long)M * nk * N;
+    const int n3 = 3 * N;
+    const float* A = fac + (long)q * dout;
+    const float* B = A + 6 * N * rank;
+    double yr[3], yi[3];
+    for (int t = 0; t < 3; ++t) {
+        const int e = lane + 64 * t;
+        yr[t] = yi[t] = 0.0;
+        if (e < n3) {
+            const long idx = (e / N) * S + (long)q * N + e % N;
+            yr[t] = v[2 * idx];
+            yi[t] = v[2 * idx + 1];
+        }
+    }
+    for (int j = 0; j < rank; ++j) {  // c_j = sum_e conj(B_ej) y_e
+        double cr = 0.0, ci = 0.0;
+        for (int t = 0; t < 3; ++t) {
+            const int e = lane + 64 * t;
+            if (e < n3) {
+                const double br = B[2 * (e * rank + j)], bi = B[2 * (e * rank + j) + 1];
+                cr += br * yr[t] + bi * yi[t];
+                ci += br * yi[t] - bi * yr[t];
+            }
+        }
+        // every lane holds the same sum and stores it: each lane reads back its own store
+        cs[w][2 * j] = wave_sum(cr);
+        cs[w][2 * j + 1] = wave_sum(ci);
+    }
+    for (int t = 0; t < 3; ++t) {
+        const int e = lane + 64 * t;
+        if (e >= n3) continue;
+        double zr = -yr[t], zi = -yi[t];
+        for (int j = 0; j < rank; ++j) {
+            const double ar = A[2 * (e * rank + j)], ai = A[2 * (e * rank + j) + 1];
+            const double cr = cs[w][2 * j], ci = cs[w][2 * j + 1];
+            zr += ar * cr - ai * ci;
+            zi += ar * ci + ai * cr;
+        }
+        if (mir) zi = -zi;
+        if (mi == 0 && kk == K - 1) zi = 0.0;
+        const long out = (e / N) * S + (long)q0 * N + e % N;
+        z[2 * out] = zr;
+        z[2 * out + 1] = zi;
+    }
+}
+
+struct HeadArgs {
+    const double* pairs;  // [npairs][2][3][M][2K-1][N] complex: (z, J z)
+    long vec;             // doubles per vector
+    const int* idx;       // pair indices of the batch
+    int batch;
+    int N, M, nk, rank, dout;
+    int rows, rp;  // M(2K-1) live rows, rows padded to 32
+    float* Y;      // in: network output rows; out: dLoss/dY
+    bf16_t* dyb;   // [rp][dout]
+    bf16_t* dyt;   // [dout][ldt]
+    int ldt;
+    float* lrow;  // per-row loss
+    float scale;  // 1 / (batch rows)
+};
+
+// Loss head of the training pairs: the network's factors U = A, V = B model
+// the Jacobian on each mode, J_q ~ -I + U V^H.  For mode q and pair p:
+// s = RMS of the z_q profile (pairs with s = 0 skip), xhat = z_q / s,
+// that = (J z)_q / s, c = V^H xhat, r = -xhat + U c - that;
+// loss = scale sum |r|^2, dU = 2 scale sum r c^H, dV = 2 scale sum xhat (U^H r)^H.
+// In the code y is the input profile (xhat) and z the target (that).  One
+// workgroup of one wave per row; the row's factors are staged in LDS and the
+// gradient is accumulated in place of the row in Y (each lane owns its
+// elements e).
+__global__ __launch_bounds__(64) void k_head(HeadArgs a) {
+    extern __shared__ float fl[];  // the row's factors, dout floats
+    __shared__ double cg[4 * RMAX];
+    const int q = blockIdx.x, lane = threadIdx.x;
+    float* yrow = a.Y + (long)q * a.dout;
+    const int n3 = 3 * a.N;
+    const int nf = 12 * a.N * a.rank;
+    if (q >= a.rows) {  // padding rows: zero gradient
+        for (int j = lane; j < a.dout; j += 64) {
+            yrow[j] = 0.0f;
+            a.dyb[(long)q * a.dout + j] = 0;
+            a.dyt[(long)j * a.ldt + q] = 0;
+        }
+        if (lane == 0) a.lrow[q] = 0.0f;
+        return;
+    }
+    for (int j = lane; j < a.dout; j += 64) {
+        fl[j] = yrow[j];
+        yrow[j] = 0.0f;
+    }
+    __syncthreads();
+    const float* A = fl;
+    const float* B = fl + nf / 2;
+    float* dA = yrow;
+    float* dB = yrow + nf / 2;
+    const long S = (long)a.M * a.nk * a.N;
+    const int R = a.rank;
+    double lsum = 0.0;
+    for (int b = 0; b < a.batch; ++b) {
+        const double* yv = a.pairs + (long)a.idx[b] * 2 * a.vec;  // z: the model's input
+        const double* zv = yv + a.vec;                              // J z: its target
+        double yr[3], yi[3], zr[3], zi[3];
+        double s2 = 0.0;
+        for (int t = 0; t < 3; ++t) {
+            const int e = lane + 64 * t;
+            yr[t] = yi[t] = zr[t] = zi[t] = 0.0;
+            if (e < n3) {
+                const long idx = (e / a.N) * S + (long)q * a.N + e % a.N;
+                yr[t] = yv[2 * idx];
+                yi[t] = yv[2 * idx + 1];
+                zr[t] = zv[2 * idx];
+                zi[t] = zv[2 * idx + 1];
+                s2 += yr[t] * yr[t] + yi[t] * yi[t];
+            }
+        }
+        s2 = wave_sum(s2);
+        if (!(s2 > 0.0)) continue;
+        const double inv = 1.0 / sqrt(s2 / n3);
+        for (int t = 0; t < 3; ++t) {
+            yr[t] *= inv;
+            yi[t] *= inv;
+            zr[t] *= inv;
+            zi[t] *= inv;
+        }
+        for (int j = 0; j < R; ++j) {  // c = B^H yhat
+            double cr = 0.0, ci = 0.0;
+            for (int t = 0; t < 3; ++t) {
+                const int e = lane + 64 * t;
+                if (e < n3) {
+                    const double br = B[2 * (e * R + j)], bi = B[2 * (e * R + j) + 1];
+                    cr += br * yr[t] + bi * yi[t];
+                    ci += br * yi[t] - bi * yr[t];
+                }
+            }
+            cg[2 * j] = wave_sum(cr);  // same value in every lane; each reads its own store
+            cg[2 * j + 1] = wave_sum(ci);
+        }
+        double rr[3], ri[3];
+        double l = 0.0;
+        for (int t = 0; t < 3; ++t) {  // r = -yhat + A c - zhat
+            const int e = lane + 64 * t;
+            rr[t] = ri[t] = 0.0;
+            if (e >= n3) continue;
+            double pr = -yr[t] - zr[t], pi = -yi[t] - zi[t];
+            for (int j = 0; j < R; ++j) {
+                const double ar = A[2 * (e * R + j)], ai = A[2 * (e * R + j) + 1];
+                pr += ar * cg[2 * j] - ai * cg[2 * j + 1];
+                pi += ar * cg[2 * j + 1] + ai * cg[2 * j];
+            }
+            rr[t] = pr;
+            ri[t] = pi;
+            l += pr * pr + pi * pi;
+        }
+        lsum += l;
+        for (int j = 0; j < R; ++j) {  // g = A^H r
+            double gr = 0.0, gi = 0.0;
+            for (int t = 0; t < 3; ++t) {
+                const int e = lane + 64 * t;
+                if (e < n3) {
+                    const double ar = A[2 * (e * R + j)], ai = A[2 * (e * R + j) + 1];
+                    gr += ar * rr[t] + ai * ri[t];
+                    gi += ar * ri[t] - ai * rr[t];
+                }
+            }
+            cg[2 * RMAX + 2 * j] = wave_sum(gr);
+            cg[2 * RMAX + 2 * j + 1] = wave_sum(gi);
+        }
+        for (int t = 0; t < 3; ++t) {  // dA += 2 r conj(c), dB += 2 yhat conj(g) (own elements only)
+            const int e = lane + 64 * t;
+            if (e >= n3) continue;
+            for (int j = 0; j < R; ++j) {
+                const double cr = cg[2 * j], ci = cg[2 * j + 1];
+                const double gr = cg[2 * RMAX + 2 * j], gi = cg[2 * RMAX + 2 * j + 1];
+                float* pa = dA + 2 * (e * R + j);
+                float* pb = dB + 2 * (e * R + j);
+                pa[0] += (float)(2.0 * (rr[t] * cr + ri[t] * ci));
+                pa[1] += (float)(2.0 * (ri[t] * cr - rr[t] * ci));
+                pb[0] += (float)(2.0 * (yr[t] * gr + yi[t] * gi));
+                pb[1] += (float)(2.0 * (yi[t] * gr - yr[t] * gi));
+            }
+        }
+    }
+    __syncthreads();  // the final pass reads elements other lanes accumulated
+    lsum = wave_sum(lsum);
+    if (lane == 0) a.lrow[q] = (float)lsum;
+    for (int j = lane; j < a.dout; j += 64) {
+        const float g = j < nf ? yrow[j] * a.scale : 0.0f;
+        yrow[j] = g;
+        const bf16_t hb = f2bf(g);
+        a.dyb[(long)q * a.dout + j] = hb;
+        a.dyt[(long)j * a.ldt + q] = hb;
+    }
+}
+
+// Preconditioner factors from the Jacobian model of each mode: with
+// J_q ~ -I + U V^H, J_q^{-1} = -(I + U G^{-1} V^H), G = I_R - V^H U
+// (Sherman-Morrison-Woodbury), so P(v) = -v + A (B^H v) with A = -U G^{-1},
+// B = V.  G is inverted by Gauss-Jordan elimination with partial pivoting in
+// FP64; a mode whose G has a zero pivot gets A = 0 (P = -I there) and
+// singular[q] = 1.  One workgroup of one wave per mode.
+__global__ __launch_bounds__(64) void k_woodbury(const float* __restrict__ uv, float* __restrict__ fac, int dout,
+                                                 int N, int rank, int rows, int* __restrict__ singular) {
+    __shared__ double g[RMAX][2 * RMAX];   // G, then its inverse (complex, row-major)
+    __shared__ double gi[RMAX][2 * RMAX];
+    const int q = blockIdx.x, lane = threadIdx.x;
+    if (q >= rows) return;
+    const int R = rank, n3 = 3 * N, nf = 6 * N * R;
+    const float* U = uv + (long)q * dout;
+    const float* V = U + nf;
+    float* A = fac + (long)q * dout;
+    float* B = A + nf;
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) {  // (V^H U)_ij = sum_e conj(V_ei) U_ej
+            double sr = 0.0, si = 0.0;
+            for (int e = lane; e < n3; e += 64) {
+                const double vr = V[2 * (e * R + i)], vi = V[2 * (e * R + i) + 1];
+                const double ur = U[2 * (e * R + j)], ui = U[2 * (e * R + j) + 1];
+                sr += vr * ur + vi * ui;
+                si += vr * ui - vi * ur;
+            }
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            if (lane == 0) {
+                g[i][2 * j] = (i == j ? 1.0 : 0.0) - sr;
+                g[i][2 * j + 1] = -si;
+            }
+        }
+    __shared__ int bad;
+    if (lane == 0) {  // Gauss-Jordan on [G | I]
+        bad = 0;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < R; ++j) {
+                gi[i][2 * j] = i == j ? 1.0 : 0.0;
+                gi[i][2 * j + 1] = 0.0;
+            }
+        for (int c = 0; c < R && !bad; ++c) {
+            int piv = c;
+            double best = -1.0;
+            for (int i = c; i < R; ++i) {
+                const double m = g[i][2 * c] * g[i][2 * c] + g[i][2 * c + 1] * g[i][2 * c + 1];
+                if (m > best) {
+                    best = m;
+                    piv = i;
+                }
+            }
+            if (!(best > 0.0)) {
+                bad = 1;
+                break;
+            }
+            for (int j = 0; j < 2 * R; ++j) {
+                const double t = g[c][j];
+                g[c][j] = g[piv][j];
+                g[piv][j] = t;
+                const double u = gi[c][j];
+                gi[c][j] = gi[piv][j];
+                gi[piv][j] = u;
+            }
+            const double pr = g[c][2 * c], pi = g[c][2 * c + 1];
+            const double den = pr * pr + pi * pi;
+            const double ir = pr / den, ii = -pi / den;  // 1 / pivot
+            for (int j = 0; j < R; ++j) {
+                double a = g[c][2 * j], b = g[c][2 * j + 1];
+                g[c][2 * j] = a * ir - b * ii;
+                g[c][2 * j + 1] = a * ii + b * ir;
+                a = gi[c][2 * j];
+                b = gi[c][2 * j + 1];
+                gi[c][2 * j] = a * ir - b * ii;
+                gi[c][2 * j + 1] = a * ii + b * ir;
+            }
+            for (int i = 0; i < R; ++i) {
+                if (i == c) continue;
+                const double fr = g[i][2 * c], fi = g[i][2 * c + 1];
+                for (int j = 0; j < R; ++j) {
+                    g[i][2 * j] -= fr * g[c][2 * j] - fi * g[c][2 * j + 1];
+                    g[i][2 * j + 1] -= fr * g[c][2 * j + 1] + fi * g[c][2 * j];
+                    gi[i][2 * j] -= fr * gi[c][2 * j] - fi * gi[c][2 * j + 1];
+                    gi[i][2 * j + 1] -= fr * gi[c][2 * j + 1] + fi * gi[c][2 * j];
+                }
+            }
+        }
+        singular[q] = bad;
+    }
+    __syncthreads();
+    for (int e = lane; e < n3; e += 64)
+        for (int j = 0; j < R; ++j) {  // A = -U G^{-1}, B = V
+            double ar = 0.0, ai = 0.0;
+            if (!bad)
+                for (int i = 0; i < R; ++i) {
+                    const double ur = U[2 * (e * R + i)], ui = U[2 * (e * R + i) + 1];
+                    ar -= ur * gi[i][2 * j] - ui * gi[i][2 * j + 1];
+                    ai -= ur * gi[i][2 * j + 1] + ui * gi[i][2 * j];
+                }
+            A[2 * (e * R + j)] = (float)ar;
+            A[2 * (e * R + j) + 1] = (float)ai;
+            B[2 * (e * R + j)] = V[2 * (e * R + j)];
+            B[2 * (e * R + j) + 1] = V[2 * (e * R + j) + 1];
+        }
+    for (int j = 2 * nf + lane; j < dout; j += 64) A[j] = 0.0f;
 }
 
 uint64_t splitmix64(uint64_t& state) {
@@ -417,12 +625,13 @@ struct opf_mlp {
     hipStream_t s = nullptr;
     int N = 0, M = 0, K = 0, nk = 0, mp = 1;
     double alpha = 1.0;
-    int H = 0, L = 0, p6 = 0, din = 0, dout = 0, R = 0;
+    int H = 0, L = 0, rank = 0, din = 0, dout = 0, R = 0, mode_rows = 0;
     long np = 0;
     Segs segs{};
     long woff[MAXL + 2] = {}, boff[MAXL + 2] = {};
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     long t = 0;
+    bool fac_ok = false;
     float *P = nullptr, *G = nullptr, *Am = nullptr, *Av = nullptr;
     bf16_t *Wb = nullptr, *Wt = nullptr;
     bf16_t *Xb = nullptr, *XT = nullptr;
@@ -430,8 +639,10 @@ struct opf_mlp {
     bf16_t *Hb = nullptr, *HT = nullptr;
     float *Z = nullptr, *Y = nullptr, *dH = nullptr;
     bf16_t *dYb = nullptr, *dYT = nullptr, *dZb0 = nullptr, *dZb1 = nullptr, *dZT = nullptr;
-    float* X = nullptr;
-    double* sc = nullptr;
+    float *fx = nullptr, *fac = nullptr;
+    int* idx = nullptr;
+    int* singular = nullptr;  // [rows] modes whose Woodbury matrix is singular
+    int n_singular = 0;
     float *lrow = nullptr, *wsum = nullptr, *losses = nullptr;
     int loss_cap = 0;
     std::string err;
@@ -444,7 +655,7 @@ struct opf_mlp {
 
 namespace {
 
-constexpr int LOSS_CAP = 1 << 16;
+constexpr int LOSS_CAP = 1 << 16;  // training steps per call, and pair indices per call
 
 #define MCHK(net, call)                                                             \
     do {                                                                            \
@@ -469,9 +680,8 @@ struct Layout {
 
 // dims, parameter segments and buffer layout of a network
 Layout plan(opf_mlp* m) {
-    m->p6 = round32(6 * m->N);
-    m->din = m->p6 + NCOND;
-    m->dout = m->p6;
+    m->din = NCOND;
+    m->dout = round32(12 * m->N * m->rank);
     long o = 0;
     int j = 0;
     auto seg = [&](int rows, int cols, int mat) {
@@ -513,8 +723,10 @@ Layout plan(opf_mlp* m) {
     lay.take(R * H * 2);                           // dZb0
     lay.take(R * H * 2);                           // dZb1
     lay.take(R * H * 2);                           // dZT
-    lay.take(R * m->din * 4);                      // X
-    lay.take(R * 3 * 8);                           // sc
+    lay.take(R * m->din * 4);                      // fx: mode feature rows
+    lay.take(R * m->dout * 4);                     // fac: factor rows in use
+    lay.take((size_t)LOSS_CAP * 4);                // idx: pair indices
+    lay.take(R * 4);                               // singular: per-mode flag of a singular G
     lay.take(R * 4);                               // lrow
     lay.take(256);                                 // wsum
     lay.take((size_t)LOSS_CAP * 4);                // losses
@@ -524,38 +736,32 @@ Layout plan(opf_mlp* m) {
 opf_status check_cfg(const opf_ctx* c, const opf_mlp_config* cfg, std::string* why) {
     if (!c || !cfg) return OPF_E_INVALID;
     const opf_params& p = ctx_params(c);
-    if (cfg->width < 32 || cfg->width > 512 || cfg->width % 32) {
-        if (why) *why = "width must be a multiple of 32 in [32, 512]";
+    auto bad = [&](const char* s) {
+        if (why) *why = s;
         return OPF_E_INVALID;
-    }
-    if (cfg->layers < 1 || cfg->layers > MAXL) {
-        if (why) *why = "layers must be in [1, 8]";
-        return OPF_E_INVALID;
-    }
-    if (cfg->max_rows < p.M * (2 * p.K - 1) || cfg->max_rows > (1 << 20)) {
-        if (why) *why = "max_rows must cover M(2K-1) rows and be <= 2^20";
-        return OPF_E_INVALID;
-    }
+    };
+    if (cfg->width < 32 || cfg->width > 512 || cfg->width % 32) return bad("width must be a multiple of 32 in [32, 512]");
+    if (cfg->layers < 1 || cfg->layers > MAXL) return bad("layers must be in [1, 8]");
+    if (cfg->rank < 1 || cfg->rank > RMAX) return bad("rank must be in [1, 32]");
+    if (12L * p.N * cfg->rank * 4 > 65536) return bad("12 N rank factors of a mode must fit 64 KiB of LDS");
+    if (cfg->max_rows < 0 || cfg->max_rows > (1 << 20)) return bad("max_rows must be in [0, 2^20]");
     if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
-        !(cfg->adam_eps > 0.0f)) {
-        if (why) *why = "bad Adam parameters";
-        return OPF_E_INVALID;
-    }
+        !(cfg->adam_eps > 0.0f))
+        return bad("bad Adam parameters");
     return OPF_OK;
 }
 
-template <bool AF32>
-hipError_t gemm(hipStream_t s, const void* A, int lda, const bf16_t* B, int ldb, int rows, int cols, int K,
+hipError_t gemm(hipStream_t s, const bf16_t* A, int lda, const bf16_t* B, int ldb, int rows, int cols, int K,
                 const Epi& e) {
     if (rows % GT || cols % GT || K % 16 || lda % 8 || ldb % 8 || rows <= 0 || cols <= 0 || K <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm<AF32>, dim3(cols / GT, rows / GT), dim3(256), 0, s, A, lda, B, ldb, K, e);
+    hipLaunchKernelGGL(k_gemm, dim3(cols / GT, rows / GT), dim3(256), 0, s, A, lda, B, ldb, K, e);
     return hipGetLastError();
 }
 
-// Forward pass over rp rows (multiple of 32) of A (FP32 or bfloat16 rows
-// of din).  train: also keep pre-activations and transposed activations.
-hipError_t forward(opf_mlp* m, const void* A, bool af32, int lda, int rp, bool train) {
+// Forward pass over rp rows (multiple of 32) of bfloat16 rows Xb.
+// train: also keep pre-activations and transposed activations.
+hipError_t forward(opf_mlp* m, int rp, bool train) {
     const int H = m->H, L = m->L;
     Epi e{};
     e.bias = m->P + m->boff[0];
@@ -567,8 +773,7 @@ hipError_t forward(opf_mlp* m, const void* A, bool af32, int lda, int rp, bool t
         e.outT = m->ht(0);
         e.ldt = m->R;
     }
-    hipError_t st = af32 ? gemm<true>(m->s, A, lda, m->Wb + m->woff[0], m->din, rp, H, m->din, e)
-                         : gemm<false>(m->s, A, lda, m->Wb + m->woff[0], m->din, rp, H, m->din, e);
+    hipError_t st = gemm(m->s, m->Xb, m->din, m->Wb + m->woff[0], m->din, rp, H, m->din, e);
     if (st != hipSuccess) return st;
     for (int l = 0; l < L; ++l) {
         Epi f{};
@@ -586,32 +791,27 @@ hipError_t forward(opf_mlp* m, const void* A, bool af32, int lda, int rp, bool t
         f.ldo = H;
         f.outb = m->hb(l + 1);
         f.ldb = H;
-        st = gemm<false>(m->s, m->hb(l), H, m->Wb + m->woff[l + 1], H, rp, H, H, f);
+        st = gemm(m->s, m->hb(l), H, m->Wb + m->woff[l + 1], H, rp, H, H, f);
         if (st != hipSuccess) return st;
     }
     Epi g{};
     g.bias = m->P + m->boff[L + 1];
     g.out = m->Y;
     g.ldo = m->dout;
-    return gemm<false>(m->s, m->hb(L), H, m->Wb + m->woff[L + 1], H, rp, m->dout, H, g);
+    return gemm(m->s, m->hb(L), H, m->Wb + m->woff[L + 1], H, rp, m->dout, H, g);
 }
 
-// Loss and parameter gradients after forward(train = true) over rp rows of
-// which the first nrows are live; targets t [nrows][dout], weights om.
-hipError_t backward(opf_mlp* m, const float* t, const float* om, int nrows, int rp, float* loss_slot) {
+// Parameter gradients from dL/dY (FP32 in Y, bfloat16 in dYb / dYT) after
+// forward(train = true) over rp rows.
+hipError_t backprop(opf_mlp* m, int rp) {
     const int H = m->H, L = m->L, R = m->R, dout = m->dout;
     hipStream_t s = m->s;
-    hipLaunchKernelGGL(k_weight_sum, dim3(1), dim3(256), 0, s, om, nrows, m->wsum);
-    hipLaunchKernelGGL(k_loss, dim3(rp / 4), dim3(256), 0, s, m->Y, t, om, m->wsum, nrows, rp, dout, m->dYb,
-                       m->dYT, R, m->lrow);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lrow, nrows, m->wsum, loss_slot);
-    hipError_t st = hipGetLastError();
-    if (st != hipSuccess) return st;
+    hipError_t st;
     {  // output layer: dW = dY^T H_L, db = colsum dY, dH_L = dY W_out
         Epi e{};
         e.out = m->G + m->woff[L + 1];
         e.ldo = H;
-        if ((st = gemm<false>(s, m->dYT, R, m->ht(L), R, dout, H, rp, e)) != hipSuccess) return st;
+        if ((st = gemm(s, m->dYT, R, m->ht(L), R, dout, H, rp, e)) != hipSuccess) return st;
         hipLaunchKernelGGL(k_colsum, dim3(dout / 32), dim3(256), 0, s, m->Y, nullptr, rp, dout,
                            m->G + m->boff[L + 1]);
         Epi f{};
@@ -623,7 +823,7 @@ hipError_t backward(opf_mlp* m, const float* t, const float* om, int nrows, int 
         f.ldb = H;
         f.outT = m->dZT;
         f.ldt = R;
-        if ((st = gemm<false>(s, m->dYb, dout, m->Wt + m->woff[L + 1], dout, rp, H, dout, f)) != hipSuccess)
+        if ((st = gemm(s, m->dYb, dout, m->Wt + m->woff[L + 1], dout, rp, H, dout, f)) != hipSuccess)
             return st;
     }
     bf16_t* dz[2] = {m->dZb0, m->dZb1};
@@ -634,7 +834,7 @@ hipError_t backward(opf_mlp* m, const float* t, const float* om, int nrows, int 
         Epi e{};
         e.out = m->G + m->woff[l + 1];
         e.ldo = H;
-        if ((st = gemm<false>(s, m->dZT, R, m->ht(l), R, H, H, rp, e)) != hipSuccess) return st;
+        if ((st = gemm(s, m->dZT, R, m->ht(l), R, H, H, rp, e)) != hipSuccess) return st;
         Epi f{};
         f.mode = EPI_ADD;
         f.res = m->dH;
@@ -649,7 +849,7 @@ hipError_t backward(opf_mlp* m, const float* t, const float* om, int nrows, int 
             f.outb = dz[cur ^ 1];
             f.ldb = H;
         }
-        if ((st = gemm<false>(s, dz[cur], H, m->Wt + m->woff[l + 1], H, rp, H, H, f)) != hipSuccess) return st;
+        if ((st = gemm(s, dz[cur], H, m->Wt + m->woff[l + 1], H, rp, H, H, f)) != hipSuccess) return st;
         cur ^= 1;
     }
     // input layer: dW_in = dH_0^T X, db_in = colsum dH_0
@@ -657,12 +857,55 @@ hipError_t backward(opf_mlp* m, const float* t, const float* om, int nrows, int 
     Epi e{};
     e.out = m->G + m->woff[0];
     e.ldo = m->din;
-    if ((st = gemm<false>(s, m->dZT, R, m->XT, R, H, m->din, rp, e)) != hipSuccess) return st;
+    if ((st = gemm(s, m->dZT, R, m->XT, R, H, m->din, rp, e)) != hipSuccess) return st;
     return hipGetLastError();
+}
+
+// Squared-error loss of rows (targets t, weights om) into *loss_slot and
+// dL/dY, then the parameter gradients.
+hipError_t backward_rows(opf_mlp* m, const float* t, const float* om, int nrows, int rp, float* loss_slot) {
+    hipStream_t s = m->s;
+    hipLaunchKernelGGL(k_weight_sum, dim3(1), dim3(256), 0, s, om, nrows, m->wsum);
+    hipLaunchKernelGGL(k_loss, dim3(rp / 4), dim3(256), 0, s, m->Y, t, om, m->wsum, nrows, rp, m->dout, m->dYb,
+                       m->dYT, m->R, m->lrow);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lrow, nrows, m->wsum, loss_slot);
+    const hipError_t st = hipGetLastError();
+    return st != hipSuccess ? st : backprop(m, rp);
+}
+
+// Loss head over pairs idx[0..batch) into *loss_slot and dL/dY, then the
+// parameter gradients (forward over the mode feature rows first).
+hipError_t backward_pairs(opf_mlp* m, const double* pairs, const int* idx, int batch, float* loss_slot) {
+    hipStream_t s = m->s;
+    const int rp = round32(m->mode_rows);
+    HeadArgs a{};
+    a.pairs = pairs;
+    a.vec = 2L * 3 * m->M * m->nk * m->N;
+    a.idx = idx;
+    a.batch = batch;
+    a.N = m->N;
+    a.M = m->M;
+    a.nk = m->nk;
+    a.rank = m->rank;
+    a.dout = m->dout;
+    a.rows = m->mode_rows;
+    a.rp = rp;
+    a.Y = m->Y;
+    a.dyb = m->dYb;
+    a.dyt = m->dYT;
+    a.ldt = m->R;
+    a.lrow = m->lrow;
+    a.scale = (float)(1.0 / ((double)batch * m->mode_rows));
+    hipLaunchKernelGGL(k_head, dim3(rp), dim3(64), (size_t)m->dout * 4, s, a);
+    hipLaunchKernelGGL(k_weight_sum, dim3(1), dim3(256), 0, s, nullptr, batch * m->mode_rows, m->wsum);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lrow, m->mode_rows, m->wsum, loss_slot);
+    const hipError_t st = hipGetLastError();
+    return st != hipSuccess ? st : backprop(m, rp);
 }
 
 hipError_t adam(opf_mlp* m) {
     m->t += 1;
+    m->fac_ok = false;
     const float c1 = (float)(1.0 / (1.0 - std::pow((double)m->b1, (double)m->t)));
     const float c2 = (float)(1.0 / (1.0 - std::pow((double)m->b2, (double)m->t)));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((m->np + 255) / 256)), dim3(256), 0, m->s, m->P, m->G, m->Am, m->Av,
@@ -675,6 +918,31 @@ hipError_t rows_bf16(opf_mlp* m, const float* x, int nrows, int rp, bool transpo
     hipLaunchKernelGGL(k_rows_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, m->s, x, nrows, rp, m->din,
                        m->Xb, transposed ? m->XT : nullptr, m->R);
     return hipGetLastError();
+}
+
+// The mode feature rows as GEMM input (and transposed, for training).
+hipError_t feature_input(opf_mlp* m) { return rows_bf16(m, m->fx, m->mode_rows, round32(m->mode_rows), true); }
+
+// Preconditioner factors (A, B) of the current parameters into fac: the
+// network's Jacobian model (U, V) per mode, inverted by Woodbury.
+hipError_t refresh_factors(opf_mlp* m) {
+    if (m->fac_ok) return hipSuccess;
+    const int rp = round32(m->mode_rows);
+    hipError_t st = feature_input(m);
+    if (st == hipSuccess) st = forward(m, rp, false);
+    if (st != hipSuccess) return st;
+    hipLaunchKernelGGL(k_woodbury, dim3(m->mode_rows), dim3(64), 0, m->s, m->Y, m->fac, m->dout, m->N, m->rank,
+                       m->mode_rows, m->singular);
+    if ((st = hipGetLastError()) != hipSuccess) return st;
+    std::vector<int> flags(m->mode_rows);
+    if ((st = hipMemcpyAsync(flags.data(), m->singular, flags.size() * sizeof(int), hipMemcpyDeviceToHost, m->s)) !=
+            hipSuccess ||
+        (st = hipStreamSynchronize(m->s)) != hipSuccess)
+        return st;
+    m->n_singular = 0;
+    for (int f : flags) m->n_singular += f;
+    m->fac_ok = true;
+    return hipSuccess;
 }
 
 bool same_grid(const opf_mlp* m, const opf_ctx* c) {
@@ -691,6 +959,7 @@ opf_status opf_mlp_default_config(opf_mlp_config* cfg) {
     *cfg = opf_mlp_config{};
     cfg->width = 256;
     cfg->layers = 4;
+    cfg->rank = 8;
     cfg->max_rows = 0;
     cfg->seed = 1;
     cfg->lr = 1e-3f;
@@ -700,16 +969,27 @@ opf_status opf_mlp_default_config(opf_mlp_config* cfg) {
     return OPF_OK;
 }
 
+static void dims_for(opf_mlp* m, const opf_ctx* ctx, const opf_mlp_config* cfg) {
+    const opf_params& p = ctx_params(ctx);
+    m->N = p.N;
+    m->M = p.M;
+    m->K = p.K;
+    m->nk = 2 * p.K - 1;
+    m->mp = p.mp;
+    m->alpha = p.alpha;
+    m->H = cfg->width;
+    m->L = cfg->layers;
+    m->rank = cfg->rank;
+    m->mode_rows = p.M * m->nk;
+    m->R = round32(std::max(cfg->max_rows, m->mode_rows));
+}
+
 opf_status opf_mlp_workspace_size(const opf_ctx* ctx, const opf_mlp_config* cfg, size_t* bytes) {
     if (!bytes) return OPF_E_INVALID;
     const opf_status st = check_cfg(ctx, cfg, nullptr);
     if (st != OPF_OK) return st;
     opf_mlp m;
-    const opf_params& p = ctx_params(ctx);
-    m.N = p.N;
-    m.H = cfg->width;
-    m.L = cfg->layers;
-    m.R = round32(cfg->max_rows);
+    dims_for(&m, ctx, cfg);
     *bytes = plan(&m).total;
     return OPF_OK;
 }
@@ -727,18 +1007,9 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return OPF_E_INVALID;
     opf_mlp* m = new (std::nothrow) opf_mlp;
     if (!m) return OPF_E_NOMEM;
-    const opf_params& p = ctx_params(ctx);
     m->ctx = ctx;
     m->s = ctx_stream(ctx);
-    m->N = p.N;
-    m->M = p.M;
-    m->K = p.K;
-    m->nk = 2 * p.K - 1;
-    m->mp = p.mp;
-    m->alpha = p.alpha;
-    m->H = cfg->width;
-    m->L = cfg->layers;
-    m->R = round32(cfg->max_rows);
+    dims_for(m, ctx, cfg);
     m->lr = cfg->lr;
     m->b1 = cfg->beta1;
     m->b2 = cfg->beta2;
@@ -770,12 +1041,21 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
     at(m->dZb0);
     at(m->dZb1);
     at(m->dZT);
-    at(m->X);
-    at(m->sc);
+    at(m->fx);
+    at(m->fac);
+    at(m->idx);
+    at(m->singular);
     at(m->lrow);
     at(m->wsum);
     at(m->losses);
     m->loss_cap = LOSS_CAP;
+    const int rp = round32(m->mode_rows);
+    hipLaunchKernelGGL(k_features, dim3((rp * NCOND + 255) / 256), dim3(256), 0, m->s, m->fx, m->mode_rows, rp, m->nk,
+                       m->K, m->mp, m->alpha);
+    if (hipGetLastError() != hipSuccess) {
+        delete m;
+        return OPF_E_HIP;
+    }
     // initial weights: W ~ U(-a, a), a = 1/sqrt(fan_in) (output layer 0.01 a),
     // biases 0, from SplitMix64 (Steele, Lea & Flood 2014)
     std::vector<float> host(m->np, 0.0f);
@@ -790,12 +1070,6 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
         ctx_set_error(ctx, m->err);
         delete m;
         return st;
-    }
-    // rows past M(2K-1) of the preconditioner input stay zero
-    if (hipMemsetAsync(m->X, 0, (size_t)m->R * m->din * 4, m->s) != hipSuccess ||
-        hipStreamSynchronize(m->s) != hipSuccess) {
-        delete m;
-        return OPF_E_HIP;
     }
     *out = m;
     return OPF_OK;
@@ -826,6 +1100,7 @@ opf_status opf_mlp_set_params(opf_mlp* net, const float* host, int64_t n) {
     MCHK(net, hipGetLastError());
     MCHK(net, hipStreamSynchronize(net->s));
     net->t = 0;
+    net->fac_ok = false;
     return OPF_OK;
 }
 
@@ -840,7 +1115,7 @@ opf_status opf_mlp_forward(opf_mlp* net, const float* x_dev, int32_t rows, float
     if (!net || !x_dev || !y_dev || rows < 1 || rows > net->R) return OPF_E_INVALID;
     const int rp = round32(rows);
     MCHK(net, rows_bf16(net, x_dev, rows, rp, false));
-    MCHK(net, forward(net, net->Xb, false, net->din, rp, false));
+    MCHK(net, forward(net, rp, false));
     MCHK(net, hipMemcpyAsync(y_dev, net->Y, (size_t)rows * net->dout * 4, hipMemcpyDeviceToDevice, net->s));
     return OPF_OK;
 }
@@ -850,8 +1125,8 @@ opf_status opf_mlp_gradient(opf_mlp* net, const float* x_dev, const float* t_dev
     if (!net || !x_dev || !t_dev || rows < 1 || rows > net->R) return OPF_E_INVALID;
     const int rp = round32(rows);
     MCHK(net, rows_bf16(net, x_dev, rows, rp, true));
-    MCHK(net, forward(net, net->Xb, false, net->din, rp, true));
-    MCHK(net, backward(net, t_dev, w_dev, rows, rp, net->losses));
+    MCHK(net, forward(net, rp, true));
+    MCHK(net, backward_rows(net, t_dev, w_dev, rows, rp, net->losses));
     float l = 0.0f;
     MCHK(net, hipMemcpyAsync(&l, net->losses, 4, hipMemcpyDeviceToHost, net->s));
     if (grad_host) MCHK(net, hipMemcpyAsync(grad_host, net->G, (size_t)net->np * 4, hipMemcpyDeviceToHost, net->s));
@@ -876,83 +1151,90 @@ opf_status opf_mlp_train(opf_mlp* net, const float* x_dev, const float* t_dev, c
             const int n = std::min(batch, rows - r0);
             const int rp = round32(n);
             MCHK(net, rows_bf16(net, x_dev + (size_t)r0 * net->din, n, rp, true));
-            MCHK(net, forward(net, net->Xb, false, net->din, rp, true));
-            MCHK(net, backward(net, t_dev + (size_t)r0 * net->dout, w_dev ? w_dev + r0 : nullptr, n, rp,
-                               net->losses + step));
+            MCHK(net, forward(net, rp, true));
+            MCHK(net, backward_rows(net, t_dev + (size_t)r0 * net->dout, w_dev ? w_dev + r0 : nullptr, n, rp,
+                                    net->losses + step));
             MCHK(net, adam(net));
             ++step;
         }
     }
-    if (loss_host && epochs > 0) {
-        std::vector<float> l(step);
-        MCHK(net, hipMemcpyAsync(l.data(), net->losses, (size_t)step * 4, hipMemcpyDeviceToHost, net->s));
-        MCHK(net, hipStreamSynchronize(net->s));
+    std::vector<float> l(step);
+    if (step) MCHK(net, hipMemcpyAsync(l.data(), net->losses, (size_t)step * 4, hipMemcpyDeviceToHost, net->s));
+    MCHK(net, hipStreamSynchronize(net->s));
+    if (loss_host)
         for (int ep = 0; ep < epochs; ++ep) {
             double a = 0.0;
             for (int i = 0; i < nb; ++i) a += l[(size_t)ep * nb + i];
             loss_host[ep] = (float)(a / nb);
         }
-    } else {
-        MCHK(net, hipStreamSynchronize(net->s));
-    }
     return OPF_OK;
 }
 
-opf_status opf_mlp_pack_pairs(opf_ctx* ctx, const opf_mlp* net, const void* pairs_dev, int32_t npairs, float* x_dev,
-                              float* t_dev, float* w_dev) {
-    if (!ctx || !net || !pairs_dev || npairs < 1 || !x_dev || !t_dev) return OPF_E_INVALID;
+opf_status opf_mlp_pair_gradient(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs,
+                                 const int32_t* idx_host, int32_t batch, double* loss_host, float* grad_host) {
+    if (!ctx || !net || !pairs_dev || !idx_host || npairs < 1 || batch < 1 || batch > LOSS_CAP) return OPF_E_INVALID;
     if (!same_grid(net, ctx)) return OPF_E_INVALID;
-    const long vec = 2L * 3 * net->M * net->nk * net->N;  // doubles per vector
-    PackArgs a{};
-    a.z = static_cast<const double*>(pairs_dev);
-    a.y = a.z + vec;
-    a.pstride = 2 * vec;
-    a.N = net->N;
-    a.M = net->M;
-    a.nk = net->nk;
-    a.K = net->K;
-    a.mp = net->mp;
-    a.alpha = net->alpha;
-    a.p6 = net->p6;
-    a.din = net->din;
-    a.rows = npairs * net->M * net->nk;
-    a.X = x_dev;
-    a.T = t_dev;
-    a.om = w_dev;
-    hipLaunchKernelGGL(k_pack, dim3((a.rows + 3) / 4), dim3(256), 0, ctx_stream(ctx), a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        ctx_set_error(ctx, std::string("k_pack: ") + hipGetErrorString(e));
-        return OPF_E_HIP;
+    for (int b = 0; b < batch; ++b)
+        if (idx_host[b] < 0 || idx_host[b] >= npairs) return OPF_E_INVALID;
+    MCHK(net, hipMemcpyAsync(net->idx, idx_host, (size_t)batch * 4, hipMemcpyHostToDevice, net->s));
+    MCHK(net, feature_input(net));
+    MCHK(net, forward(net, round32(net->mode_rows), true));
+    MCHK(net, backward_pairs(net, static_cast<const double*>(pairs_dev), net->idx, batch, net->losses));
+    float l = 0.0f;
+    MCHK(net, hipMemcpyAsync(&l, net->losses, 4, hipMemcpyDeviceToHost, net->s));
+    if (grad_host) MCHK(net, hipMemcpyAsync(grad_host, net->G, (size_t)net->np * 4, hipMemcpyDeviceToHost, net->s));
+    MCHK(net, hipStreamSynchronize(net->s));
+    if (loss_host) *loss_host = l;
+    return std::isfinite(l) ? OPF_OK : OPF_E_NUMERIC;
+}
+
+opf_status opf_mlp_train_pairs(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs, int32_t batch,
+                               int32_t steps, uint64_t seed, float* loss_host) {
+    if (!ctx || !net || !pairs_dev || npairs < 1 || batch < 1 || steps < 0) return OPF_E_INVALID;
+    if ((long)batch * steps > LOSS_CAP || steps > net->loss_cap) return OPF_E_INVALID;
+    if (!same_grid(net, ctx)) return OPF_E_INVALID;
+    // pair indices of every step: consecutive batches of per-epoch shuffles
+    std::vector<int> idx((size_t)batch * steps);
+    std::vector<int> perm(npairs);
+    uint64_t state = seed;
+    size_t filled = 0;
+    while (filled < idx.size()) {
+        for (int i = 0; i < npairs; ++i) perm[i] = i;
+        for (int i = npairs - 1; i > 0; --i) std::swap(perm[i], perm[(int)(uniform01(state) * (i + 1))]);
+        for (int i = 0; i < npairs && filled < idx.size(); ++i) idx[filled++] = perm[i];
     }
+    if (!idx.empty()) MCHK(net, hipMemcpyAsync(net->idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, net->s));
+    MCHK(net, feature_input(net));
+    const int rp = round32(net->mode_rows);
+    for (int st = 0; st < steps; ++st) {
+        MCHK(net, forward(net, rp, true));
+        MCHK(net, backward_pairs(net, static_cast<const double*>(pairs_dev), net->idx + (size_t)st * batch, batch,
+                                 net->losses + st));
+        MCHK(net, adam(net));
+    }
+    if (loss_host && steps > 0) MCHK(net, hipMemcpyAsync(loss_host, net->losses, (size_t)steps * 4,
+                                                         hipMemcpyDeviceToHost, net->s));
+    MCHK(net, hipStreamSynchronize(net->s));  // the host index array lives until here
     return OPF_OK;
 }
 
 opf_status opf_precondition(opf_ctx* ctx, opf_mlp* net, const void* v_dev, void* z_dev) {
     if (!ctx || !net || !v_dev || !z_dev) return OPF_E_INVALID;
     if (!same_grid(net, ctx)) return OPF_E_INVALID;
-    const int rows = net->M * net->nk;
-    PackArgs a{};
-    a.y = static_cast<const double*>(v_dev);
-    a.N = net->N;
-    a.M = net->M;
-    a.nk = net->nk;
-    a.K = net->K;
-    a.mp = net->mp;
-    a.alpha = net->alpha;
-    a.p6 = net->p6;
-    a.din = net->din;
-    a.rows = rows;
-    a.X = net->X;
-    a.sc = net->sc;
-    hipLaunchKernelGGL(k_pack, dim3((rows + 3) / 4), dim3(256), 0, net->s, a);
+    MCHK(net, refresh_factors(net));
+    hipLaunchKernelGGL(k_lowrank_apply, dim3((net->mode_rows + 3) / 4), dim3(256), 0, net->s, net->fac, net->dout,
+                       net->rank, static_cast<const double*>(v_dev), static_cast<double*>(z_dev), net->N, net->M,
+                       net->nk, net->K);
     MCHK(net, hipGetLastError());
-    MCHK(net, forward(net, net->X, true, net->din, round32(rows), false));
-    const long n = 3L * rows * net->N;
-    hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, net->s, net->Y, net->dout, net->sc,
-                       static_cast<const double*>(v_dev), static_cast<double*>(z_dev), net->N, net->M, net->nk,
-                       net->K);
-    MCHK(net, hipGetLastError());
+    return OPF_OK;
+}
+
+opf_status opf_mlp_factors(opf_mlp* net, float* host, int64_t n, int32_t* singular_modes) {
+    if (!net || (host && n != (int64_t)net->mode_rows * net->dout)) return OPF_E_INVALID;
+    MCHK(net, refresh_factors(net));
+    if (host) MCHK(net, hipMemcpyAsync(host, net->fac, (size_t)n * 4, hipMemcpyDeviceToHost, net->s));
+    MCHK(net, hipStreamSynchronize(net->s));
+    if (singular_modes) *singular_modes = net->n_singular;
     return OPF_OK;
 }
 

@@ -1,5 +1,6 @@
-"""GPU parity of the learned-preconditioner network (matrix-core GEMMs,
-backward pass, Adam, pack / unpack of mode profiles) against the oracle MLP.
+"""GPU parity of the learned preconditioner (matrix-core GEMMs of the
+residual MLP, backward pass, Adam, the pair-loss head and the per-mode
+low-rank map) against the oracle, and its effect on Newton-Krylov.
 
 Tolerances.  The device rounds every GEMM operand to bfloat16 exactly as the
 oracle's bf16 mode does, but accumulates in FP32 where the oracle uses FP64.
@@ -9,8 +10,8 @@ product, one element changes by one bfloat16 ulp (2^-8).  With a few percent
 of such flips per layer the norm-wise effect stays below ~3e-3, so outputs
 and gradients are held to 1e-2 relative (norm-wise) against the bf16 oracle,
 while the same outputs differ from the unrounded FP64 oracle by several times
-more (which shows that the device really computes in bfloat16).  Adam and the
-packing run in FP32 / FP64 arithmetic and are held to FP32 rounding.
+more (which shows that the device really computes in bfloat16).  Adam runs
+in FP32 and is held to FP32 rounding.
 """
 import numpy as np
 import pytest
@@ -20,6 +21,7 @@ from inputs import make_state
 pytestmark = pytest.mark.gpu
 
 GRID = dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007)  # 42 mode rows: ragged tile
+RANK = 2
 
 
 def say(*a):
@@ -33,11 +35,11 @@ def torch_cuda():
     return torch
 
 
-def make_net(torch_cuda, width=64, layers=3, max_rows=None, seed=7, **kw):
+def make_net(torch_cuda, width=64, layers=3, max_rows=0, seed=7, **kw):
     import paper_1705_03838_amd as opf
     from oracle.mlp import flatten, init_params, unflatten
     s = opf.Solver(**GRID)
-    net = opf.Mlp(s, width=width, layers=layers, max_rows=max_rows, **kw)
+    net = opf.Mlp(s, width=width, layers=layers, rank=RANK, max_rows=max_rows, **kw)
     p = init_params(net.din, width, layers, net.dout, seed=seed)
     rng = np.random.default_rng(seed)
     for k in p:
@@ -74,8 +76,21 @@ def test_forward_matches_bf16_oracle(torch_cuda):
         assert e_b <= 0.3 * e_f
 
 
+def check_grads(g, gref, layers):
+    from oracle.mlp import flatten, param_names
+    gflat = flatten(gref, layers)
+    o = 0
+    for k in param_names(layers):
+        sz = gref[k].size
+        e = nrel(g[o:o + sz].astype(np.float64), gflat[o:o + sz])
+        say("   grad", k, e)
+        assert e <= 1e-2, k
+        o += sz
+    assert o == g.size
+
+
 def test_gradient_matches_bf16_oracle(torch_cuda):
-    from oracle.mlp import backward, flatten, forward, loss
+    from oracle.mlp import backward, forward, loss
     s, net, p = make_net(torch_cuda, max_rows=224)  # batch rows (160 padded) < capacity (224)
     rng = np.random.default_rng(2)
     n = 150
@@ -87,15 +102,7 @@ def test_gradient_matches_bf16_oracle(torch_cuda):
     y, cache = forward(p, x64, 3, bf16=True)
     gref = backward(p, cache, y, t64, 3, bf16=True, w=w64)
     assert abs(lg - loss(y, t64, w64)) <= 1e-3 * loss(y, t64, w64)
-    gflat = flatten(gref, 3)
-    o = 0
-    for k in ["W_in", "b_in", "W_0", "b_0", "W_1", "b_1", "W_2", "b_2", "W_out", "b_out"]:
-        sz = gref[k].size
-        e = nrel(g[o:o + sz].astype(np.float64), gflat[o:o + sz])
-        say("   grad", k, e)
-        assert e <= 1e-2, k
-        o += sz
-    assert o == net.n_params
+    check_grads(g, gref, 3)
 
 
 def test_adam_step_and_weight_copies(torch_cuda):
@@ -118,50 +125,91 @@ def test_adam_step_and_weight_copies(torch_cuda):
     assert nrel(y, yb) <= 1e-2
 
 
-def field(s, seed):
-    v = make_state(GRID["N"], GRID["M"], GRID["K"], GRID["mp"], GRID["alpha"], s.nodes(), 1e-2, 3.0, 3.0,
+def field(s, seed, energy=1e-2):
+    v = make_state(GRID["N"], GRID["M"], GRID["K"], GRID["mp"], GRID["alpha"], s.nodes(), energy, 3.0, 3.0,
                    seed, laminar=False)
     K = GRID["K"]
-    for kk in range(K - 1):  # exactly Hermitian at m = 0
+    for kk in range(K - 1):  # exactly the spectrum of a real field at m = 0
         v[:, 0, kk] = np.conj(v[:, 0, 2 * (K - 1) - kk])
     v[:, 0, K - 1] = v[:, 0, K - 1].real
     return v
 
 
-def test_pack_pairs_match_oracle(torch_cuda):
-    from oracle.mlp import pack
-    s, net, p = make_net(torch_cuda, max_rows=100)
-    v, jv = field(s, 21), field(s, 22)
-    pairs = np.stack([np.stack([v, jv]), np.stack([jv, v])])
-    say("pack pairs", pairs.shape)
-    x, t, w = net.pack_pairs(torch_cuda.from_numpy(pairs))
-    x, t, w = x.cpu().numpy(), t.cpu().numpy(), w.cpu().numpy()
-    rows_ = s.M * (2 * s.K - 1)
-    for i in range(2):
-        X, T, W, _, _ = pack(pairs[i, 1], GRID["mp"], GRID["alpha"], z=pairs[i, 0])
-        sl = slice(i * rows_, (i + 1) * rows_)
-        assert np.max(np.abs(x[sl] - X)) <= 1e-6 * np.max(np.abs(X))
-        assert np.max(np.abs(t[sl] - T)) <= 1e-6 * np.max(np.abs(T))
-        assert np.all(np.abs(w[sl] - W) <= 1e-6 * W + 1e-30)
-
-
-def test_precondition_matches_oracle(torch_cuda):
-    from oracle.mlp import precondition
+def test_factors_and_precondition_match_oracle(torch_cuda):
+    from oracle.mlp import lowrank_apply, precondition
     s, net, p = make_net(torch_cuda)
+    F, singular = net.factors()
+    assert singular == 0
     v = field(s, 23)
     say("precondition", v.shape)
     z = net.precondition(torch_cuda.from_numpy(v)).cpu().numpy()
-    zb = precondition(p, 3, v, GRID["mp"], GRID["alpha"], bf16=True)
+    # the low-rank map itself, from the device's own factors: FP64 rounding only
+    zf = lowrank_apply(F.astype(np.float64), v, RANK)
+    assert np.max(np.abs(z - zf)) <= 1e-12 * np.max(np.abs(zf))
+    # network + Woodbury + map against the bf16 oracle
+    zb = precondition(p, 3, v, GRID["mp"], GRID["alpha"], RANK, bf16=True)
     assert nrel(z + v, zb + v) <= 1e-2
     K = GRID["K"]
     for kk in range(K - 1):
         assert np.array_equal(z[:, 0, kk], np.conj(z[:, 0, 2 * (K - 1) - kk]))
-    # a network with zero output layer gives z = -v exactly
+    assert np.all(z[:, 0, K - 1].imag == 0)
+    # a network with zero output layer models J = -I and gives z = -v exactly
     q = net.get_params()
     q[-(net.dout * 64 + net.dout):] = 0.0
     net.set_params(q)
     z0 = net.precondition(torch_cuda.from_numpy(v)).cpu().numpy()
     assert np.array_equal(z0, -v)
+
+
+def test_pair_gradient_matches_oracle(torch_cuda):
+    from oracle.mlp import backprop, feature_rows, forward, head
+    s, net, p = make_net(torch_cuda)
+    pairs = np.stack([np.stack([field(s, 40 + i), field(s, 50 + i)]) for i in range(5)])
+    pairs[2, 1, :, 3, 2] = 0.0  # an empty (J z) profile: that mode-pair is skipped
+    idx = np.array([3, 0, 2, 2], dtype=np.int32)
+    say("pair gradient", pairs.shape, idx)
+    lg, g = net.pair_gradient(torch_cuda.from_numpy(pairs), idx)
+    # the head on the device's own model rows: FP32 accumulation of the loss only
+    X = feature_rows(GRID["M"], GRID["K"], GRID["mp"], GRID["alpha"])
+    Fdev = net.forward(torch_cuda.from_numpy(X.astype(np.float32))).cpu().numpy().astype(np.float64)
+    Ldev, _ = head(Fdev, pairs[idx], RANK)
+    say("   loss", lg, Ldev)
+    assert abs(lg - Ldev) <= 1e-5 * Ldev
+    F, cache = forward(p, X, 3, bf16=True)
+    L, dF = head(F.astype(np.float32).astype(np.float64), pairs[idx], RANK)
+    assert abs(lg - L) <= 1e-2 * L
+    gref = backprop(p, cache, dF, 3, bf16=True)
+    check_grads(g, gref, 3)
+
+
+def test_probe_pairs_are_jacobian_products(torch_cuda):
+    import paper_1705_03838_amd as opf
+    from inputs import laminar_state
+    kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
+    say("probe pairs", kw)
+    s = opf.Solver(**kw)
+    x = torch_cuda.from_numpy(make_state(12, 2, 2, 2, 1.25, s.nodes(), 1e-4, 4.0, 4.0, 6)).cuda()
+    pairs = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
+    again = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
+    assert torch_cuda.equal(pairs, again)
+    other = s.probe_pairs(x, 1.0, 0.0, 1, seed=6)
+    assert not torch_cuda.equal(pairs[0, 0], other[0, 0])
+    for i in range(3):
+        z, jz = pairs[i, 0], pairs[i, 1]
+        assert abs(s.vec_dot(z, z) - 1.0) <= 1e-12
+        zn = z.cpu().numpy()
+        assert np.array_equal(zn[:, 0, 0], np.conj(zn[:, 0, 2])) and np.all(zn[:, 0, 1].imag == 0)
+        F0, _ = s.newton_residual(x, 1.0, 0.0)
+        eps = 1e-7 * max(np.sqrt(s.vec_dot(x, x)), 1.0)
+        F1, _ = s.newton_residual(x + eps * z, 1.0, 0.0)
+        fd = ((F1 - F0) / eps - jz).cpu().numpy()
+        assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(fd), torch_cuda.from_numpy(fd))) <= 1e-10 * max(
+            1.0, np.sqrt(s.vec_dot(jz, jz)))
+    # near laminar flow J z of a unit z has norm of order one, and not J = -I
+    lam = torch_cuda.from_numpy(laminar_state(12, 2, 2, s.nodes())).cuda()
+    pl = s.probe_pairs(lam, 1.0, 0.0, 1, seed=5)
+    d = pl[0, 1] + pl[0, 0]
+    assert 1e-3 < np.sqrt(s.vec_dot(d, d)) < 1.0
 
 
 def test_flexible_gmres_with_minus_identity_matches_plain(torch_cuda):
@@ -172,7 +220,7 @@ def test_flexible_gmres_with_minus_identity_matches_plain(torch_cuda):
     kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
     say("fgmres -I", kw)
     s = opf.Solver(**kw)
-    net = opf.Mlp(s, width=32, layers=1)
+    net = opf.Mlp(s, width=32, layers=1, rank=2)
     q = net.get_params()
     q[-(net.dout * 32 + net.dout):] = 0.0
     net.set_params(q)
@@ -197,3 +245,33 @@ def test_flexible_gmres_with_minus_identity_matches_plain(torch_cuda):
     fd = ((F1 - F0) / eps - jz).cpu().numpy()
     assert np.sqrt(s.vec_dot(torch_cuda.from_numpy(fd), torch_cuda.from_numpy(fd))) <= 1e-10 * max(
         1.0, np.sqrt(s.vec_dot(jz, jz)))
+
+
+def test_trained_preconditioner_cuts_krylov_work(torch_cuda):
+    """What the learned preconditioner gains: trained on Jacobian probes at
+    laminar flow, it must leave the Newton-Krylov search converging to the
+    same laminar solution with far fewer Jacobian-vector products than plain
+    GMRES on a near-laminar guess of another seed."""
+    import paper_1705_03838_amd as opf
+    from inputs import laminar_state
+    kw = dict(N=12, M=4, K=4, mp=2, alpha=1.25, Re=200.0, dt=0.05)
+    T = 2.0
+    say("learned preconditioner gain", kw, "T", T)
+    s = opf.Solver(**kw)
+    lam = torch_cuda.from_numpy(laminar_state(12, 4, 4, s.nodes())).cuda()
+    pairs = s.probe_pairs(lam, T, 0.0, 96, seed=3)  # 3N = 36 complex unknowns per mode
+    net = opf.Mlp(s, width=128, layers=4, rank=4, seed=2)
+    losses = net.train_pairs(pairs, batch=16, steps=2000, seed=4)
+    say("  loss first / last", losses[0], losses[-50:].mean())
+    assert losses[-50:].mean() < 0.05 * losses[0]
+    _, bad = net.factors()
+    assert bad == 0
+    x = torch_cuda.from_numpy(make_state(12, 4, 4, 2, 1.25, s.nodes(), 1e-4, 4.0, 4.0, 17))
+    x1, r1 = s.nk_solve(x, T, 0.0, tol=1e-10, gmres_tol=1e-4)
+    x2, r2 = s.nk_solve(x, T, 0.0, tol=1e-10, gmres_tol=1e-4, precond=net)
+    say("  plain", r1, "\n  learned", r2)
+    assert r1["converged"] and r2["converged"]
+    assert r2["jvps"] <= 0.6 * r1["jvps"]
+    for xs in (x1, x2):
+        d = xs - lam
+        assert np.sqrt(s.vec_dot(d, d)) < 1e-8

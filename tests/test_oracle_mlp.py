@@ -80,64 +80,76 @@ def _field(seed, M=4, K=3, N=5):
     for kk in range(K - 1):  # real field: m = 0 Hermitian in k
         v[:, 0, kk] = np.conj(v[:, 0, 2 * (K - 1) - kk])
     v[:, 0, K - 1] = v[:, 0, K - 1].real
-    v[:, 2, 1] = 0.0  # an empty mode
+    if M > 2:
+        v[:, 2, 1] = 0.0  # an empty mode
     return v
 
 
-def _net(N, seed=5, layers=2, width=32, zero_out=False):
-    from oracle.mlp import dims
-    din, dout = dims(N)
-    p = init_params(din, width, layers, dout, seed=seed)
-    p["b_out"] = np.linspace(-0.2, 0.3, dout)
-    if zero_out:
-        p["W_out"][:] = 0.0
-        p["b_out"][:] = 0.0
-    return p
-
-
-def test_zero_network_is_minus_identity():
-    from oracle.mlp import precondition
-    v = _field(1)
-    z = precondition(_net(5, zero_out=True), 2, v, mp=2, alpha=1.25)
-    assert np.array_equal(z, -v) or np.max(np.abs(z + v)) <= 1e-15 * np.max(np.abs(v))
-
-
-def test_preconditioner_homogeneous_phase_equivariant_hermitian():
-    from oracle.mlp import precondition
-    v = _field(2)
-    p = _net(5)
-    K = 3
-    z = precondition(p, 2, v, mp=2, alpha=1.25)
-    # positive homogeneity
-    z2 = precondition(p, 2, 3.7 * v, mp=2, alpha=1.25)
-    assert np.max(np.abs(z2 - 3.7 * z)) <= 1e-12 * np.max(np.abs(z2))
-    # commutes with a phase rotation of the modes m > 0 (and of (0, k >= 0))
-    ph = np.exp(0.83j)
-    zr = precondition(p, 2, ph * v, mp=2, alpha=1.25)
-    assert np.max(np.abs(zr[:, 1:] - ph * z[:, 1:])) <= 1e-12 * np.max(np.abs(z))
-    assert np.max(np.abs(zr[:, 0, K - 1:] - ph * z[:, 0, K - 1:])) <= 1e-12 * np.max(np.abs(z))
-    # m = 0 output is Hermitian in k; an empty mode maps to zero
-    for kk in range(K - 1):
+def test_zero_factors_give_minus_identity_and_map_is_linear():
+    from oracle.mlp import factor_dims, lowrank_apply
+    M, K, N, R = 4, 3, 5, 2
+    rows = M * (2 * K - 1)
+    u, v = _field(1), _field(2)
+    assert np.max(np.abs(lowrank_apply(np.zeros((rows, factor_dims(N, R))), v, R) + v)) == 0.0
+    F = np.random.default_rng(3).standard_normal((rows, factor_dims(N, R)))
+    a, b = 0.7, -2.3
+    lhs = lowrank_apply(F, a * u + b * v, R)
+    rhs = a * lowrank_apply(F, u, R) + b * lowrank_apply(F, v, R)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    z = lowrank_apply(F, v, R)
+    for kk in range(K - 1):  # real output field
         assert np.array_equal(z[:, 0, kk], np.conj(z[:, 0, 2 * (K - 1) - kk]))
-    assert np.all(z[:, 2, 1] == 0)
-    # a nonzero network changes the result
-    assert np.max(np.abs(z + v)) > 1e-3
+    assert np.all(z[:, 0, K - 1].imag == 0) and np.all(z[:, 2, 1] == 0)
 
 
-def test_pack_rows_layout_and_features():
-    from oracle.mlp import cond_features, dims, pack
-    v = _field(3)
-    X, T, w, S, E = pack(v, 2, 1.25, z=-v)
-    din, p6 = dims(5)
-    assert X.shape == (4 * 5, din) and T.shape == (4 * 5, p6)
-    q = 1 * 5 + 3  # m = 1, k = +1
-    prof = v[:, 1, 3, :].reshape(-1)
-    s = np.sqrt(np.mean(np.abs(prof) ** 2))
-    assert abs(S[q] - s) <= 1e-15 * s and abs(w[q] - s * s) <= 1e-14 * s * s
-    yh = X[q, 0:30:2] + 1j * X[q, 1:30:2]
-    assert abs(np.sum(yh).imag) <= 1e-12 and np.sum(yh).real > 0  # phase canonical
-    assert abs(np.mean(np.abs(yh) ** 2) - 1) <= 1e-12
-    assert np.max(np.abs(T[q])) <= 1e-12  # target of z = -y is zero
+def test_woodbury_inverts_a_low_rank_jacobian_model():
+    # J = -I + U V^H on one mode (rank 2): the preconditioner built from the
+    # model rows must return x from J x exactly (up to rounding)
+    from oracle.mlp import factor_dims, lowrank_apply, woodbury
+    M, K, N, R = 2, 2, 4, 2
+    nk, n3 = 2 * K - 1, 3 * N
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal((n3, R)) + 1j * rng.standard_normal((n3, R))
+    V = 0.2 * (rng.standard_normal((n3, R)) + 1j * rng.standard_normal((n3, R)))
+    q = 1 * nk + 2  # mode m = 1, k = +1
+    F = np.zeros((M * nk, factor_dims(N, R)))
+    F[q, 0:2 * n3 * R:2], F[q, 1:2 * n3 * R:2] = U.reshape(-1).real, U.reshape(-1).imag
+    F[q, 2 * n3 * R:4 * n3 * R:2], F[q, 2 * n3 * R + 1:4 * n3 * R:2] = V.reshape(-1).real, V.reshape(-1).imag
+    x = rng.standard_normal(n3) + 1j * rng.standard_normal(n3)
+    jx = -x + U @ (np.conj(V).T @ x)
+    v = np.zeros((3, M, nk, N), dtype=complex)
+    v[:, 1, 2, :] = jx.reshape(3, N)
+    z = lowrank_apply(woodbury(F, N, R), v, R)
+    assert np.max(np.abs(z[:, 1, 2, :].reshape(-1) - x)) <= 1e-12 * np.max(np.abs(x))
+    # modes with a zero model are left at P = -I
+    assert np.all(z[:, 0] == 0) and np.all(z[:, 1, 0] == 0)
+
+
+def test_head_gradient_matches_finite_differences():
+    from oracle.mlp import factor_dims, head
+    M, K, N, R = 2, 2, 4, 2
+    rows = M * (2 * K - 1)
+    rng = np.random.default_rng(9)
+    F = 0.3 * rng.standard_normal((rows, factor_dims(N, R)))
+    pairs = np.stack([np.stack([_field(20 + i, M, K, N), _field(30 + i, M, K, N)]) for i in range(3)])
+    L0, dF = head(F, pairs, R)
+    assert L0 > 0
+    h = 1e-6
+    for idx in [(0, 0), (1, 7), (3, 3 * N * R * 2 + 5), (5, 4 * 3 * N * R - 1)]:
+        Fp, Fm = F.copy(), F.copy()
+        Fp[idx] += h
+        Fm[idx] -= h
+        fd = (head(Fp, pairs, R)[0] - head(Fm, pairs, R)[0]) / (2 * h)
+        assert abs(fd - dF[idx]) <= 1e-7 * max(1.0, abs(fd)), (idx, fd, dF[idx])
+
+
+def test_feature_rows():
+    from oracle.mlp import cond_features, feature_rows
+    X = feature_rows(3, 4, 2, 1.25)
+    assert X.shape == (3 * 7, 32)
     f = cond_features(1, 1, 2, 1.25)
-    assert np.array_equal(X[q, p6:], f)
-    assert f[0] == 1 and f[9] == 1 and f[24] == 1 and f[31] == 0 and f.sum() > 3
+    assert np.array_equal(X[1 * 7 + 4], f)
+    assert f[0] == 1 and f[9] == 1 and f[24] == 1 and f[31] == 0
+    assert abs(f[1] - 2 / 48) < 1e-15 and abs(f[2] - 1.25 / 40) < 1e-15 and f[4] == 1
+    g = cond_features(9, -8, 2, 1.25)
+    assert g[31] == 1 and np.all(g[8:31] == 0) and g[4] == -1
