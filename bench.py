@@ -106,7 +106,7 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     return (t1 - t0) / steps, prof, diag
 
 
-def run_nk(w, gmres_m=40, probes=320, rank=8, train_steps=6000, batch=16):
+def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
     near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain,

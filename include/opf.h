@@ -314,7 +314,7 @@ opf_status opf_mlp_pair_gradient(opf_ctx* ctx, opf_mlp* net, const void* pairs_d
                                  const int32_t* idx_host, int32_t batch, double* loss_host, float* grad_host);
 /* Adam on the pair loss: `steps` steps of `batch` pairs, taken in order from
  * per-epoch shuffles (seed) of the npairs pairs; loss_host[steps] (or NULL)
- * gets each step's loss.  batch * steps <= 65536.  Synchronises. */
+ * gets each step's loss.  steps <= 65536, batch * steps <= 2^20.  Synchronises. */
 opf_status opf_mlp_train_pairs(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs, int32_t batch,
                                int32_t steps, uint64_t seed, float* loss_host);
 /* The preconditioner's factor rows (A, B) for the grid's modes (host FP32

@@ -655,7 +655,8 @@ struct opf_mlp {
 
 namespace {
 
-constexpr int LOSS_CAP = 1 << 16;  // training steps per call, and pair indices per call
+constexpr int LOSS_CAP = 1 << 16;  // training steps per call
+constexpr int IDX_CAP = 1 << 20;   // pair indices per call (steps x batch)
 
 #define MCHK(net, call)                                                             \
     do {                                                                            \
@@ -725,7 +726,7 @@ Layout plan(opf_mlp* m) {
     lay.take(R * H * 2);                           // dZT
     lay.take(R * m->din * 4);                      // fx: mode feature rows
     lay.take(R * m->dout * 4);                     // fac: factor rows in use
-    lay.take((size_t)LOSS_CAP * 4);                // idx: pair indices
+    lay.take((size_t)IDX_CAP * 4);                 // idx: pair indices
     lay.take(R * 4);                               // singular: per-mode flag of a singular G
     lay.take(R * 4);                               // lrow
     lay.take(256);                                 // wsum
@@ -1172,7 +1173,7 @@ opf_status opf_mlp_train(opf_mlp* net, const float* x_dev, const float* t_dev, c
 
 opf_status opf_mlp_pair_gradient(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs,
                                  const int32_t* idx_host, int32_t batch, double* loss_host, float* grad_host) {
-    if (!ctx || !net || !pairs_dev || !idx_host || npairs < 1 || batch < 1 || batch > LOSS_CAP) return OPF_E_INVALID;
+    if (!ctx || !net || !pairs_dev || !idx_host || npairs < 1 || batch < 1 || batch > IDX_CAP) return OPF_E_INVALID;
     if (!same_grid(net, ctx)) return OPF_E_INVALID;
     for (int b = 0; b < batch; ++b)
         if (idx_host[b] < 0 || idx_host[b] >= npairs) return OPF_E_INVALID;
@@ -1191,7 +1192,7 @@ opf_status opf_mlp_pair_gradient(opf_ctx* ctx, opf_mlp* net, const void* pairs_d
 opf_status opf_mlp_train_pairs(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev, int32_t npairs, int32_t batch,
                                int32_t steps, uint64_t seed, float* loss_host) {
     if (!ctx || !net || !pairs_dev || npairs < 1 || batch < 1 || steps < 0) return OPF_E_INVALID;
-    if ((long)batch * steps > LOSS_CAP || steps > net->loss_cap) return OPF_E_INVALID;
+    if ((long)batch * steps > IDX_CAP || steps > net->loss_cap) return OPF_E_INVALID;
     if (!same_grid(net, ctx)) return OPF_E_INVALID;
     // pair indices of every step: consecutive batches of per-epoch shuffles
     std::vector<int> idx((size_t)batch * steps);
