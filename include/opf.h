@@ -272,7 +272,7 @@ opf_status opf_probe_pairs(opf_ctx* ctx, const void* x_dev, double T, double shi
 typedef struct {
     int32_t width;      /* H: multiple of 32 in [32, 512] (256)              */
     int32_t layers;     /* L: 1..8 (4)                                       */
-    int32_t rank;       /* R: 1..32 with 48 N R <= 65536 (8)                 */
+    int32_t rank;       /* R: 1..32 with 3 N R <= 3072 (8)                   */
     int32_t max_rows;   /* rows of the plain row calls (>= mode count used)  */
     uint64_t seed;      /* initial weights (SplitMix64 uniforms)             */
     float lr, beta1, beta2, adam_eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8)      */

@@ -184,26 +184,37 @@ __global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ lr
     if (threadIdx.x == 0) *out = (((part[0] + part[1]) + part[2]) + part[3]) / *wsum;
 }
 
-// out[col] = sum_{row < rows} src[row][col] (times [mask > 0] when mask is
-// given); 32 columns per workgroup, 8 row groups summed in a fixed order.
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ src, const float* __restrict__ mask,
-                                                int rows, int ld, float* __restrict__ out) {
-    __shared__ float part[8][32];
+// Column sums in two passes (bias gradients):
+// part[c][col] = sum over rows c*ch .. c*ch+ch-1 (< rows) of src[row][col]
+// (times [mask > 0] when mask is given), 32 columns x 8 row groups per
+// workgroup; then out[col] = sum_c part[c][col] in order.  Deterministic.
+constexpr int CS_CHUNKS = 64;  // largest number of row chunks
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ src, const float* __restrict__ mask,
+                                                     int rows, int ld, int ch, float* __restrict__ part) {
+    __shared__ float red[8][32];
     const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
     const int col = blockIdx.x * 32 + c;
+    const int r0 = blockIdx.y * ch, r1 = min(rows, r0 + ch);
     float s = 0.0f;
-    for (int r = g; r < rows; r += 8) {
+    for (int r = r0 + g; r < r1; r += 8) {
         const size_t i = (size_t)r * ld + col;
         const float v = src[i];
         s += (!mask || mask[i] > 0.0f) ? v : 0.0f;
     }
-    part[g][c] = s;
+    red[g][c] = s;
     __syncthreads();
     if (g == 0) {
         float t = 0.0f;
-        for (int q = 0; q < 8; ++q) t += part[q][c];
-        out[col] = t;
+        for (int q = 0; q < 8; ++q) t += red[q][c];
+        part[(size_t)blockIdx.y * ld + col] = t;
     }
+}
+__global__ void k_colsum_fin(const float* __restrict__ part, int nch, int ld, float* __restrict__ out) {
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= ld) return;
+    float t = 0.0f;
+    for (int c = 0; c < nch; ++c) t += part[(size_t)c * ld + col];
+    out[col] = t;
 }
 
 // Parameter segments: weight matrices [rows][cols] and bias vectors.
@@ -368,136 +379,154 @@ struct HeadArgs {
     float scale;  // 1 / (batch rows)
 };
 
+constexpr int HB = 8;             // pairs staged per pass of the loss head
+constexpr int HOUT = 12;          // gradient outputs per thread and factor: 3N R <= 256 HOUT
+constexpr int HMAX3N = 3 * 64;    // profile length bound (N <= 64)
+
 // Loss head of the training pairs: the network's factors U = A, V = B model
 // the Jacobian on each mode, J_q ~ -I + U V^H.  For mode q and pair p:
 // s = RMS of the z_q profile (pairs with s = 0 skip), xhat = z_q / s,
 // that = (J z)_q / s, c = V^H xhat, r = -xhat + U c - that;
 // loss = scale sum |r|^2, dU = 2 scale sum r c^H, dV = 2 scale sum xhat (U^H r)^H.
-// In the code y is the input profile (xhat) and z the target (that).  One
-// workgroup of one wave per row; the row's factors are staged in LDS and the
-// gradient is accumulated in place of the row in Y (each lane owns its
-// elements e).
-__global__ __launch_bounds__(64) void k_head(HeadArgs a) {
-    extern __shared__ float fl[];  // the row's factors, dout floats
-    __shared__ double cg[4 * RMAX];
-    const int q = blockIdx.x, lane = threadIdx.x;
+// One workgroup of 256 threads per row.  Pairs pass through LDS HB at a time
+// (FP32); per pass the products C = V^H X, R = -X + U C - T, G = U^H R are
+// formed by threads over their outputs, and dU += R C^H, dV += X G^H stay in
+// registers (each thread owns fixed gradient entries) until the row is
+// written once: dY in FP32 and its bfloat16 copies.
+__global__ __launch_bounds__(256) void k_head(HeadArgs a) {
+    __shared__ float xs[HB][HMAX3N][2];  // xhat, then kept for dV
+    __shared__ float rs[HB][HMAX3N][2];  // that, then the residual r
+    __shared__ float cs[HB][RMAX][2];
+    __shared__ float gs[HB][RMAX][2];
+    __shared__ float sinv[HB];
+    __shared__ float lpart[4];
+    const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     float* yrow = a.Y + (long)q * a.dout;
-    const int n3 = 3 * a.N;
-    const int nf = 12 * a.N * a.rank;
+    const int n3 = 3 * a.N, R = a.rank, nf = n3 * R;  // complex entries of U (and of V)
     if (q >= a.rows) {  // padding rows: zero gradient
-        for (int j = lane; j < a.dout; j += 64) {
+        for (int j = t; j < a.dout; j += 256) {
             yrow[j] = 0.0f;
             a.dyb[(long)q * a.dout + j] = 0;
             a.dyt[(long)j * a.ldt + q] = 0;
         }
-        if (lane == 0) a.lrow[q] = 0.0f;
+        if (t == 0) a.lrow[q] = 0.0f;
         return;
     }
-    for (int j = lane; j < a.dout; j += 64) {
-        fl[j] = yrow[j];
-        yrow[j] = 0.0f;
-    }
-    __syncthreads();
-    const float* A = fl;
-    const float* B = fl + nf / 2;
-    float* dA = yrow;
-    float* dB = yrow + nf / 2;
+    const float* U = yrow;
+    const float* V = yrow + 2 * nf;
     const long S = (long)a.M * a.nk * a.N;
-    const int R = a.rank;
-    double lsum = 0.0;
-    for (int b = 0; b < a.batch; ++b) {
-        const double* yv = a.pairs + (long)a.idx[b] * 2 * a.vec;  // z: the model's input
-        const double* zv = yv + a.vec;                              // J z: its target
-        double yr[3], yi[3], zr[3], zi[3];
-        double s2 = 0.0;
-        for (int t = 0; t < 3; ++t) {
-            const int e = lane + 64 * t;
-            yr[t] = yi[t] = zr[t] = zi[t] = 0.0;
-            if (e < n3) {
-                const long idx = (e / a.N) * S + (long)q * a.N + e % a.N;
-                yr[t] = yv[2 * idx];
-                yi[t] = yv[2 * idx + 1];
-                zr[t] = zv[2 * idx];
-                zi[t] = zv[2 * idx + 1];
-                s2 += yr[t] * yr[t] + yi[t] * yi[t];
+    float du[HOUT][2], dv[HOUT][2];
+#pragma unroll
+    for (int o = 0; o < HOUT; ++o) du[o][0] = du[o][1] = dv[o][0] = dv[o][1] = 0.0f;
+    float lsum = 0.0f;
+    for (int b0 = 0; b0 < a.batch; b0 += HB) {
+        const int nb = min(HB, a.batch - b0);
+        for (int i = t; i < nb * n3; i += 256) {  // stage z and J z profiles of mode q
+            const int b = i / n3, e = i % n3;
+            const double* zv = a.pairs + (long)a.idx[b0 + b] * 2 * a.vec;
+            const long idx = (e / a.N) * S + (long)q * a.N + e % a.N;
+            xs[b][e][0] = (float)zv[2 * idx];
+            xs[b][e][1] = (float)zv[2 * idx + 1];
+            rs[b][e][0] = (float)zv[a.vec + 2 * idx];
+            rs[b][e][1] = (float)zv[a.vec + 2 * idx + 1];
+        }
+        __syncthreads();
+        for (int b = w; b < nb; b += 4) {  // s of each pair: one wave per pair
+            float s2 = 0.0f;
+            for (int e = lane; e < n3; e += 64) s2 += xs[b][e][0] * xs[b][e][0] + xs[b][e][1] * xs[b][e][1];
+            s2 = wave_sum(s2);
+            if (lane == 0) sinv[b] = s2 > 0.0f ? 1.0f / sqrtf(s2 / n3) : 0.0f;
+        }
+        __syncthreads();
+        for (int i = t; i < nb * n3; i += 256) {
+            const int b = i / n3, e = i % n3;
+            const float f = sinv[b];
+            xs[b][e][0] *= f;
+            xs[b][e][1] *= f;
+            rs[b][e][0] *= f;
+            rs[b][e][1] *= f;
+        }
+        __syncthreads();
+        for (int i = t; i < nb * R; i += 256) {  // C = V^H X
+            const int b = i / R, j = i % R;
+            float cr = 0.0f, ci = 0.0f;
+            for (int e = 0; e < n3; ++e) {
+                const float vr = V[2 * (e * R + j)], vi = V[2 * (e * R + j) + 1];
+                const float xr = xs[b][e][0], xi = xs[b][e][1];
+                cr += vr * xr + vi * xi;
+                ci += vr * xi - vi * xr;
             }
+            cs[b][j][0] = cr;
+            cs[b][j][1] = ci;
         }
-        s2 = wave_sum(s2);
-        if (!(s2 > 0.0)) continue;
-        const double inv = 1.0 / sqrt(s2 / n3);
-        for (int t = 0; t < 3; ++t) {
-            yr[t] *= inv;
-            yi[t] *= inv;
-            zr[t] *= inv;
-            zi[t] *= inv;
+        __syncthreads();
+        for (int i = t; i < nb * n3; i += 256) {  // r = -x + U c - that
+            const int b = i / n3, e = i % n3;
+            float pr = -xs[b][e][0] - rs[b][e][0], pi = -xs[b][e][1] - rs[b][e][1];
+            for (int j = 0; j < R; ++j) {
+                const float ur = U[2 * (e * R + j)], ui = U[2 * (e * R + j) + 1];
+                pr += ur * cs[b][j][0] - ui * cs[b][j][1];
+                pi += ur * cs[b][j][1] + ui * cs[b][j][0];
+            }
+            rs[b][e][0] = pr;
+            rs[b][e][1] = pi;
+            lsum += pr * pr + pi * pi;
         }
-        for (int j = 0; j < R; ++j) {  // c = B^H yhat
-            double cr = 0.0, ci = 0.0;
-            for (int t = 0; t < 3; ++t) {
-                const int e = lane + 64 * t;
-                if (e < n3) {
-                    const double br = B[2 * (e * R + j)], bi = B[2 * (e * R + j) + 1];
-                    cr += br * yr[t] + bi * yi[t];
-                    ci += br * yi[t] - bi * yr[t];
+        __syncthreads();
+        for (int i = t; i < nb * R; i += 256) {  // G = U^H r
+            const int b = i / R, j = i % R;
+            float gr = 0.0f, gi = 0.0f;
+            for (int e = 0; e < n3; ++e) {
+                const float ur = U[2 * (e * R + j)], ui = U[2 * (e * R + j) + 1];
+                const float rr = rs[b][e][0], ri = rs[b][e][1];
+                gr += ur * rr + ui * ri;
+                gi += ur * ri - ui * rr;
+            }
+            gs[b][j][0] = gr;
+            gs[b][j][1] = gi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < HOUT; ++o) {  // dU += r c^H, dV += x g^H on this thread's entries
+            const int i = t + 256 * o;
+            if (i < nf) {
+                const int e = i / R, j = i % R;
+                for (int b = 0; b < nb; ++b) {
+                    const float rr = rs[b][e][0], ri = rs[b][e][1], cr = cs[b][j][0], ci = cs[b][j][1];
+                    du[o][0] += rr * cr + ri * ci;
+                    du[o][1] += ri * cr - rr * ci;
+                    const float xr = xs[b][e][0], xi = xs[b][e][1], gr = gs[b][j][0], gi = gs[b][j][1];
+                    dv[o][0] += xr * gr + xi * gi;
+                    dv[o][1] += xi * gr - xr * gi;
                 }
             }
-            cg[2 * j] = wave_sum(cr);  // same value in every lane; each reads its own store
-            cg[2 * j + 1] = wave_sum(ci);
         }
-        double rr[3], ri[3];
-        double l = 0.0;
-        for (int t = 0; t < 3; ++t) {  // r = -yhat + A c - zhat
-            const int e = lane + 64 * t;
-            rr[t] = ri[t] = 0.0;
-            if (e >= n3) continue;
-            double pr = -yr[t] - zr[t], pi = -yi[t] - zi[t];
-            for (int j = 0; j < R; ++j) {
-                const double ar = A[2 * (e * R + j)], ai = A[2 * (e * R + j) + 1];
-                pr += ar * cg[2 * j] - ai * cg[2 * j + 1];
-                pi += ar * cg[2 * j + 1] + ai * cg[2 * j];
-            }
-            rr[t] = pr;
-            ri[t] = pi;
-            l += pr * pr + pi * pi;
-        }
-        lsum += l;
-        for (int j = 0; j < R; ++j) {  // g = A^H r
-            double gr = 0.0, gi = 0.0;
-            for (int t = 0; t < 3; ++t) {
-                const int e = lane + 64 * t;
-                if (e < n3) {
-                    const double ar = A[2 * (e * R + j)], ai = A[2 * (e * R + j) + 1];
-                    gr += ar * rr[t] + ai * ri[t];
-                    gi += ar * ri[t] - ai * rr[t];
-                }
-            }
-            cg[2 * RMAX + 2 * j] = wave_sum(gr);
-            cg[2 * RMAX + 2 * j + 1] = wave_sum(gi);
-        }
-        for (int t = 0; t < 3; ++t) {  // dA += 2 r conj(c), dB += 2 yhat conj(g) (own elements only)
-            const int e = lane + 64 * t;
-            if (e >= n3) continue;
-            for (int j = 0; j < R; ++j) {
-                const double cr = cg[2 * j], ci = cg[2 * j + 1];
-                const double gr = cg[2 * RMAX + 2 * j], gi = cg[2 * RMAX + 2 * j + 1];
-                float* pa = dA + 2 * (e * R + j);
-                float* pb = dB + 2 * (e * R + j);
-                pa[0] += (float)(2.0 * (rr[t] * cr + ri[t] * ci));
-                pa[1] += (float)(2.0 * (ri[t] * cr - rr[t] * ci));
-                pb[0] += (float)(2.0 * (yr[t] * gr + yi[t] * gi));
-                pb[1] += (float)(2.0 * (yi[t] * gr - yr[t] * gi));
+        __syncthreads();
+    }
+    lsum = wave_sum(lsum);
+    if (lane == 0) lpart[w] = lsum;
+    __syncthreads();  // every read of this row's factors is done: the row can take dY
+    if (t == 0) a.lrow[q] = ((lpart[0] + lpart[1]) + lpart[2]) + lpart[3];
+    const float g2 = 2.0f * a.scale;
+#pragma unroll
+    for (int o = 0; o < HOUT; ++o) {
+        const int i = t + 256 * o;
+        if (i < nf) {
+            const float vals[4] = {g2 * du[o][0], g2 * du[o][1], g2 * dv[o][0], g2 * dv[o][1]};
+            const int cols[4] = {2 * i, 2 * i + 1, 2 * nf + 2 * i, 2 * nf + 2 * i + 1};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                yrow[cols[c]] = vals[c];
+                const bf16_t hb = f2bf(vals[c]);
+                a.dyb[(long)q * a.dout + cols[c]] = hb;
+                a.dyt[(long)cols[c] * a.ldt + q] = hb;
             }
         }
     }
-    __syncthreads();  // the final pass reads elements other lanes accumulated
-    lsum = wave_sum(lsum);
-    if (lane == 0) a.lrow[q] = (float)lsum;
-    for (int j = lane; j < a.dout; j += 64) {
-        const float g = j < nf ? yrow[j] * a.scale : 0.0f;
-        yrow[j] = g;
-        const bf16_t hb = f2bf(g);
-        a.dyb[(long)q * a.dout + j] = hb;
-        a.dyt[(long)j * a.ldt + q] = hb;
+    for (int j = 4 * nf + t; j < a.dout; j += 256) {
+        yrow[j] = 0.0f;
+        a.dyb[(long)q * a.dout + j] = 0;
+        a.dyt[(long)j * a.ldt + q] = 0;
     }
 }
 
@@ -642,6 +671,7 @@ struct opf_mlp {
     float *fx = nullptr, *fac = nullptr;
     int* idx = nullptr;
     int* singular = nullptr;  // [rows] modes whose Woodbury matrix is singular
+    float* part = nullptr;    // [CS_CHUNKS][max(H, dout)] column-sum partials
     int n_singular = 0;
     float *lrow = nullptr, *wsum = nullptr, *losses = nullptr;
     int loss_cap = 0;
@@ -728,6 +758,7 @@ Layout plan(opf_mlp* m) {
     lay.take(R * m->dout * 4);                     // fac: factor rows in use
     lay.take((size_t)IDX_CAP * 4);                 // idx: pair indices
     lay.take(R * 4);                               // singular: per-mode flag of a singular G
+    lay.take((size_t)CS_CHUNKS * std::max(m->H, m->dout) * 4);  // part
     lay.take(R * 4);                               // lrow
     lay.take(256);                                 // wsum
     lay.take((size_t)LOSS_CAP * 4);                // losses
@@ -744,12 +775,21 @@ opf_status check_cfg(const opf_ctx* c, const opf_mlp_config* cfg, std::string* w
     if (cfg->width < 32 || cfg->width > 512 || cfg->width % 32) return bad("width must be a multiple of 32 in [32, 512]");
     if (cfg->layers < 1 || cfg->layers > MAXL) return bad("layers must be in [1, 8]");
     if (cfg->rank < 1 || cfg->rank > RMAX) return bad("rank must be in [1, 32]");
-    if (12L * p.N * cfg->rank * 4 > 65536) return bad("12 N rank factors of a mode must fit 64 KiB of LDS");
+    if (3L * p.N * cfg->rank > 256L * HOUT) return bad("3 N rank must not exceed 3072");
     if (cfg->max_rows < 0 || cfg->max_rows > (1 << 20)) return bad("max_rows must be in [0, 2^20]");
     if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
         !(cfg->adam_eps > 0.0f))
         return bad("bad Adam parameters");
     return OPF_OK;
+}
+
+// Column sums of rows x cols FP32 src (row stride = cols) into out.
+hipError_t colsum(opf_mlp* m, const float* src, const float* mask, int rows, int cols, float* out) {
+    const int ch = std::max(128, (rows + CS_CHUNKS - 1) / CS_CHUNKS);
+    const int nch = (rows + ch - 1) / ch;
+    hipLaunchKernelGGL(k_colsum_part, dim3(cols / 32, nch), dim3(256), 0, m->s, src, mask, rows, cols, ch, m->part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((cols + 255) / 256), dim3(256), 0, m->s, m->part, nch, cols, out);
+    return hipGetLastError();
 }
 
 hipError_t gemm(hipStream_t s, const bf16_t* A, int lda, const bf16_t* B, int ldb, int rows, int cols, int K,
@@ -813,8 +853,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
         e.out = m->G + m->woff[L + 1];
         e.ldo = H;
         if ((st = gemm(s, m->dYT, R, m->ht(L), R, dout, H, rp, e)) != hipSuccess) return st;
-        hipLaunchKernelGGL(k_colsum, dim3(dout / 32), dim3(256), 0, s, m->Y, nullptr, rp, dout,
-                           m->G + m->boff[L + 1]);
+        if ((st = colsum(m, m->Y, nullptr, rp, dout, m->G + m->boff[L + 1])) != hipSuccess) return st;
         Epi f{};
         f.out = m->dH;
         f.ldo = H;
@@ -831,7 +870,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
     int cur = 0;
     for (int l = L - 1; l >= 0; --l) {
         // dz_l = dH_{l+1} [z_l > 0] is in dz[cur] (row-major) and dZT (transposed)
-        hipLaunchKernelGGL(k_colsum, dim3(H / 32), dim3(256), 0, s, m->dH, m->z(l), rp, H, m->G + m->boff[l + 1]);
+        if ((st = colsum(m, m->dH, m->z(l), rp, H, m->G + m->boff[l + 1])) != hipSuccess) return st;
         Epi e{};
         e.out = m->G + m->woff[l + 1];
         e.ldo = H;
@@ -854,7 +893,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
         cur ^= 1;
     }
     // input layer: dW_in = dH_0^T X, db_in = colsum dH_0
-    hipLaunchKernelGGL(k_colsum, dim3(H / 32), dim3(256), 0, s, m->dH, nullptr, rp, H, m->G + m->boff[0]);
+    if ((st = colsum(m, m->dH, nullptr, rp, H, m->G + m->boff[0])) != hipSuccess) return st;
     Epi e{};
     e.out = m->G + m->woff[0];
     e.ldo = m->din;
@@ -897,7 +936,7 @@ hipError_t backward_pairs(opf_mlp* m, const double* pairs, const int* idx, int b
     a.ldt = m->R;
     a.lrow = m->lrow;
     a.scale = (float)(1.0 / ((double)batch * m->mode_rows));
-    hipLaunchKernelGGL(k_head, dim3(rp), dim3(64), (size_t)m->dout * 4, s, a);
+    hipLaunchKernelGGL(k_head, dim3(rp), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_weight_sum, dim3(1), dim3(256), 0, s, nullptr, batch * m->mode_rows, m->wsum);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lrow, m->mode_rows, m->wsum, loss_slot);
     const hipError_t st = hipGetLastError();
@@ -1046,6 +1085,7 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
     at(m->fac);
     at(m->idx);
     at(m->singular);
+    at(m->part);
     at(m->lrow);
     at(m->wsum);
     at(m->losses);
