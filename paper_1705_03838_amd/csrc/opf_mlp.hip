@@ -67,48 +67,81 @@ struct Epi {
     int ldt;
 };
 
+__device__ __forceinline__ void epilogue(const Epi& e, int row, int col, float s) {
+    float v = s + (e.bias ? e.bias[col] : 0.0f);
+    if (e.zout) e.zout[(size_t)row * e.ldz + col] = v;
+    if (e.mode == EPI_RELU_RES)
+        v = e.res[(size_t)row * e.ldr + col] + fmaxf(v, 0.0f);
+    else if (e.mode == EPI_ADD)
+        v = e.res[(size_t)row * e.ldr + col] + v;
+    if (e.out) e.out[(size_t)row * e.ldo + col] = v;
+    float w = v;
+    if (e.mask && !(e.mask[(size_t)row * e.ldm + col] > 0.0f)) w = 0.0f;
+    if (e.outb) e.outb[(size_t)row * e.ldb + col] = f2bf(w);
+    if (e.outT) e.outT[(size_t)col * e.ldt + row] = f2bf(w);
+}
+
 // C[rows][cols] = A[rows][K] B[cols][K]^T on v_mfma_f32_32x32x16_bf16.
-// One workgroup per 32x32 tile of C; its four waves split K (wave w takes
-// the 16-wide slices w, w+4, ...) and their partial tiles are summed in LDS
-// in a fixed order.  Lane l of a wave supplies row l%32 of the A slice and
-// row l%32 of the B slice, elements 8*(l/32)..+7 (the operand layout of the
-// instruction); accumulator entry i of lane l is C[8(i/4) + 4(l/32) + i%4][l%32].
-// Requires rows, cols multiples of 32, K of 16, lda, ldb multiples of 8.
+// One workgroup per 32x32 tile of C; its four waves split the workgroup's
+// K range [k_begin, k_end) (wave w takes the 16-wide slices w, w+4, ...) and
+// their partial tiles are summed in LDS in a fixed order.  Lane l of a wave
+// supplies row l%32 of the A slice and row l%32 of the B slice, elements
+// 8*(l/32)..+7 (the operand layout of the instruction); accumulator entry i
+// of lane l is C[8(i/4) + 4(l/32) + i%4][l%32].  The next slice's operands
+// are loaded before the current product is issued.  Without a split
+// (part == null) the tile goes through the epilogue; with a split over
+// gridDim.z ranges of kc, workgroup z writes its raw partial tile to
+// part[z][rows][cols] for k_gemm_reduce.
+// Requires rows, cols multiples of 32, K and kc of 16, lda, ldb multiples of 8.
 __global__ __launch_bounds__(256) void k_gemm(const bf16_t* __restrict__ A, int lda, const bf16_t* __restrict__ B,
-                                              int ldb, int K, Epi e) {
+                                              int ldb, int K, int kc, Epi e, float* __restrict__ part) {
     __shared__ float red[4][16][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int rr = lane & 31, kq = (lane >> 5) * 8;
+    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
     f32x16 acc = {};
     const bf16_t* ap = A + (size_t)(m0 + rr) * lda + kq;
     const bf16_t* bp = B + (size_t)(n0 + rr) * ldb + kq;
-    for (int k0 = wv * 16; k0 < K; k0 += 64) {
-        const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + k0));
-        const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bp + k0));
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    int k0 = kb + wv * 16;
+    u32x4 an = {}, bn = {};
+    if (k0 < ke) {
+        an = *reinterpret_cast<const u32x4*>(ap + k0);
+        bn = *reinterpret_cast<const u32x4*>(bp + k0);
+    }
+    for (; k0 < ke; k0 += 64) {
+        const u32x4 ac = an, bc = bn;
+        if (k0 + 64 < ke) {
+            an = *reinterpret_cast<const u32x4*>(ap + k0 + 64);
+            bn = *reinterpret_cast<const u32x4*>(bp + k0 + 64);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ac), __builtin_bit_cast(bf16x8, bc),
+                                                      acc, 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) red[wv][i][lane] = acc[i];
     __syncthreads();
+    const int cols = gridDim.x * GT, rows = gridDim.y * GT;
     for (int q = threadIdx.x; q < 1024; q += 256) {
         const int i = q >> 6, l = q & 63;
         const float s = ((red[0][i][l] + red[1][i][l]) + red[2][i][l]) + red[3][i][l];
         const int row = m0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
         const int col = n0 + (l & 31);
-        float v = s + (e.bias ? e.bias[col] : 0.0f);
-        if (e.zout) e.zout[(size_t)row * e.ldz + col] = v;
-        if (e.mode == EPI_RELU_RES)
-            v = e.res[(size_t)row * e.ldr + col] + fmaxf(v, 0.0f);
-        else if (e.mode == EPI_ADD)
-            v = e.res[(size_t)row * e.ldr + col] + v;
-        if (e.out) e.out[(size_t)row * e.ldo + col] = v;
-        float w = v;
-        if (e.mask && !(e.mask[(size_t)row * e.ldm + col] > 0.0f)) w = 0.0f;
-        if (e.outb) e.outb[(size_t)row * e.ldb + col] = f2bf(w);
-        if (e.outT) e.outT[(size_t)col * e.ldt + row] = f2bf(w);
+        if (part)
+            part[((size_t)blockIdx.z * rows + row) * cols + col] = s;
+        else
+            epilogue(e, row, col, s);
     }
+}
+
+// Sum of the split partial tiles in order, then the epilogue.
+__global__ void k_gemm_reduce(const float* __restrict__ part, int rows, int cols, int nsplit, Epi e) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)rows * cols) return;
+    float s = 0.0f;
+    for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * rows * cols + i];
+    epilogue(e, (int)(i / cols), (int)(i % cols), s);
 }
 
 // FP32 rows [nrows][d] -> bfloat16 rows [rp][d] and transposed [d][ldt];
@@ -189,6 +222,8 @@ __global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ lr
 // (times [mask > 0] when mask is given), 32 columns x 8 row groups per
 // workgroup; then out[col] = sum_c part[c][col] in order.  Deterministic.
 constexpr int CS_CHUNKS = 64;  // largest number of row chunks
+constexpr int GSPLIT = 8;                     // largest K split of a GEMM
+constexpr size_t GPART = (size_t)1 << 23;     // floats of split partial tiles (split x rows x cols)
 __global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ src, const float* __restrict__ mask,
                                                      int rows, int ld, int ch, float* __restrict__ part) {
     __shared__ float red[8][32];
@@ -672,6 +707,7 @@ struct opf_mlp {
     int* idx = nullptr;
     int* singular = nullptr;  // [rows] modes whose Woodbury matrix is singular
     float* part = nullptr;    // [CS_CHUNKS][max(H, dout)] column-sum partials
+    float* gpart = nullptr;   // [GPART] split-K partial tiles
     int n_singular = 0;
     float *lrow = nullptr, *wsum = nullptr, *losses = nullptr;
     int loss_cap = 0;
@@ -759,6 +795,7 @@ Layout plan(opf_mlp* m) {
     lay.take((size_t)IDX_CAP * 4);                 // idx: pair indices
     lay.take(R * 4);                               // singular: per-mode flag of a singular G
     lay.take((size_t)CS_CHUNKS * std::max(m->H, m->dout) * 4);  // part
+    lay.take(GPART * 4);                                         // gpart
     lay.take(R * 4);                               // lrow
     lay.take(256);                                 // wsum
     lay.take((size_t)LOSS_CAP * 4);                // losses
@@ -792,11 +829,31 @@ hipError_t colsum(opf_mlp* m, const float* src, const float* mask, int rows, int
     return hipGetLastError();
 }
 
-hipError_t gemm(hipStream_t s, const bf16_t* A, int lda, const bf16_t* B, int ldb, int rows, int cols, int K,
+// Launch a GEMM; one whose tile count cannot fill the chip but whose K is
+// long is split over K (partial tiles to the scratch, then k_gemm_reduce).
+hipError_t gemm(opf_mlp* m, const bf16_t* A, int lda, const bf16_t* B, int ldb, int rows, int cols, int K,
                 const Epi& e) {
     if (rows % GT || cols % GT || K % 16 || lda % 8 || ldb % 8 || rows <= 0 || cols <= 0 || K <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm, dim3(cols / GT, rows / GT), dim3(256), 0, s, A, lda, B, ldb, K, e);
+    const long tiles = (long)(rows / GT) * (cols / GT);
+    int nsplit = 1, kc = K;
+    if (tiles < 1024 && K >= 512) {
+        nsplit = (int)std::min<long>((2048 + tiles - 1) / tiles, std::min(K / 256, GSPLIT));
+        kc = (K + nsplit - 1) / nsplit;
+        kc = (kc + 63) / 64 * 64;
+        nsplit = (K + kc - 1) / kc;
+        if ((size_t)nsplit * rows * cols > GPART) nsplit = 1, kc = K;
+    }
+    if (nsplit == 1) {
+        hipLaunchKernelGGL(k_gemm, dim3(cols / GT, rows / GT, 1), dim3(256), 0, m->s, A, lda, B, ldb, K, K, e,
+                           nullptr);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_gemm, dim3(cols / GT, rows / GT, nsplit), dim3(256), 0, m->s, A, lda, B, ldb, K, kc, e,
+                       m->gpart);
+    const size_t n = (size_t)rows * cols;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, m->s, m->gpart, rows, cols,
+                       nsplit, e);
     return hipGetLastError();
 }
 
@@ -814,7 +871,7 @@ hipError_t forward(opf_mlp* m, int rp, bool train) {
         e.outT = m->ht(0);
         e.ldt = m->R;
     }
-    hipError_t st = gemm(m->s, m->Xb, m->din, m->Wb + m->woff[0], m->din, rp, H, m->din, e);
+    hipError_t st = gemm(m, m->Xb, m->din, m->Wb + m->woff[0], m->din, rp, H, m->din, e);
     if (st != hipSuccess) return st;
     for (int l = 0; l < L; ++l) {
         Epi f{};
@@ -832,27 +889,26 @@ hipError_t forward(opf_mlp* m, int rp, bool train) {
         f.ldo = H;
         f.outb = m->hb(l + 1);
         f.ldb = H;
-        st = gemm(m->s, m->hb(l), H, m->Wb + m->woff[l + 1], H, rp, H, H, f);
+        st = gemm(m, m->hb(l), H, m->Wb + m->woff[l + 1], H, rp, H, H, f);
         if (st != hipSuccess) return st;
     }
     Epi g{};
     g.bias = m->P + m->boff[L + 1];
     g.out = m->Y;
     g.ldo = m->dout;
-    return gemm(m->s, m->hb(L), H, m->Wb + m->woff[L + 1], H, rp, m->dout, H, g);
+    return gemm(m, m->hb(L), H, m->Wb + m->woff[L + 1], H, rp, m->dout, H, g);
 }
 
 // Parameter gradients from dL/dY (FP32 in Y, bfloat16 in dYb / dYT) after
 // forward(train = true) over rp rows.
 hipError_t backprop(opf_mlp* m, int rp) {
     const int H = m->H, L = m->L, R = m->R, dout = m->dout;
-    hipStream_t s = m->s;
     hipError_t st;
     {  // output layer: dW = dY^T H_L, db = colsum dY, dH_L = dY W_out
         Epi e{};
         e.out = m->G + m->woff[L + 1];
         e.ldo = H;
-        if ((st = gemm(s, m->dYT, R, m->ht(L), R, dout, H, rp, e)) != hipSuccess) return st;
+        if ((st = gemm(m, m->dYT, R, m->ht(L), R, dout, H, rp, e)) != hipSuccess) return st;
         if ((st = colsum(m, m->Y, nullptr, rp, dout, m->G + m->boff[L + 1])) != hipSuccess) return st;
         Epi f{};
         f.out = m->dH;
@@ -863,7 +919,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
         f.ldb = H;
         f.outT = m->dZT;
         f.ldt = R;
-        if ((st = gemm(s, m->dYb, dout, m->Wt + m->woff[L + 1], dout, rp, H, dout, f)) != hipSuccess)
+        if ((st = gemm(m, m->dYb, dout, m->Wt + m->woff[L + 1], dout, rp, H, dout, f)) != hipSuccess)
             return st;
     }
     bf16_t* dz[2] = {m->dZb0, m->dZb1};
@@ -874,7 +930,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
         Epi e{};
         e.out = m->G + m->woff[l + 1];
         e.ldo = H;
-        if ((st = gemm(s, m->dZT, R, m->ht(l), R, H, H, rp, e)) != hipSuccess) return st;
+        if ((st = gemm(m, m->dZT, R, m->ht(l), R, H, H, rp, e)) != hipSuccess) return st;
         Epi f{};
         f.mode = EPI_ADD;
         f.res = m->dH;
@@ -889,7 +945,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
             f.outb = dz[cur ^ 1];
             f.ldb = H;
         }
-        if ((st = gemm(s, dz[cur], H, m->Wt + m->woff[l + 1], H, rp, H, H, f)) != hipSuccess) return st;
+        if ((st = gemm(m, dz[cur], H, m->Wt + m->woff[l + 1], H, rp, H, H, f)) != hipSuccess) return st;
         cur ^= 1;
     }
     // input layer: dW_in = dH_0^T X, db_in = colsum dH_0
@@ -897,7 +953,7 @@ hipError_t backprop(opf_mlp* m, int rp) {
     Epi e{};
     e.out = m->G + m->woff[0];
     e.ldo = m->din;
-    if ((st = gemm(s, m->dZT, R, m->XT, R, H, m->din, rp, e)) != hipSuccess) return st;
+    if ((st = gemm(m, m->dZT, R, m->XT, R, H, m->din, rp, e)) != hipSuccess) return st;
     return hipGetLastError();
 }
 
@@ -1086,6 +1142,7 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
     at(m->idx);
     at(m->singular);
     at(m->part);
+    at(m->gpart);
     at(m->lrow);
     at(m->wsum);
     at(m->losses);
