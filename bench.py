@@ -131,14 +131,17 @@ def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
         return rep
 
     plain = search()
+    progress(f"nk plain: {plain['jvps']} jvps, {plain['wall_s']} s")
     t0 = time.perf_counter()
     lam = torch.from_numpy(laminar_state(w["N"], w["M"], w["K"], s.nodes()))
     pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11)
     probe_s = time.perf_counter() - t0
-    net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3)
+    progress(f"nk probes: {probes} in {probe_s:.1f} s")
+    net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3, lr=1e-3, lr_final=3e-5)
     t0 = time.perf_counter()
     losses = net.train_pairs(pairs, batch=batch, steps=train_steps, seed=5)
     train_s = time.perf_counter() - t0
+    progress(f"nk training: {train_steps} steps in {train_s:.1f} s")
     del pairs
     pre = search(net)
     flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
@@ -148,7 +151,8 @@ def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
            "steps_per_residual": int(round(w["T"] / w["dt"])),
            "network": {"width": 256, "layers": 4, "rank": rank, "params": net.n_params,
                        "probes": probes, "probe_s": round(probe_s, 2),
-                       "train_steps": train_steps, "batch_pairs": batch, "train_s": round(train_s, 2),
+                       "train_steps": train_steps, "batch_pairs": batch, "lr": "cosine 1e-3 -> 3e-5",
+                       "train_s": round(train_s, 2),
                        "train_step_ms": round(train_s / train_steps * 1e3, 4),
                        "train_gemm_TFLOPs_lower_bound": round(flops_step * train_steps / train_s / 1e12, 2),
                        "loss_first_last": [float(f"{losses[0]:.3e}"), float(f"{losses[-100:].mean():.3e}")]},
@@ -156,6 +160,33 @@ def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
     net.close()
     s.close()
     return out
+
+
+def profile_mlp(steps, rank=16):
+    """Training-step timing of the learned preconditioner alone on the nk grid
+    (for kernel traces): 32 random (z, J z) pairs of unit normals, batch 16,
+    20 untimed steps, then `steps` timed steps."""
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import WORKLOADS
+
+    w = WORKLOADS["nk"]
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
+    g = torch.Generator(device="cpu").manual_seed(1)
+    shape = (32, 2) + tuple(s.shape)
+    pairs = torch.complex(torch.randn(shape, generator=g, dtype=torch.float64),
+                          torch.randn(shape, generator=g, dtype=torch.float64)).cuda()
+    net = opf.Mlp(s, width=256, layers=4, rank=rank)
+    net.train_pairs(pairs, batch=16, steps=20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.train_pairs(pairs, batch=16, steps=steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    flops = mlp_train_flops(net, s.M * (2 * s.K - 1))
+    return {"mlp_train_step_ms": round(dt * 1e3, 4), "gemm_gflop_per_step": round(flops / 1e9, 2),
+            "rank": rank, "steps": steps}
 
 
 def mlp_train_flops(net, rows):
@@ -227,6 +258,11 @@ def cpu_baseline(w, nsteps=2):
                       f"untimed step; {dt:.1f} s (numpy + LAPACK dense solves)"}
 
 
+def progress(msg):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +277,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (a known byte count "
                          "for scaling HBM counters)")
+    ap.add_argument("--profile-mlp", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS training steps of the learned preconditioner (kernel traces)")
     args = ap.parse_args()
+    if args.profile_mlp:
+        print(json.dumps(profile_mlp(args.profile_mlp)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(ensemble members and Newton seeds would shard as independent units)", file=sys.stderr)
@@ -260,6 +301,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ms64, prof64, diag64 = run_gpu(w, opf.OPF_FP64, args.steps, args.warmup, args.profile_steps)
+    progress(f"fp64 {args.workload}: {ms64 * 1e3:.4f} ms/step")
 
     def roofline(prof, mixed, prec):
         """Dominant kernel by device time per step.  The predictor and
@@ -307,6 +349,7 @@ def main():
     }
     if not args.fp64_only:
         ms32, prof32, _ = run_gpu(w, opf.OPF_MIXED, args.steps, args.warmup, args.profile_steps)
+        progress(f"mixed {args.workload}: {ms32 * 1e3:.4f} ms/step")
         out["mixed"] = {"steps_per_s": round(1.0 / ms32, 2), "ms_per_step": round(ms32 * 1e3, 4),
                         "speedup_vs_fp64": round(ms64 / ms32, 3),
                         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, True) / ms32 / 1e9, 1),
@@ -314,12 +357,14 @@ def main():
                         "roofline": roofline(prof32, True, "mixed")}
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble()
+        progress(f"ensemble: {out['ensemble']['ms_per_step']} ms/step")
     if not args.no_nk:
         out["newton_krylov"] = {"workload": "nk: N=48, |m|<24 (mp=2), |k|<32, alpha=1.25, Re=2400, "
                                             "dt=0.01, T=20, near-laminar seed 5000",
                                 **run_nk(WORKLOADS["nk"])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -276,6 +276,8 @@ typedef struct {
     int32_t max_rows;   /* rows of the plain row calls (>= mode count used)  */
     uint64_t seed;      /* initial weights (SplitMix64 uniforms)             */
     float lr, beta1, beta2, adam_eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8)      */
+    float lr_final;     /* opf_mlp_train_pairs: cosine decay from lr to this
+                           over the steps of one call (1e-3: constant)      */
 } opf_mlp_config;
 
 opf_status opf_mlp_default_config(opf_mlp_config* cfg);

@@ -64,7 +64,7 @@ class opf_nk_report(ctypes.Structure):
 class opf_mlp_config(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("layers", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("max_rows", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float), ("lr_final", ctypes.c_float)]
 
 
 class OpfError(RuntimeError):
@@ -430,7 +430,7 @@ class Mlp:
     applied by Solver.nk_solve(precond=...)."""
 
     def __init__(self, solver, width=256, layers=4, rank=8, max_rows=0, seed=1, lr=1e-3, beta1=0.9,
-                 beta2=0.999, adam_eps=1e-8):
+                 beta2=0.999, adam_eps=1e-8, lr_final=None):
         import torch
         self.torch = torch
         self.solver = solver  # the context must outlive the network
@@ -441,6 +441,7 @@ class Mlp:
         cfg.width, cfg.layers, cfg.rank, cfg.seed = int(width), int(layers), int(rank), int(seed)
         cfg.max_rows = int(max_rows)
         cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps = lr, beta1, beta2, adam_eps
+        cfg.lr_final = lr if lr_final is None else lr_final
         self.cfg = cfg
         self.layers, self.rank, self.width = int(layers), int(rank), int(width)
         nbytes = ctypes.c_size_t()

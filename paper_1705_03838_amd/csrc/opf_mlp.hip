@@ -693,7 +693,7 @@ struct opf_mlp {
     long np = 0;
     Segs segs{};
     long woff[MAXL + 2] = {}, boff[MAXL + 2] = {};
-    float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float lr = 1e-3f, lr_final = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     long t = 0;
     bool fac_ok = false;
     float *P = nullptr, *G = nullptr, *Am = nullptr, *Av = nullptr;
@@ -814,8 +814,8 @@ opf_status check_cfg(const opf_ctx* c, const opf_mlp_config* cfg, std::string* w
     if (cfg->rank < 1 || cfg->rank > RMAX) return bad("rank must be in [1, 32]");
     if (3L * p.N * cfg->rank > 256L * HOUT) return bad("3 N rank must not exceed 3072");
     if (cfg->max_rows < 0 || cfg->max_rows > (1 << 20)) return bad("max_rows must be in [0, 2^20]");
-    if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
-        !(cfg->adam_eps > 0.0f))
+    if (!(cfg->lr >= 0.0f) || !(cfg->lr_final >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->adam_eps > 0.0f))
         return bad("bad Adam parameters");
     return OPF_OK;
 }
@@ -999,13 +999,13 @@ hipError_t backward_pairs(opf_mlp* m, const double* pairs, const int* idx, int b
     return st != hipSuccess ? st : backprop(m, rp);
 }
 
-hipError_t adam(opf_mlp* m) {
+hipError_t adam(opf_mlp* m, float lr) {
     m->t += 1;
     m->fac_ok = false;
     const float c1 = (float)(1.0 / (1.0 - std::pow((double)m->b1, (double)m->t)));
     const float c2 = (float)(1.0 / (1.0 - std::pow((double)m->b2, (double)m->t)));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((m->np + 255) / 256)), dim3(256), 0, m->s, m->P, m->G, m->Am, m->Av,
-                       m->np, m->lr, m->b1, m->b2, c1, c2, m->eps, m->segs, m->Wb, m->Wt);
+                       m->np, lr, m->b1, m->b2, c1, c2, m->eps, m->segs, m->Wb, m->Wt);
     return hipGetLastError();
 }
 
@@ -1062,6 +1062,7 @@ opf_status opf_mlp_default_config(opf_mlp_config* cfg) {
     cfg->beta1 = 0.9f;
     cfg->beta2 = 0.999f;
     cfg->adam_eps = 1e-8f;
+    cfg->lr_final = 1e-3f;
     return OPF_OK;
 }
 
@@ -1107,6 +1108,7 @@ opf_status opf_mlp_create(opf_ctx* ctx, const opf_mlp_config* cfg, void* dev_wor
     m->s = ctx_stream(ctx);
     dims_for(m, ctx, cfg);
     m->lr = cfg->lr;
+    m->lr_final = cfg->lr_final;
     m->b1 = cfg->beta1;
     m->b2 = cfg->beta2;
     m->eps = cfg->adam_eps;
@@ -1252,7 +1254,7 @@ opf_status opf_mlp_train(opf_mlp* net, const float* x_dev, const float* t_dev, c
             MCHK(net, forward(net, rp, true));
             MCHK(net, backward_rows(net, t_dev + (size_t)r0 * net->dout, w_dev ? w_dev + r0 : nullptr, n, rp,
                                     net->losses + step));
-            MCHK(net, adam(net));
+            MCHK(net, adam(net, net->lr));
             ++step;
         }
     }
@@ -1305,10 +1307,13 @@ opf_status opf_mlp_train_pairs(opf_ctx* ctx, opf_mlp* net, const void* pairs_dev
     MCHK(net, feature_input(net));
     const int rp = round32(net->mode_rows);
     for (int st = 0; st < steps; ++st) {
+        // cosine schedule from lr to lr_final over the call's steps
+        const double c = 0.5 * (1.0 + std::cos(M_PI * st / std::max(steps, 1)));
+        const float lr = (float)(net->lr_final + (net->lr - net->lr_final) * c);
         MCHK(net, forward(net, rp, true));
         MCHK(net, backward_pairs(net, static_cast<const double*>(pairs_dev), net->idx + (size_t)st * batch, batch,
                                  net->losses + st));
-        MCHK(net, adam(net));
+        MCHK(net, adam(net, lr));
     }
     if (loss_host && steps > 0) MCHK(net, hipMemcpyAsync(loss_host, net->losses, (size_t)steps * 4,
                                                          hipMemcpyDeviceToHost, net->s));
