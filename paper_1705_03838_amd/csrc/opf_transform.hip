@@ -410,6 +410,158 @@ __global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) 
 }
 
 // ---------------------------------------------------------------------------
+// k_theta_lp: the same computation as k_theta with the three packed lines
+// spread over the three waves of a 192-thread workgroup (wave p holds line
+// p), TZ = 4 axial points per workgroup.  A thread keeps one line's RA or RB
+// values instead of all three, so the FP64 kernel needs about half the
+// registers of k_theta and twice as many waves fit a CU; the product reads
+// the three lines from LDS.  Workgroups are ordered so that the two 4-point
+// tiles sharing a 128-byte line of H and G (FP64) run on the same XCD:
+// blocks g*16 + x and g*16 + x + 8 (x < 8) take tiles g*16 + 2x, g*16 + 2x + 1,
+// with consecutive block indices dispatched round-robin over the 8 XCDs.
+constexpr int TZ = 4;
+constexpr int NT3 = 192;
+
+__device__ __forceinline__ int xcd_pair_tile(int b, int total) {
+    const int g = b / 16, w = b % 16;
+    if ((g + 1) * 16 > total) return b;
+    return g * 16 + 2 * (w % 8) + w / 8;
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
+    static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
+    cpx<T>* buf = tw + L;                                // [3][TZ][LS]
+    const int N = a.N, M = a.M, L3K = 3 * a.K;
+    const int nzt = (L3K + TZ - 1) / TZ;
+    const int tile = xcd_pair_tile(blockIdx.x, N * nzt);
+    const int n = tile / nzt;
+    const int z0 = (tile % nzt) * TZ;
+    const int tid = threadIdx.x;
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
+    for (int t = tid; t < L; t += NT3) tw[t] = twg[t];
+    const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
+    const size_t fstride = (size_t)N * M * L3K;
+    const size_t nbase = (size_t)n * M * L3K;
+    cpx<T>* lb = buf + p * TZ * LS;  // this wave's line
+    // inverse pass A: lane (j, zz), z fastest; bins j + r RB of line p = fields (2p, 2p+1)
+    const int ja = lane / TZ, za = lane % TZ;
+    const int zc = min(z0 + za, L3K - 1);
+    cpx<T> v[RA];
+    if (ja < RB) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int bin = ja + r * RB;
+            int mm = -1;
+            bool neg = false;
+            if (bin < M) mm = bin;
+            else if (bin > L - M) { mm = L - bin; neg = true; }
+            cpx<T> val = {T(0), T(0)};
+            if (mm >= 0) {
+                const size_t off = nbase + (size_t)mm * L3K + zc;
+                const cpx<T> A = H[(2 * p) * fstride + off];
+                const cpx<T> B = H[(2 * p + 1) * fstride + off];
+                // Z = A + i B on m >= 0; conj(A) + i conj(B) on bins L - m
+                val = neg ? cpx<T>{A.x + B.y, B.x - A.y} : cpx<T>{A.x - B.y, A.y + B.x};
+            }
+            v[r] = val;
+        }
+    }
+    __syncthreads();  // twiddles
+    if (ja < RB) {
+        dftn<T, RA>(v, +1, tw, L);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) lb[za * LS + ja * RA + r] = v[r];
+    }
+    __syncthreads();
+    // inverse pass B: lane (zz, j); the line's values at theta points j + r RA
+    const int zb = lane / RA, jb = lane % RA;
+    const bool actB = zb < TZ;
+    cpx<T> u[RB];
+    if (actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> x = lb[zb * LS + jb + r * RA];
+            u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+        }
+        dftn<T, RB>(u, +1, tw, L);
+    }
+    __syncthreads();
+    if (actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) lb[zb * LS + jb + r * RA] = u[r];
+    }
+    __syncthreads();
+    // u x omega from the three lines; waves 0, 1 form (N_r + i N_t), (N_z + i 0)
+    // and run forward pass A' (radix RB on the same points)
+    const bool out = p < 2;
+    if (out && actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int pt = jb + r * RA;
+            const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZ + zb) * LS + pt], l2 = buf[(2 * TZ + zb) * LS + pt];
+            const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
+            u[r] = p == 0 ? cpx<T>{ut * wz - uz * wt, uz * wr - ur * wz} : cpx<T>{ur * wt - ut * wr, T(0)};
+        }
+        dftn<T, RB>(u, -1, tw, L);
+    }
+    __syncthreads();  // every line has been read
+    if (out && actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) lb[zb * LS + jb * RB + r] = u[r];
+    }
+    __syncthreads();
+    // forward pass B' (radix RA, Ns = RB): lane (zz, j), j < RB, takes y[j + r RB]
+    const int zc2 = lane / RB, jc = lane % RB;
+    const bool actC = out && zc2 < TZ;
+    cpx<T> x2[RA];
+    if (actC) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const cpx<T> x = lb[zc2 * LS + jc + r * RB];
+            x2[r] = r == 0 ? x : cmul(x, tw[jc * r]);
+        }
+        dftn<T, RA>(x2, -1, tw, L);
+    }
+    __syncthreads();
+    if (actC) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) lb[zc2 * LS + jc + r * RB] = x2[r];
+    }
+    __syncthreads();
+    // unpack the two output lines and store G (scaled by 1/(9KM))
+    cpx<T>* G = reinterpret_cast<cpx<T>*>(a.G);
+    const T h = T(0.5) * T(a.scale);
+    for (int t = tid; t < 2 * M * TZ; t += NT3) {
+        const int q = t / (M * TZ), rem = t % (M * TZ);
+        const int mm = rem / TZ, zz = rem % TZ, z = z0 + zz;
+        if (z >= L3K) continue;
+        const int mc = mm == 0 ? 0 : L - mm;
+        const cpx<T>* line = buf + (q * TZ + zz) * LS;
+        const cpx<T> Z = line[mm], Y = line[mc];
+        const size_t off = nbase + (size_t)mm * L3K + z;
+        if (q == 0) {  // A = (Z + conj Y)/2 -> N_r, B = (Z - conj Y)/(2i) -> N_t
+            G[off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
+            G[fstride + off] = {h * (Z.y + Y.y), h * (Y.x - Z.x)};
+        } else {
+            G[2 * fstride + off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
+        }
+    }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L>(a); }
+template <typename T, int L>
+__global__ __launch_bounds__(NT3) void k_theta_lp_b(const NLArgs* __restrict__ aa) {
+    const NLArgs a = aa[blockIdx.y];
+    k_theta_lp_body<T, L>(a);
+}
+
+// ---------------------------------------------------------------------------
 // k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
 template <typename TS, typename T, int L>
 __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
@@ -501,6 +653,19 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
     case V:                                                                          \
         if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, V>), g, dim3(NT2), lz, s, batch); \
         else hipLaunchKernelGGL((k_zinv<TS, T, V>), g, dim3(NT2), lz, s, a);         \
+        break;
+            OPF_FOR_LENGTHS(OPF_CASE)
+#undef OPF_CASE
+            default: return hipErrorInvalidValue;
+        }
+    } else if (stage == 1 && sizeof(T) == 8) {  // FP64: line-parallel form
+        const dim3 g(a.N * ((L3K + TZ - 1) / TZ), b ? members : 1);
+        const size_t l3 = (size_t)(L3M + 3 * TZ * (L3M + 1)) * sizeof(cpx<T>);
+        switch (L3M) {
+#define OPF_CASE(V)                                                                    \
+    case V:                                                                            \
+        if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), l3, s, batch);    \
+        else hipLaunchKernelGGL((k_theta_lp<T, V>), g, dim3(NT3), l3, s, a);            \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
