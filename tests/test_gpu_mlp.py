@@ -275,3 +275,45 @@ def test_trained_preconditioner_cuts_krylov_work(torch_cuda):
     for xs in (x1, x2):
         d = xs - lam
         assert np.sqrt(s.vec_dot(d, d)) < 1e-8
+
+
+def test_full_size_network_matches_oracle(torch_cuda):
+    """The configuration the bench trains (nk grid: N=48, |m|<24 with mp=2,
+    |k|<32; width 256, 4 layers, rank 16): model rows of sampled modes and
+    the preconditioner of a field against the bf16 oracle, and one pair
+    gradient against the oracle's head + backprop."""
+    import paper_1705_03838_amd as opf
+    from inputs import WORKLOADS
+    from oracle.mlp import (backprop, flatten, feature_rows, forward, head, init_params, precondition,
+                            unflatten)
+    w = WORKLOADS["nk"]
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
+    net = opf.Mlp(s, width=256, layers=4, rank=16)
+    say("full-size network", net.din, net.dout, net.n_params)
+    p = init_params(net.din, 256, 4, net.dout, seed=12)
+    p["W_out"] *= 0.3
+    flat = flatten(p, 4).astype(np.float32)
+    net.set_params(flat)
+    p = unflatten(flat.astype(np.float64), net.din, 256, 4, net.dout)
+    X = feature_rows(w["M"], w["K"], w["mp"], w["alpha"])
+    rows_ = [0, 1, 31, 62, 63, 700, 1511]
+    Fdev = net.forward(torch_cuda.from_numpy(X.astype(np.float32))).cpu().numpy().astype(np.float64)
+    Fb, cache = forward(p, X, 4, bf16=True)
+    assert nrel(Fdev[rows_], Fb[rows_]) <= 1e-2
+    v = make_state(w["N"], w["M"], w["K"], w["mp"], w["alpha"], s.nodes(), 1e-3, 4.0, 4.0, 77, laminar=False)
+    K = w["K"]
+    for kk in range(K - 1):
+        v[:, 0, kk] = np.conj(v[:, 0, 2 * (K - 1) - kk])
+    v[:, 0, K - 1] = v[:, 0, K - 1].real
+    z = net.precondition(torch_cuda.from_numpy(v)).cpu().numpy()
+    zb = precondition(p, 4, v, w["mp"], w["alpha"], 16, bf16=True)
+    say("   precondition rel", nrel(z + v, zb + v))
+    assert nrel(z + v, zb + v) <= 2e-2
+    g = np.random.default_rng(5)
+    pairs = g.standard_normal((3, 2) + s.shape) + 1j * g.standard_normal((3, 2) + s.shape)
+    idx = np.array([2, 0], dtype=np.int32)
+    lg, grad = net.pair_gradient(torch_cuda.from_numpy(pairs), idx)
+    L, dF = head(Fb.astype(np.float32).astype(np.float64), pairs[idx], 16)
+    assert abs(lg - L) <= 1e-2 * L
+    gref = backprop(p, cache, dF, 4, bf16=True)
+    check_grads(grad, gref, 4)
