@@ -106,13 +106,14 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     return (t1 - t0) / steps, prof, diag
 
 
-def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
+def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
     near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain,
     then with the learned preconditioner trained on Jacobian probes at
-    laminar flow (probing and training timed separately: they are made once
-    per grid, Re and T and serve every later search)."""
+    laminar flow, run 32 at a time as ensemble members (probing and training
+    timed separately: they are made once per grid, Re and T and serve every
+    later search)."""
     import torch
 
     import paper_1705_03838_amd as opf
@@ -134,7 +135,7 @@ def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
     progress(f"nk plain: {plain['jvps']} jvps, {plain['wall_s']} s")
     t0 = time.perf_counter()
     lam = torch.from_numpy(laminar_state(w["N"], w["M"], w["K"], s.nodes()))
-    pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11)
+    pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11, batch=32)
     probe_s = time.perf_counter() - t0
     progress(f"nk probes: {probes} in {probe_s:.1f} s")
     net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3, lr=1e-3, lr_final=3e-5)
@@ -150,7 +151,7 @@ def run_nk(w, gmres_m=40, probes=320, rank=16, train_steps=12000, batch=16):
            "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
            "steps_per_residual": int(round(w["T"] / w["dt"])),
            "network": {"width": 256, "layers": 4, "rank": rank, "params": net.n_params,
-                       "probes": probes, "probe_s": round(probe_s, 2),
+                       "probes": probes, "probe_batch": 32, "probe_s": round(probe_s, 2),
                        "train_steps": train_steps, "batch_pairs": batch, "lr": "cosine 1e-3 -> 3e-5",
                        "train_s": round(train_s, 2),
                        "train_step_ms": round(train_s / train_steps * 1e3, 4),

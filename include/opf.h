@@ -354,6 +354,14 @@ opf_status opf_ensemble_step(opf_ensemble* ens, int32_t nsteps);
  * tune before setting the states to be used).  Synchronises. */
 opf_status opf_ensemble_tune(opf_ensemble* ens, int32_t nsteps, char* report, size_t report_bytes);
 const char* opf_ensemble_last_error(const opf_ensemble* ens);
+/* opf_probe_pairs with the probes' trajectories run as ensemble members:
+ * every member must have the same parameters (one class, equal nodes); the
+ * B members advance B probes per batch of graph launches (idle members of
+ * the last batch run x).  The pairs equal those of opf_probe_pairs with the
+ * same seed bitwise.  Uses the first member as the context; the members'
+ * states are overwritten.  work_dev: 3 vectors.  Synchronises. */
+opf_status opf_probe_pairs_ensemble(opf_ensemble* ens, const void* x_dev, double T, double shift, int32_t n,
+                                    uint64_t seed, double fd_eps, void* pairs_dev, void* work_dev);
 
 const char* opf_status_string(opf_status s);
 const char* opf_last_error(const opf_ctx* ctx);

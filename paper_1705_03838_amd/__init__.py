@@ -27,7 +27,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pair_gradient",
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
-           "opf_ensemble_last_error",
+           "opf_ensemble_last_error", "opf_probe_pairs_ensemble",
            "opf_status_string", "opf_last_error"]
 
 
@@ -129,6 +129,7 @@ def load_library(path=LIB_PATH):
         "opf_ensemble_step": ([vp, i32], i32),
         "opf_ensemble_tune": ([vp, i32, ctypes.c_char_p, ctypes.c_size_t], i32),
         "opf_ensemble_last_error": ([vp], ctypes.c_char_p),
+        "opf_probe_pairs_ensemble": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp, vp], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -180,6 +181,7 @@ class Solver:
         import torch
         self.torch = torch
         self.lib = load_library()
+        self.kw = dict(kw)
         self.p = make_params(**kw)
         self._nodes = None
         if r_nodes is not None:
@@ -334,15 +336,27 @@ class Solver:
                    "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
                    "recorded": rep.recorded, "precond_applies": rep.precond_applies}
 
-    def probe_pairs(self, x, T, shift, n, seed=1, fd_eps=1e-7):
+    def probe_pairs(self, x, T, shift, n, seed=1, fd_eps=1e-7, batch=1):
         """n Jacobian probes (z, J z) of the travelling-wave residual at x:
-        complex128 device tensor [n, 2, 3, M, 2K-1, N]."""
+        complex128 device tensor [n, 2, 3, M, 2K-1, N].  batch > 1 runs the
+        probes' trajectories `batch` at a time as ensemble members (same
+        pairs, bitwise)."""
         x = self._dev(x, self.shape)
         pairs = self.torch.empty((int(n), 2) + tuple(self.shape), dtype=self.torch.complex128, device=self.device)
         work = self.torch.empty((3,) + tuple(self.shape), dtype=self.torch.complex128, device=self.device)
-        self._check(self.lib.opf_probe_pairs(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
-                                             int(n), int(seed), float(fd_eps), ctypes.c_void_p(pairs.data_ptr()),
-                                             ctypes.c_void_p(work.data_ptr())))
+        args = (ctypes.c_void_p(x.data_ptr()), float(T), float(shift), int(n), int(seed), float(fd_eps),
+                ctypes.c_void_p(pairs.data_ptr()), ctypes.c_void_p(work.data_ptr()))
+        if batch > 1:
+            kw = dict(self.kw)
+            if self._nodes is not None:
+                raise OpfError(OPF_E_UNSUPPORTED, "batched probes use the default radial nodes")
+            ens = Ensemble([kw] * int(batch), stream=self.stream)
+            try:
+                ens._check(self.lib.opf_probe_pairs_ensemble(ens.ens, *args))
+            finally:
+                ens.close()
+        else:
+            self._check(self.lib.opf_probe_pairs(self.ctx, *args))
         return pairs
 
     def diagnostics(self):

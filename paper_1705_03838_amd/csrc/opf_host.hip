@@ -1246,6 +1246,27 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
     return OPF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Probe i of a seed: unit normals, spectrum of a real field, unit energy norm.
+opf_status make_probe(opf_ctx* c, double* z, int i, uint64_t seed) {
+    const size_t total = 3 * field_entries(c);
+    hipLaunchKernelGGL(k_noise, dim3((total + 255) / 256), dim3(256), 0, c->stream, z, total,
+                       seed * 0x2545F4914F6CDD1Dull + (uint64_t)i * 0xD1B54A32D192ED03ull);
+    hipLaunchKernelGGL(k_realfield, dim3((3 * c->p.K * c->p.N + 255) / 256), dim3(256), 0, c->stream, z, c->p.N,
+                       c->p.M, c->nk, c->p.K);
+    HIPCHK(c, hipGetLastError());
+    double zn2 = 0.0;
+    opf_status st = opf_vec_dot(c, z, z, &zn2);
+    if (st != OPF_OK) return st;
+    if (!(zn2 > 0.0)) return OPF_E_NUMERIC;
+    return opf_vec_axpby(c, 0.0, z, 1.0 / std::sqrt(zn2), z);
+}
+}  // namespace
+
+extern "C" {
+
 opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n, uint64_t seed,
                            double fd_eps, void* pairs_dev, void* work_dev) {
     if (!c || !x_dev || !pairs_dev || !work_dev || n < 1 || !(fd_eps > 0.0)) return OPF_E_INVALID;
@@ -1264,15 +1285,7 @@ opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift
     for (int i = 0; i < n; ++i) {
         double* z = reinterpret_cast<double*>(out + (size_t)i * 2 * vb);
         void* jz = out + (size_t)i * 2 * vb + vb;
-        hipLaunchKernelGGL(k_noise, dim3((total + 255) / 256), dim3(256), 0, c->stream, z, total,
-                           seed * 0x2545F4914F6CDD1Dull + (uint64_t)i * 0xD1B54A32D192ED03ull);
-        hipLaunchKernelGGL(k_realfield, dim3((3 * c->p.K * c->p.N + 255) / 256), dim3(256), 0, c->stream, z, c->p.N,
-                           c->p.M, c->nk, c->p.K);
-        HIPCHK(c, hipGetLastError());
-        double zn2 = 0.0;
-        if ((st = opf_vec_dot(c, z, z, &zn2)) != OPF_OK) return st;
-        if (!(zn2 > 0.0)) return OPF_E_NUMERIC;
-        if ((st = opf_vec_axpby(c, 0.0, z, 1.0 / std::sqrt(zn2), z)) != OPF_OK) return st;
+        if ((st = make_probe(c, z, i, seed)) != OPF_OK) return st;
         if ((st = opf_vec_axpby(c, 1.0, x_dev, 0.0, tmp)) != OPF_OK) return st;
         if ((st = opf_vec_axpby(c, eps, z, 1.0, tmp)) != OPF_OK) return st;
         if ((st = opf_newton_residual(c, tmp, T, shift, F1, nullptr)) != OPF_OK) return st;
@@ -1514,6 +1527,65 @@ opf_status opf_ensemble_step(opf_ensemble* e, int32_t nsteps) {
             return OPF_E_HIP;
         }
     }
+    return OPF_OK;
+}
+
+opf_status opf_probe_pairs_ensemble(opf_ensemble* e, const void* x_dev, double T, double shift, int32_t n,
+                                    uint64_t seed, double fd_eps, void* pairs_dev, void* work_dev) {
+    if (!e || e->members.empty() || !x_dev || !pairs_dev || !work_dev || n < 1 || !(fd_eps > 0.0))
+        return OPF_E_INVALID;
+    opf_ctx* c0 = e->members[0];
+    for (opf_ctx* c : e->members) {
+        const opf_params &a = c->p, &b = c0->p;
+        if (a.N != b.N || a.M != b.M || a.K != b.K || a.mp != b.mp || a.alpha != b.alpha || a.Re != b.Re ||
+            a.dt != b.dt || a.c != b.c || a.n_corr != b.n_corr || a.fixed_flux != b.fixed_flux ||
+            a.precision != b.precision || a.nonlinear != b.nonlinear || c->r != c0->r)
+            return OPF_E_INVALID;
+    }
+    if (!(T >= 0)) return OPF_E_INVALID;
+    const size_t total = 3 * field_entries(c0);
+    const size_t vb = total * 16;
+    unsigned char* w = static_cast<unsigned char*>(work_dev);
+    void* F0 = w;
+    void* tmp = w + vb;
+    void* F1 = w + 2 * vb;
+    opf_status st = opf_newton_residual(c0, x_dev, T, shift, F0, nullptr);
+    if (st != OPF_OK) return st;
+    double xn2 = 0.0;
+    if ((st = opf_vec_dot(c0, x_dev, x_dev, &xn2)) != OPF_OK) return st;
+    const double eps = fd_eps * std::max(std::sqrt(xn2), 1.0);
+    const int nsteps = (int)std::lround(T / c0->p.dt);
+    const int B = (int)e->members.size();
+    unsigned char* out = static_cast<unsigned char*>(pairs_dev);
+    for (int i0 = 0; i0 < n; i0 += B) {
+        const int nb = std::min(B, n - i0);
+        for (int j = 0; j < B; ++j) {  // member j runs x + eps z_{i0+j} (idle members run x)
+            if (j < nb) {
+                double* z = reinterpret_cast<double*>(out + (size_t)(i0 + j) * 2 * vb);
+                if ((st = make_probe(c0, z, i0 + j, seed)) != OPF_OK) return st;
+                if ((st = opf_vec_axpby(c0, 1.0, x_dev, 0.0, tmp)) != OPF_OK) return st;
+                if ((st = opf_vec_axpby(c0, eps, z, 1.0, tmp)) != OPF_OK) return st;
+                if ((st = opf_set_state(e->members[j], tmp)) != OPF_OK) return st;
+            } else if ((st = opf_set_state(e->members[j], x_dev)) != OPF_OK) {
+                return st;
+            }
+        }
+        if ((st = opf_ensemble_step(e, nsteps)) != OPF_OK) return st;
+        for (int j = 0; j < nb; ++j) {  // J z = (shift(Phi_T(x + eps z), -s) - (x + eps z) - F(x)) / eps
+            opf_ctx* c = e->members[j];
+            const double* z = reinterpret_cast<const double*>(out + (size_t)(i0 + j) * 2 * vb);
+            void* jz = out + (size_t)(i0 + j) * 2 * vb + vb;
+            if ((st = opf_vec_axpby(c, 1.0, x_dev, 0.0, tmp)) != OPF_OK) return st;
+            if ((st = opf_vec_axpby(c, eps, z, 1.0, tmp)) != OPF_OK) return st;
+            hipLaunchKernelGGL(k_shift_sub, dim3((total + 255) / 256), dim3(256), 0, c->stream, c->u,
+                               static_cast<const double*>(tmp), static_cast<double*>(F1), c->p.N, c->nk, c->p.K,
+                               total, c->p.alpha, shift);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipMemcpyAsync(jz, F1, vb, hipMemcpyDeviceToDevice, c->stream));
+            if ((st = opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, jz)) != OPF_OK) return st;
+        }
+    }
+    if (hipStreamSynchronize(e->stream) != hipSuccess) return OPF_E_HIP;
     return OPF_OK;
 }
 

@@ -192,6 +192,9 @@ def test_probe_pairs_are_jacobian_products(torch_cuda):
     pairs = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
     again = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
     assert torch_cuda.equal(pairs, again)
+    # run as ensemble members, two at a time (the second batch has an idle member): the same pairs
+    batched = s.probe_pairs(x, 1.0, 0.0, 3, seed=5, batch=2)
+    assert torch_cuda.equal(pairs, batched)
     other = s.probe_pairs(x, 1.0, 0.0, 1, seed=6)
     assert not torch_cuda.equal(pairs[0, 0], other[0, 0])
     for i in range(3):
