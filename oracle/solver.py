@@ -36,7 +36,7 @@ from typing import Optional
 import numpy as np
 
 from .grid import radial_nodes, fd_matrices, quadrature_weights
-from .spectral import to_pm, from_pm, vorticity, nonlinear
+from .spectral import to_pm, from_pm, vorticity, nonlinear, to_physical
 
 
 @dataclass
@@ -278,6 +278,37 @@ class Oracle:
         I = (4.0 / p.Re) * (1.0 + self.beta) * vol * flux
         tau = -float((g.D1[0] @ u[2, 0, k0].real)[-1])
         return dict(E=E, I=I, D=D, tau_w=tau, flux=flux, beta=self.beta)
+
+    def boundary_and_divergence(self, u):
+        """Largest boundary-condition residual over the modes,
+        max_mk max(|u_+(1)|, |u_-(1)|, |u_z(1)|, |div u(1)|) (the vector g of
+        Section 2), and the largest interior divergence max_mk max_{n<N-1}
+        |div u_mk(r_n)|, with div u = (1/r) d(r u_r)/dr + (i m/r) u_theta +
+        i kappa u_z written in the (+,-,z) form."""
+        v = to_pm(u)
+        gmax = dmax = 0.0
+        for mi in range(self.M):
+            m = self.p.mp * mi
+            dv = self.div_pm(m, self.kap, v[0, mi], v[1, mi], v[2, mi])
+            bc = np.stack([v[0, mi][:, -1], v[1, mi][:, -1], v[2, mi][:, -1], dv[:, -1]])
+            gmax = max(gmax, float(np.max(np.abs(bc))))
+            dmax = max(dmax, float(np.max(np.abs(dv[:, :-1]))))
+        return gmax, dmax
+
+    def cfl(self, u):
+        """dt max over the dealiased physical grid (N x 3M x 3K) of
+        |u_r|/dr_n + |u_theta|/(r_n dtheta) + |u_z|/dz, with dtheta = 2 pi/(mp 3M),
+        dz = 2 pi/(alpha 3K) and dr_n the distance from r_n to its nearer
+        radial neighbour (the axis mirror -r_0 counts as the neighbour of r_0)."""
+        p, r = self.p, self.g.r
+        ur, ut, uz = (to_physical(u[c], self.M, self.K) for c in range(3))
+        left = np.concatenate([[2.0 * r[0]], np.diff(r)])
+        right = np.concatenate([np.diff(r), [np.inf]])
+        dr = np.minimum(left, right)
+        dth = 2.0 * np.pi / (p.mp * 3 * self.M)
+        dz = 2.0 * np.pi / (p.alpha * 3 * self.K)
+        loc = (np.abs(ur) / dr[:, None, None] + np.abs(ut) / (r[:, None, None] * dth) + np.abs(uz) / dz)
+        return float(p.dt * np.max(loc))
 
     def energy_norm(self, u):
         """||u||^2 = sum_k sum_{m>=0} c_m sum_n w_n |u_mk(r_n)|^2."""
