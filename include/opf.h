@@ -82,13 +82,18 @@ typedef struct {
 /* Global diagnostics (Section 3.2: kinetic energy E, energy input from the
  * driving pressure gradient I, dissipation D; laminar values for
  * normalisation), plus wall shear tau_w = -du_z/dr of the mean flow at r = 1,
- * flux = int_0^1 u_z,00 r dr and the pressure-gradient excess beta.  g_norm is
- * the largest boundary-condition residual |g| over all modes after the last
- * radial solve (Section 2: at machine-epsilon level). */
+ * flux = int_0^1 u_z,00 r dr and the pressure-gradient excess beta.
+ * g_norm: largest boundary-condition residual over all modes of the state,
+ * max |g_i| of g = (u+(1), u-(1), u_z(1), div u(1)) (Section 2: the influence
+ * matrix drives it to round-off).  div_max: largest |div u| over all modes
+ * and interior nodes (finite-difference divergence).  cfl: dt times the
+ * largest |u_r|/dr_n + |u_theta|/(r_n dtheta) + |u_z|/dz over the dealiased
+ * physical grid, dtheta = 2 pi/(mp 3M), dz = 2 pi/(alpha 3K), dr_n the
+ * distance from r_n to its nearer radial neighbour (-r_0 for n = 0). */
 typedef struct {
     double E, I, D, tau_w, flux, beta;
     double E_lam, I_lam, D_lam;
-    double g_norm;
+    double g_norm, div_max, cfl;
 } opf_diag;
 
 typedef struct opf_ctx opf_ctx;

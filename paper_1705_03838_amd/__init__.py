@@ -43,7 +43,8 @@ class opf_params(ctypes.Structure):
 
 class opf_diag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
-                ("E", "I", "D", "tau_w", "flux", "beta", "E_lam", "I_lam", "D_lam", "g_norm")]
+                ("E", "I", "D", "tau_w", "flux", "beta", "E_lam", "I_lam", "D_lam", "g_norm", "div_max",
+                 "cfl")]
 
 
 class opf_nk_opts(ctypes.Structure):

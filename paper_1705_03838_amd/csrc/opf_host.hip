@@ -30,6 +30,7 @@ struct opf_ctx {
     Tables t{};
     // buffers (device)
     double *u = nullptr, *up = nullptr, *w64 = nullptr, *beta = nullptr, *partial = nullptr;
+    double *dpart = nullptr, *cflw = nullptr, *cpart = nullptr;  // diagnostics: per-mode g / div, CFL weights, per-block CFL
     void *w = nullptr, *Nn = nullptr, *Np = nullptr, *H = nullptr, *G = nullptr;
     float *u32 = nullptr, *up32 = nullptr;
     void *twz = nullptr, *twt = nullptr;
@@ -295,7 +296,7 @@ void build_grid(opf_ctx* c, const double* r_nodes) {
 
 struct Layout {
     size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, twz, twt;
-    size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, total;
+    size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, dpart, cflw, cpart, total;
 };
 
 Layout layout(const opf_params& p) {
@@ -331,6 +332,9 @@ Layout layout(const opf_params& p) {
     L.up32 = take(3 * S * 8);
     L.beta = take(8);
     L.partial = take(2 * M * 8);
+    L.dpart = take(2 * M * nk * 8);
+    L.cflw = take(2 * N * 8);
+    L.cpart = take(N * ((3 * K + 3) / 4) * 8);
     L.total = o;
     return L;
 }
@@ -786,6 +790,15 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     if (he == hipSuccess) he = up(Lo.hom, hom.data(), hom.size() * 8);
     if (he == hipSuccess) he = up(Lo.ainv, ainv.data(), ainv.size() * 8);
     if (he == hipSuccess) he = up(Lo.green, c->green.data(), N * 8);
+    // CFL weights: 1/dr_n (nearer neighbour; the axis mirror -r_0 for n = 0) and 1/(r_n dtheta)
+    std::vector<double> cflw(2 * N);
+    for (int n = 0; n < N; ++n) {
+        const double left = n == 0 ? 2.0 * c->r[0] : c->r[n] - c->r[n - 1];
+        const double right = n == N - 1 ? left : c->r[n + 1] - c->r[n];
+        cflw[n] = 1.0 / std::min(left, right);
+        cflw[N + n] = (double)p->mp * 3 * M / (2.0 * M_PI * c->r[n]);
+    }
+    if (he == hipSuccess) he = up(Lo.cflw, cflw.data(), cflw.size() * 8);
     if (he == hipSuccess) he = mixed ? up(Lo.twz, twz32.data(), twz32.size() * 4) : up(Lo.twz, twz.data(), twz.size() * 8);
     if (he == hipSuccess) he = mixed ? up(Lo.twt, twt32.data(), twt32.size() * 4) : up(Lo.twt, twt.data(), twt.size() * 8);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -819,6 +832,9 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->up32 = reinterpret_cast<float*>(ws + Lo.up32);
     c->beta = reinterpret_cast<double*>(ws + Lo.beta);
     c->partial = reinterpret_cast<double*>(ws + Lo.partial);
+    c->dpart = reinterpret_cast<double*>(ws + Lo.dpart);
+    c->cflw = reinterpret_cast<double*>(ws + Lo.cflw);
+    c->cpart = reinterpret_cast<double*>(ws + Lo.cpart);
     *out = c;
     return OPF_OK;
 }
@@ -1015,6 +1031,17 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     x.t = c->t;
     HIPCHK(c, launch_vorticity(x, c->stream));
     HIPCHK(c, launch_energy(x, c->stream));
+    HIPCHK(c, launch_divg(x, c->dpart, c->stream));
+    // CFL: z-inverse transform of u and omega, then theta-inverse of the velocity lines
+    const bool mixed = c->p.precision == OPF_MIXED;
+    const NLArgs nl = nl_args(c, mixed ? (const void*)c->u32 : (const void*)c->u, c->w, c->Nn);
+    HIPCHK(c, launch_nonlinear_stage(nl, c->p.precision, 0, c->stream));
+    HIPCHK(c, launch_cfl(nl, c->p.precision, c->cflw, c->cflw + N, c->p.alpha * 3 * K / (2.0 * M_PI), c->cpart,
+                         c->stream));
+    const int ncfl = N * ((3 * K + 3) / 4);
+    std::vector<double> dp(2 * (size_t)M * c->nk), cp(ncfl);
+    HIPCHK(c, hipMemcpyAsync(dp.data(), c->dpart, dp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cp.data(), c->cpart, cp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     std::vector<double> part(2 * M), uz(2 * N);
     double beta = 0.0;
     const size_t S = field_entries(c);
@@ -1043,7 +1070,14 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     d->tau_w = -dz;
     d->E_lam = M_PI * lz / (6.0 * c->p.mp);
     d->I_lam = d->D_lam = 2.0 * M_PI * lz / (c->p.mp * c->p.Re);
-    if (!std::isfinite(d->E) || !std::isfinite(d->D)) return OPF_E_NUMERIC;
+    for (size_t q = 0; q < dp.size() / 2; ++q) {
+        d->g_norm = std::max(d->g_norm, dp[2 * q]);
+        d->div_max = std::max(d->div_max, dp[2 * q + 1]);
+    }
+    double cm = 0.0;
+    for (double v : cp) cm = std::max(cm, v);
+    d->cfl = c->p.dt * cm;
+    if (!std::isfinite(d->E) || !std::isfinite(d->D) || !std::isfinite(d->cfl)) return OPF_E_NUMERIC;
     return OPF_OK;
 }
 

@@ -101,6 +101,14 @@ bool gm_ok(int gm, int mp);
 constexpr int NFH = 6;  // Helmholtz factors a solve workgroup stages at once
 hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s);
 hipError_t launch_energy(const AuxArgs& a, hipStream_t s);
+// Per mode q: part[2q] = max |g| of (u+(1), u-(1), u_z(1), div u(1)),
+// part[2q+1] = max over interior nodes of |div u|.
+hipError_t launch_divg(const AuxArgs& a, double* part, hipStream_t s);
+// Largest |u_r| wr[n] + |u_theta| wt[n] + |u_z| wz over the physical points
+// of each (n, 4-point z tile) workgroup into out[block], from the
+// z-transformed fields in a.H (stage 0 of the nonlinear term).
+hipError_t launch_cfl(const NLArgs& a, int precision, const double* wr, const double* wt, double wz, double* out,
+                      hipStream_t s);
 
 // Context accessors for translation units other than the host core.
 hipStream_t ctx_stream(const opf_ctx* c);

@@ -602,6 +602,59 @@ hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s) {
     return launch_solve_batch(a, nullptr, 1, precision, s);
 }
 
+// Boundary-condition residual and interior divergence of every mode (one
+// 64-lane workgroup per mode, lanes = radial nodes), in the (+,-,z) form
+// (u+- = u_r +- i u_theta): div u = (1/2)[u+' + (1+m) u+/r]
+// + (1/2)[u-' + (1-m) u-/r] + i kappa u_z.  part[2q] = max(|u+(1)|, |u-(1)|,
+// |u_z(1)|, |div u(1)|), part[2q+1] = max over n < N-1 of |div u(r_n)|.
+__global__ __launch_bounds__(64) void k_divg(AuxArgs a, double* __restrict__ part) {
+    __shared__ dcplx sL[3][LSTR];
+    const int N = a.N, K = a.K, nk = a.nk;
+    const int q = blockIdx.x, mi = q / nk, kk = q % nk;
+    const int m = a.mp * mi, n = threadIdx.x;
+    const double kap = a.alpha * (kk - (K - 1));
+    const size_t S = (size_t)a.M * nk * N;
+    const size_t off = (size_t)q * N + n;
+    if (n < N) {
+        const dcplx ur = load_c<double>(a.u, off), ut = load_c<double>(a.u, S + off);
+        sL[0][n] = ur + ix(ut);
+        sL[1][n] = ur - ix(ut);
+        sL[2][n] = load_c<double>(a.u, 2 * S + off);
+    }
+    __syncthreads();
+    double gv = 0.0, dv = 0.0;
+    if (n < N) {
+        const int s0 = a.t.s0[n];
+        const double rinv = a.t.rinv[n];
+        const double* w1 = a.t.d1 + (((m + 1) & 1) * N + n) * W9;
+        const dcplx up = sL[0][n], um = sL[1][n], uz = sL[2][n];
+        const dcplx ap = stencil(w1, sL[0], s0) + (double(1 + m) * rinv) * up;
+        const dcplx am = stencil(w1, sL[1], s0) + (double(1 - m) * rinv) * um;
+        const dcplx d = 0.5 * (ap + am) + kap * ix(uz);
+        const double ad = sqrt(d.x * d.x + d.y * d.y);
+        if (n == N - 1) {
+            const double a1 = sqrt(up.x * up.x + up.y * up.y), a2 = sqrt(um.x * um.x + um.y * um.y);
+            const double a3 = sqrt(uz.x * uz.x + uz.y * uz.y);
+            gv = fmax(fmax(a1, a2), fmax(a3, ad));
+        } else {
+            dv = ad;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        gv = fmax(gv, __shfl_xor(gv, o, 64));
+        dv = fmax(dv, __shfl_xor(dv, o, 64));
+    }
+    if (n == 0) {
+        part[2 * q] = gv;
+        part[2 * q + 1] = dv;
+    }
+}
+
+hipError_t launch_divg(const AuxArgs& a, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_divg, dim3(a.M * a.nk), dim3(64), 0, s, a, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_vorticity(const AuxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_vorticity, dim3(a.M * a.nk), dim3(64), 0, s, a);
     return hipGetLastError();

@@ -562,6 +562,110 @@ __global__ __launch_bounds__(NT3) void k_theta_lp_b(const NLArgs* __restrict__ a
 }
 
 // ---------------------------------------------------------------------------
+// k_cfl: per (n, TZ axial points) the velocity lines (u_r + i u_theta) and
+// (u_z + i omega_r) are transformed to theta points as in k_theta_lp (wave p
+// holds line p), then out[block] = max over the tile's points of
+// |u_r| wr[n] + |u_theta| wt[n] + |u_z| wz (the local CFL rate).
+template <typename T, int L>
+__global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict__ wr, const double* __restrict__ wt,
+                                             double wz, double* __restrict__ out) {
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
+    cpx<T>* buf = tw + L;                                // [2][TZ][LS]
+    const int N = a.N, M = a.M, L3K = 3 * a.K;
+    const int nzt = (L3K + TZ - 1) / TZ;
+    const int n = blockIdx.x / nzt;
+    const int z0 = (blockIdx.x % nzt) * TZ;
+    const int tid = threadIdx.x;
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
+    for (int t = tid; t < L; t += 128) tw[t] = twg[t];
+    const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
+    const size_t fstride = (size_t)N * M * L3K;
+    const size_t nbase = (size_t)n * M * L3K;
+    cpx<T>* lb = buf + p * TZ * LS;
+    const int ja = lane / TZ, za = lane % TZ;
+    const int zc = min(z0 + za, L3K - 1);
+    cpx<T> v[RA];
+    if (ja < RB) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int bin = ja + r * RB;
+            int mm = -1;
+            bool neg = false;
+            if (bin < M) mm = bin;
+            else if (bin > L - M) { mm = L - bin; neg = true; }
+            cpx<T> val = {T(0), T(0)};
+            if (mm >= 0) {
+                const size_t off = nbase + (size_t)mm * L3K + zc;
+                const cpx<T> A = H[(2 * p) * fstride + off];
+                const cpx<T> B = H[(2 * p + 1) * fstride + off];
+                val = neg ? cpx<T>{A.x + B.y, B.x - A.y} : cpx<T>{A.x - B.y, A.y + B.x};
+            }
+            v[r] = val;
+        }
+    }
+    __syncthreads();  // twiddles
+    if (ja < RB) {
+        dftn<T, RA>(v, +1, tw, L);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) lb[za * LS + ja * RA + r] = v[r];
+    }
+    __syncthreads();
+    const int zb = lane / RA, jb = lane % RA;
+    const bool actB = zb < TZ;
+    cpx<T> u[RB];
+    if (actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cpx<T> x = lb[zb * LS + jb + r * RA];
+            u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+        }
+        dftn<T, RB>(u, +1, tw, L);
+    }
+    __syncthreads();
+    if (actB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) lb[zb * LS + jb + r * RA] = u[r];
+    }
+    __syncthreads();
+    if (p == 0) {
+        double mx = 0.0;
+        if (actB) {
+            const double a1 = wr[n], a2 = wt[n];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int pt = jb + r * RA;
+                const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZ + zb) * LS + pt];
+                mx = fmax(mx, fabs((double)l0.x) * a1 + fabs((double)l0.y) * a2 + fabs((double)l1.x) * wz);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) out[blockIdx.x] = mx;
+    }
+}
+
+#define OPF_FOR_LENGTHS_CFL(X) X(6) X(9) X(12) X(18) X(24) X(36) X(48) X(54) X(72) X(96) X(108) X(144) X(192)
+template <typename T>
+static hipError_t launch_cfl_typed(const NLArgs& a, const double* wr, const double* wt, double wz, double* out,
+                                   hipStream_t s) {
+    const int L3M = 3 * a.M;
+    const dim3 g(a.N * ((3 * a.K + TZ - 1) / TZ));
+    const size_t lds = (size_t)(L3M + 2 * TZ * (L3M + 1)) * sizeof(cpx<T>);
+    switch (L3M) {
+#define OPF_CASE(V)                                                                       \
+    case V:                                                                               \
+        hipLaunchKernelGGL((k_cfl<T, V>), g, dim3(128), lds, s, a, wr, wt, wz, out);      \
+        break;
+        OPF_FOR_LENGTHS_CFL(OPF_CASE)
+#undef OPF_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
 template <typename TS, typename T, int L>
 __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
@@ -708,6 +812,13 @@ hipError_t launch_nonlinear_batch(const NLArgs& proto, const NLArgs* dev_args, i
 hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s) {
     if (precision == OPF_MIXED) return launch_typed<float, float>(a, nullptr, 1, stage, s);
     return launch_typed<double, double>(a, nullptr, 1, stage, s);
+}
+
+hipError_t launch_cfl(const NLArgs& a, int precision, const double* wr, const double* wt, double wz, double* out,
+                      hipStream_t s) {
+    if (!length_ok(3 * a.M)) return hipErrorInvalidValue;
+    if (precision == OPF_MIXED) return launch_cfl_typed<float>(a, wr, wt, wz, out, s);
+    return launch_cfl_typed<double>(a, wr, wt, wz, out, s);
 }
 
 hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s) {

@@ -294,3 +294,32 @@ def test_ensemble_members_equal_single_runs(torch_cuda):
         a = e.members[i].get_state().cpu().numpy()
         b = s.get_state().cpu().numpy()
         assert np.array_equal(a, b), i
+
+
+@pytest.mark.parametrize("case", ["tiny", "mp3", "ragged"])
+def test_diagnostics_boundary_divergence_cfl(torch_cuda, case):
+    """g_norm, interior divergence and CFL of a state against the oracle's
+    definitions (FP64: rounding only; mixed: the CFL comes from FP32
+    transforms)."""
+    import paper_1705_03838_amd as opf
+    kw = CASES[case]
+    say("diagnostics", case, kw)
+    s = solver(torch_cuda, **kw)
+    o = oracle_for(s, **kw)
+    u = state_for(kw, s.nodes(), 3e-2, 61)
+    u[2, 1, kw["K"]] += 0.01  # a wall value the boundary residual must see
+    s.set_state(torch_cuda.from_numpy(u))
+    d = s.diagnostics()
+    g, dm = o.boundary_and_divergence(u)
+    cfl = o.cfl(u)
+    scale = np.max(np.abs(u))
+    say("   gpu", d["g_norm"], d["div_max"], d["cfl"], " oracle", g, dm, cfl)
+    assert abs(d["g_norm"] - g) <= 1e-12 * scale and g > 1e-3
+    assert abs(d["div_max"] - dm) <= 1e-12 * scale
+    assert abs(d["cfl"] - cfl) <= 1e-12 * cfl
+    # after a step the influence matrix has driven g to round-off
+    s.step(1)
+    assert s.diagnostics()["g_norm"] <= 1e-10 * scale
+    m = solver(torch_cuda, precision=opf.OPF_MIXED, **kw)
+    m.set_state(torch_cuda.from_numpy(u))
+    assert abs(m.diagnostics()["cfl"] - cfl) <= 1e-5 * cfl
