@@ -101,7 +101,7 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = s.profile_steps(profile_steps)
-    diag = s.diagnostics()
+    diag = s.diagnostics(check=False)
     s.close()
     return (t1 - t0) / steps, prof, diag
 
@@ -230,7 +230,7 @@ def run_ensemble(steps=500, warmup=5):
     e.step(steps)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    finite = all(np.isfinite(e.members[i].diagnostics()["E"]) for i in (0, 32, 64))
+    finite = all(np.isfinite(e.members[i].diagnostics(check=False)["E"]) for i in (0, 32, 64))
     e.close()
     return {"members": len(mem), "steps": steps, "ms_per_step": round(dt * 1e3, 4),
             "member_steps_per_s": round(len(mem) / dt, 1), "precision": "mixed",
@@ -346,7 +346,7 @@ def main():
         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, False) / ms64 / 1e9, 1),
         "kernel_GBps_per_step": round(step_bytes(N, M, K, False) / ms64 / 1e9, 1),
         "roofline": roofline(prof64, False, "fp64"),
-        "diagnostics_after_run": {k: diag64[k] for k in ("E", "D", "tau_w", "beta")},
+        "diagnostics_after_run": {k: diag64[k] for k in ("E", "D", "tau_w", "beta", "g_norm", "div_max", "cfl")},
     }
     if not args.fp64_only:
         ms32, prof32, _ = run_gpu(w, opf.OPF_MIXED, args.steps, args.warmup, args.profile_steps)

@@ -332,7 +332,8 @@ opf_status opf_mlp_factors(opf_mlp* net, float* host, int64_t n, int32_t* singul
 opf_status opf_precondition(opf_ctx* ctx, opf_mlp* net, const void* v_dev, void* z_dev);
 const char* opf_mlp_last_error(const opf_mlp* net);
 
-/* Diagnostics of the current state (host struct; synchronises). */
+/* Diagnostics of the current state (host struct; synchronises).  Returns
+ * OPF_E_NUMERIC, with *out filled, when a value is not finite or cfl > 1. */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
 
 /* ---- Ensembles of independent trajectories -------------------------------

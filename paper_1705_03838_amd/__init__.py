@@ -360,10 +360,16 @@ class Solver:
             self._check(self.lib.opf_probe_pairs(self.ctx, *args))
         return pairs
 
-    def diagnostics(self):
+    def diagnostics(self, check=True):
+        """Diagnostics dict; with check=False a non-finite value or CFL > 1
+        is reported in the dict ("status") instead of raising."""
         d = opf_diag()
-        self._check(self.lib.opf_diagnostics(self.ctx, ctypes.byref(d)))
-        return {name: getattr(d, name) for name, _ in opf_diag._fields_}
+        st = self.lib.opf_diagnostics(self.ctx, ctypes.byref(d))
+        if check:
+            self._check(st)
+        out = {name: getattr(d, name) for name, _ in opf_diag._fields_}
+        out["status"] = st
+        return out
 
 
 class _Member(Solver):

@@ -1078,6 +1078,10 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     for (double v : cp) cm = std::max(cm, v);
     d->cfl = c->p.dt * cm;
     if (!std::isfinite(d->E) || !std::isfinite(d->D) || !std::isfinite(d->cfl)) return OPF_E_NUMERIC;
+    if (d->cfl > 1.0) {
+        c->err = "CFL number above 1";
+        return OPF_E_NUMERIC;
+    }
     return OPF_OK;
 }
 

@@ -323,3 +323,9 @@ def test_diagnostics_boundary_divergence_cfl(torch_cuda, case):
     m = solver(torch_cuda, precision=opf.OPF_MIXED, **kw)
     m.set_state(torch_cuda.from_numpy(u))
     assert abs(m.diagnostics()["cfl"] - cfl) <= 1e-5 * cfl
+    # a state moving too fast for dt: CFL > 1 is an error, with the values still reported
+    s.set_state(torch_cuda.from_numpy(u * (2.0 / cfl)))
+    d = s.diagnostics(check=False)
+    assert d["status"] == opf.OPF_E_NUMERIC and abs(d["cfl"] - 2.0) <= 1e-11
+    with pytest.raises(opf.OpfError):
+        s.diagnostics()
