@@ -238,14 +238,22 @@ class Oracle:
 
     def step(self, u):
         """One predictor-corrector step u^n -> u^{n+1} (r,theta,z spectral)."""
+        return self.step_pc(u)[0]
+
+    def step_pc(self, u):
+        """One step, returning (u^{n+1}, the iterate before the last
+        corrector): with one corrector the second value is the predicted
+        state u^p."""
         p = self.p
         N0 = to_pm(self.nonlinear(u))
         Rlin = self.explicit(u)
         u1 = self.solve(Rlin + N0)
+        prev = u1
         for _ in range(p.n_corr):
+            prev = u1
             N1 = to_pm(self.nonlinear(u1))
             u1 = self.solve(Rlin + p.c * N1 + (1.0 - p.c) * N0)
-        return u1
+        return u1, prev
 
     def run(self, u, nsteps):
         for _ in range(nsteps):
