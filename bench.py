@@ -106,6 +106,37 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     return (t1 - t0) / steps, prof, diag
 
 
+def run_adaptive(w, steps, warmup, courant=0.5, check_every=10, dt_max=0.01):
+    """The pipe64 FP64 run under automatic time-step control (Courant limit;
+    checks every `check_every` steps, each a CFL reduction plus the last
+    correction, synchronising; a change rebuilds the dt tables on the host
+    and recaptures the step graph)."""
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import workload_state
+
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"],
+                   dt=w["dt"], precision=opf.OPF_FP64)
+    s.set_state(torch.from_numpy(workload_state(w, s.nodes())))
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = s.step_adaptive(steps, courant=courant, pc_tol=0.0, dt_min=1e-5, dt_max=dt_max, grow=0.1,
+                          check_every=check_every, trace=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dts = rep["dts"]
+    s.close()
+    return {"steps": steps, "warmup_fixed_dt": warmup, "courant": courant, "check_every": check_every,
+            "dt_max": dt_max, "wall_s": round(wall, 4), "steps_per_s": round(steps / wall, 2),
+            "sim_time_per_s": round(rep["t"] / wall, 4), "checks": rep["checks"], "changes": rep["changes"],
+            "rebuild_ms_total": round(rep["rebuild_ms"], 2),
+            "rebuild_ms_per_change": round(rep["rebuild_ms"] / max(rep["changes"], 1), 2),
+            "dt_first_last_min_max": [dts[0], dts[-1], min(dts), max(dts)],
+            "cfl_last_check": rep["cfl"]}
+
+
 def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
@@ -275,6 +306,7 @@ def main():
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-nk", action="store_true", help="skip the Newton-Krylov search")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 96-member ensemble")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the run under time-step control")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (a known byte count "
                          "for scaling HBM counters)")
@@ -356,6 +388,12 @@ def main():
                         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, True) / ms32 / 1e9, 1),
                         "kernel_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
                         "roofline": roofline(prof32, True, "mixed")}
+    if not args.no_adaptive:
+        ad = run_adaptive(w, args.steps, args.warmup)
+        ad["fixed_dt_steps_per_s"] = out["value"]
+        ad["fixed_dt_sim_time_per_s"] = round(w["dt"] / ms64, 4)
+        out["adaptive_dt"] = ad
+        progress(f"adaptive dt: {ad['steps_per_s']} steps/s, {ad['changes']} changes")
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble()
         progress(f"ensemble: {out['ensemble']['ms_per_step']} ms/step")

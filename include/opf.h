@@ -336,6 +336,56 @@ const char* opf_mlp_last_error(const opf_mlp* net);
  * OPF_E_NUMERIC, with *out filled, when a value is not finite or cfl > 1. */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
 
+/* ---- Automatic time-step control ------------------------------------------
+ * Section 2: the predictor-corrector scheme runs with automatic time-step
+ * control.  The paper gives no rule; the one implemented here:
+ *  - Courant limit: with U = cfl / dt (cfl as in opf_diag), dt_c = C / U;
+ *  - corrector limit: the last correction delta = ||u^{n+1} - u^p|| (energy
+ *    norm of opf_vec_dot; u^p the iterate before the last corrector) is
+ *    O(dt^2), so dt_e = dt sqrt(tau / delta);
+ *  - every check_every steps: lim = min(dt_c, dt_e),
+ *    new = min(dt_max, lim / (1 + h)); dt shrinks to new when dt > lim and
+ *    grows to new when new > dt and (new >= (1 + h) dt or new == dt_max);
+ *    new < dt_min is OPF_E_NUMERIC.  A new dt applies from the next step
+ *    on; no step is repeated. */
+
+/* Rebuild every dt-dependent table (Helmholtz factors, homogeneous
+ * solutions, influence matrices, flux Green's function) for a new step size
+ * dt > 0 and upload them on the context's stream (synchronises); the step
+ * graph is captured again at the next opf_step.  The state is kept.
+ * OPF_E_NUMERIC (context unchanged) if a factor fails; OPF_E_UNSUPPORTED for
+ * an ensemble member (its step runs in the class graph). */
+opf_status opf_set_dt(opf_ctx* ctx, double dt);
+
+/* delta = ||u^{n+1} - u^p|| of the last step taken by opf_step (host result,
+ * synchronises).  In mixed precision u^p is the FP32 iterate.  OPF_E_STATE if
+ * no step was taken since opf_set_state or the buffer was reused since. */
+opf_status opf_pc_difference(opf_ctx* ctx, double* out_host);
+
+typedef struct {
+    double courant;       /* C > 0: the CFL number to aim for (0.5)            */
+    double pc_tol;        /* tau >= 0: limit on delta; 0 switches it off       */
+    double dt_min;        /* > 0                                               */
+    double dt_max;        /* >= dt_min; the context's dt must lie in between   */
+    double grow;          /* h >= 0: headroom and growth threshold (0.1)       */
+    int32_t check_every;  /* >= 1 steps between checks (10)                    */
+} opf_dt_control;
+
+typedef struct {
+    int32_t steps, checks, changes;
+    double t;             /* simulated time of the steps taken                 */
+    double dt;            /* step size in force on return                      */
+    double cfl, pc_diff;  /* at the last check                                 */
+    double rebuild_ms;    /* host time spent in opf_set_dt                     */
+} opf_dt_report;
+
+/* nsteps steps under the control above (graph launches between checks; each
+ * check synchronises).  dt_trace (host, nsteps doubles, or NULL) receives the
+ * step size of every step.  *report is filled also on error.
+ * OPF_E_UNSUPPORTED for an ensemble member. */
+opf_status opf_step_adaptive(opf_ctx* ctx, int32_t nsteps, const opf_dt_control* ctl,
+                             double* dt_trace_host, opf_dt_report* report);
+
 /* ---- Ensembles of independent trajectories -------------------------------
  * Members with equal (N, M, K, mp, precision) form a class; every kernel of
  * the step runs once per class over all its members, and one step of every

@@ -27,8 +27,8 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pair_gradient",
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
-           "opf_ensemble_last_error", "opf_probe_pairs_ensemble",
-           "opf_status_string", "opf_last_error"]
+           "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
+           "opf_step_adaptive", "opf_status_string", "opf_last_error"]
 
 
 class opf_params(ctypes.Structure):
@@ -45,6 +45,17 @@ class opf_diag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("E", "I", "D", "tau_w", "flux", "beta", "E_lam", "I_lam", "D_lam", "g_norm", "div_max",
                  "cfl")]
+
+
+class opf_dt_control(ctypes.Structure):
+    _fields_ = [("courant", ctypes.c_double), ("pc_tol", ctypes.c_double), ("dt_min", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("grow", ctypes.c_double), ("check_every", ctypes.c_int32)]
+
+
+class opf_dt_report(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("checks", ctypes.c_int32), ("changes", ctypes.c_int32),
+                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("pc_diff", ctypes.c_double), ("rebuild_ms", ctypes.c_double)]
 
 
 class opf_nk_opts(ctypes.Structure):
@@ -131,6 +142,9 @@ def load_library(path=LIB_PATH):
         "opf_ensemble_tune": ([vp, i32, ctypes.c_char_p, ctypes.c_size_t], i32),
         "opf_ensemble_last_error": ([vp], ctypes.c_char_p),
         "opf_probe_pairs_ensemble": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp, vp], i32),
+        "opf_set_dt": ([vp, dbl], i32),
+        "opf_pc_difference": ([vp, P(ctypes.c_double)], i32),
+        "opf_step_adaptive": ([vp, i32, P(opf_dt_control), P(ctypes.c_double), P(opf_dt_report)], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -255,6 +269,33 @@ class Solver:
 
     def step(self, n=1):
         self._check(self.lib.opf_step(self.ctx, int(n)))
+
+    def set_dt(self, dt):
+        """Rebuild the dt-dependent operator tables for a new step size."""
+        self._check(self.lib.opf_set_dt(self.ctx, float(dt)))
+        self.p.dt = float(dt)
+
+    def pc_difference(self):
+        """||u^{n+1} - u^p|| (energy norm) of the last step."""
+        out = ctypes.c_double()
+        self._check(self.lib.opf_pc_difference(self.ctx, ctypes.byref(out)))
+        return out.value
+
+    def step_adaptive(self, n, courant=0.5, pc_tol=0.0, dt_min=1e-6, dt_max=0.05, grow=0.1, check_every=10,
+                      trace=False):
+        """n steps under automatic time-step control; returns the report as a
+        dict (with "dts", the step size of every step, when trace=True)."""
+        ctl = opf_dt_control(float(courant), float(pc_tol), float(dt_min), float(dt_max), float(grow),
+                             int(check_every))
+        rep = opf_dt_report()
+        buf = (ctypes.c_double * max(int(n), 1))() if trace else None
+        st = self.lib.opf_step_adaptive(self.ctx, int(n), ctypes.byref(ctl), buf, ctypes.byref(rep))
+        self.p.dt = rep.dt
+        self._check(st)
+        out = {name: getattr(rep, name) for name, _ in opf_dt_report._fields_}
+        if trace:
+            out["dts"] = list(buf)[:int(n)]
+        return out
 
     def nonlinear(self, u):
         u = self._dev(u, self.shape)

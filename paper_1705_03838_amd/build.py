@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libopf.so")
-SOURCES = ["opf_host.hip", "opf_transform.hip", "opf_solve.hip", "opf_mlp.hip"]
+SOURCES = ["opf_host.hip", "opf_transform.hip", "opf_solve.hip", "opf_factor.hip", "opf_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -3,6 +3,7 @@
 // influence-matrix data, FFT twiddles), workspace layout and the captured
 // step graph.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -18,7 +19,7 @@ using cd = std::complex<double>;
 
 struct opf_ctx {
     opf_params p{};
-    std::vector<double> r, rinv, quad, d1, d2, green;  // host copies
+    std::vector<double> r, rinv, quad, d1, d2;  // host copies
     std::vector<int> s0;
     int nk = 0, MU = 0, nfac = 0, gm = 1;
     double qG_inv = 0.0;
@@ -35,6 +36,8 @@ struct opf_ctx {
     float *u32 = nullptr, *up32 = nullptr;
     void *twz = nullptr, *twt = nullptr;
     bool have_state = false;
+    bool pc_valid = false;  // up / up32 hold the iterate before the last corrector of the last step
+    bool in_ensemble = false;  // member of an ensemble: its step runs in the class graph, dt is fixed
     std::string err;
 };
 
@@ -144,99 +147,6 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
     }
 }
 
-// ---- banded operators and LU ------------------------------------------
-// Dense N x N radial Laplacian L_{mu,kappa} (row N-1 left for the caller).
-void build_lap(const opf_ctx& c, int mu, double kap, std::vector<double>& A) {
-    const int N = c.p.N, par = std::abs(mu) & 1;
-    A.assign((size_t)N * N, 0.0);
-    for (int n = 0; n < N; ++n) {
-        for (int j = 0; j < W9; ++j) {
-            const int col = c.s0[n] + j;
-            A[(size_t)n * N + col] += c.d2[(par * N + n) * W9 + j] + c.rinv[n] * c.d1[(par * N + n) * W9 + j];
-        }
-        A[(size_t)n * N + n] -= double(mu) * mu * c.rinv[n] * c.rinv[n] + kap * kap;
-    }
-}
-
-// LU without pivoting of a matrix with at most 8 sub- and 4 super-diagonals;
-// writes the FACW-wide factor rows.  Returns false on element growth.
-bool band_lu(std::vector<double>& A, int N, double* F) {
-    double amax = 0.0;
-    for (double v : A) amax = std::max(amax, std::fabs(v));
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-            if ((j < i - 8 || j > i + 4) && A[(size_t)i * N + j] != 0.0) return false;
-    for (int j = 0; j < N; ++j) {
-        const double piv = A[(size_t)j * N + j];
-        if (!(std::fabs(piv) > 1e-14 * amax)) return false;
-        for (int i = j + 1; i <= std::min(N - 1, j + 8); ++i) {
-            const double l = A[(size_t)i * N + j] / piv;
-            A[(size_t)i * N + j] = l;
-            for (int col = j + 1; col <= std::min(N - 1, j + 4); ++col) A[(size_t)i * N + col] -= l * A[(size_t)j * N + col];
-        }
-    }
-    double umax = 0.0, lmax = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) {
-            const double v = std::fabs(A[(size_t)i * N + j]);
-            if (j >= i) umax = std::max(umax, v);
-            else lmax = std::max(lmax, v);
-        }
-    if (umax > 1e3 * amax || lmax > 1e3) return false;
-    // column records: row i of F holds column i of L below the diagonal
-    // (L[i+1..i+8][i]), column i of U above it (U[i-1..i-4][i]) and 1/U_ii
-    for (int i = 0; i < N; ++i) {
-        double* f = F + (size_t)i * FACW;
-        for (int j = 0; j < FACW; ++j) f[j] = 0.0;
-        for (int d = 0; d < 8; ++d)
-            if (i + 1 + d < N) f[d] = A[(size_t)(i + 1 + d) * N + i];
-        for (int d = 0; d < 4; ++d)
-            if (i - 1 - d >= 0) f[8 + d] = A[(size_t)(i - 1 - d) * N + i];
-        f[12] = 1.0 / A[(size_t)i * N + i];
-    }
-    return true;
-}
-
-// Host solve with a column-record factor (right-looking, as on the device).
-void band_solve(const double* F, int N, double* v) {
-    for (int i = 0; i < N; ++i) {
-        const double* f = F + (size_t)i * FACW;
-        for (int d = 0; d < 8; ++d)
-            if (i + 1 + d < N) v[i + 1 + d] -= f[d] * v[i];
-    }
-    for (int i = N - 1; i >= 0; --i) {
-        const double* f = F + (size_t)i * FACW;
-        v[i] *= f[12];
-        for (int d = 0; d < 4; ++d)
-            if (i - 1 - d >= 0) v[i - 1 - d] -= f[8 + d] * v[i];
-    }
-}
-
-bool invert4(cd A[4][4], cd X[4][4]) {
-    cd M[4][8];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-            M[i][j] = A[i][j];
-            M[i][4 + j] = i == j ? 1.0 : 0.0;
-        }
-    for (int c = 0; c < 4; ++c) {
-        int piv = c;
-        for (int i = c + 1; i < 4; ++i)
-            if (std::abs(M[i][c]) > std::abs(M[piv][c])) piv = i;
-        if (std::abs(M[piv][c]) == 0.0) return false;
-        for (int j = 0; j < 8; ++j) std::swap(M[c][j], M[piv][j]);
-        const cd d = M[c][c];
-        for (int j = 0; j < 8; ++j) M[c][j] /= d;
-        for (int i = 0; i < 4; ++i)
-            if (i != c) {
-                const cd f = M[i][c];
-                for (int j = 0; j < 8; ++j) M[i][j] -= f * M[c][j];
-            }
-    }
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) X[i][j] = M[i][4 + j];
-    return true;
-}
 
 // Nodes, folded finite-difference weights and quadrature (host, create time).
 void build_grid(opf_ctx* c, const double* r_nodes) {
@@ -295,7 +205,7 @@ void build_grid(opf_ctx* c, const double* r_nodes) {
 }
 
 struct Layout {
-    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, twz, twt;
+    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, flags, qg, twz, twt;
     size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, dpart, cflw, cpart, total;
 };
 
@@ -318,6 +228,8 @@ Layout layout(const opf_params& p) {
     L.hom = take(M * K * NHOM * N * 8);
     L.ainv = take(M * nk * 16 * 16);
     L.green = take(N * 8);
+    L.flags = take((nfac + M * nk) * 4);
+    L.qg = take(8);
     L.twz = take(3 * K * 16);
     L.twt = take(3 * M * 16);
     L.u = take(3 * S * 16);
@@ -387,6 +299,36 @@ __global__ __launch_bounds__(256) void k_wdot(const double* __restrict__ a, cons
         for (int c = 0; c < 3; ++c) {
             const size_t j = 2 * (c * S + off);
             sum += a[j] * b[j] + a[j + 1] * b[j + 1];
+        }
+        acc += quad[n] * sum;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[mi] = red[0];
+}
+
+// Per-m partial sums of w_n |a - b|^2 over components, k and n (the squared
+// energy norm of a - b before the m weights); b in the working precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcdiff(const double* __restrict__ a, const T* __restrict__ b,
+                                                const double* __restrict__ quad, double* __restrict__ partial,
+                                                int N, int M, int nk) {
+    __shared__ double red[256];
+    const int mi = blockIdx.x;
+    const size_t S = (size_t)M * nk * N;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nk * N; i += 256) {
+        const int n = i % N;
+        const size_t off = (size_t)mi * nk * N + i;
+        double sum = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const size_t j = 2 * (c * S + off);
+            const double dr = a[j] - (double)b[j], di = a[j + 1] - (double)b[j + 1];
+            sum += dr * dr + di * di;
         }
         acc += quad[n] * sum;
     }
@@ -495,6 +437,55 @@ SolveArgs solve_args(const opf_ctx* c, int kind) {
     return a;
 }
 
+// Operator tables for the current dt, built on the device (with pressure,
+// also the dt-independent pressure factors and unit-wall pressures), then
+// the status flags and the Green's function integral read back
+// (synchronises).  On failure c->err names the table.
+opf_status device_tables(opf_ctx* c, bool pressure) {
+    const opf_params& p = c->p;
+    const Layout Lo = layout(p);
+    FactorArgs a{};
+    a.N = p.N;
+    a.M = p.M;
+    a.K = p.K;
+    a.MU = c->MU;
+    a.mp = p.mp;
+    a.alpha = p.alpha;
+    a.cr = p.c / p.Re;
+    a.inv_dt = 1.0 / p.dt;
+    a.rinv = c->t.rinv;
+    a.quad = c->t.quad;
+    a.d1 = c->t.d1;
+    a.d2 = c->t.d2;
+    a.s0 = c->t.s0;
+    a.fac = reinterpret_cast<double*>(c->ws + Lo.fac);
+    a.hom = reinterpret_cast<double*>(c->ws + Lo.hom);
+    a.ainv = reinterpret_cast<double*>(c->ws + Lo.ainv);
+    a.green = reinterpret_cast<double*>(c->ws + Lo.green);
+    a.flags = reinterpret_cast<int*>(c->ws + Lo.flags);
+    a.qg = reinterpret_cast<double*>(c->ws + Lo.qg);
+    HIPCHK(c, launch_operator_tables(a, pressure, c->stream));
+    const int nh = c->MU * p.K, np = p.M * p.K, modes = p.M * c->nk;
+    std::vector<int> fl(nh + np + modes);
+    double qg = 0.0;
+    HIPCHK(c, hipMemcpyAsync(fl.data(), a.flags, fl.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&qg, a.qg, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int q = 0; q < nh + np + modes; ++q)
+        if (fl[q] != 0 && (q < nh || pressure)) {
+            c->err = q < nh ? "Helmholtz factor unstable without pivoting"
+                   : q < nh + np ? "pressure factor unstable without pivoting" : "singular influence matrix";
+            return OPF_E_NUMERIC;
+        }
+    if (!(std::isfinite(qg) && qg != 0.0)) {
+        c->err = "flux Green's function has no flux";
+        return OPF_E_NUMERIC;
+    }
+    c->qG_inv = 1.0 / qg;
+    c->t.qG_inv = c->qG_inv;
+    return OPF_OK;
+}
+
 // Enqueue one predictor-corrector step (captured into the step graph).
 opf_status enqueue_step(opf_ctx* c, hipStream_t s) {
     const bool mixed = c->p.precision == OPF_MIXED;
@@ -546,6 +537,51 @@ opf_status refresh_derived(opf_ctx* c) {
         HIPCHK(c, launch_vorticity(x, c->stream));
     }
     return OPF_OK;
+}
+
+// CFL: z-inverse transform of the state's velocity and vorticity (the H
+// buffer), then per-block maxima over the theta-inverse velocity lines of
+// |u_r|/dr + |u_theta|/(r dtheta) + |u_z|/dz into cpart.
+hipError_t enqueue_cfl(opf_ctx* c) {
+    const int N = c->p.N, K = c->p.K;
+    const bool mixed = c->p.precision == OPF_MIXED;
+    const NLArgs nl = nl_args(c, mixed ? (const void*)c->u32 : (const void*)c->u, c->w, c->Nn);
+    hipError_t he = launch_nonlinear_stage(nl, c->p.precision, 0, c->stream);
+    if (he != hipSuccess) return he;
+    return launch_cfl(nl, c->p.precision, c->cflw, c->cflw + N, c->p.alpha * 3 * K / (2.0 * M_PI), c->cpart,
+                      c->stream);
+}
+size_t cfl_parts(const opf_ctx* c) { return (size_t)c->p.N * ((3 * c->p.K + 3) / 4); }
+
+// Per-m partial sums of the last correction into partial[0..M).
+hipError_t enqueue_pcdiff(opf_ctx* c) {
+    const int M = c->p.M;
+    if (c->p.precision == OPF_MIXED)
+        hipLaunchKernelGGL(k_pcdiff<float>, dim3(M), dim3(256), 0, c->stream, c->u, c->up32, c->t.quad,
+                           c->partial, c->p.N, M, c->nk);
+    else
+        hipLaunchKernelGGL(k_pcdiff<double>, dim3(M), dim3(256), 0, c->stream, c->u, c->up, c->t.quad,
+                           c->partial, c->p.N, M, c->nk);
+    return hipGetLastError();
+}
+double weighted_norm(const std::vector<double>& part) {
+    double s = 0.0;
+    for (size_t m = 0; m < part.size(); ++m) s += (m == 0 ? 1.0 : 2.0) * part[m];
+    return std::sqrt(s);
+}
+
+// The step size after a check (the rule declared with opf_dt_control); a
+// value below dt_min is returned as is and rejected by the caller.
+double next_dt(double dt, double cfl, double delta, const opf_dt_control& k) {
+    const double U = cfl / dt;
+    const double dt_c = U > 0 ? k.courant / U : INFINITY;
+    const double dt_e = k.pc_tol > 0 && delta > 0 ? dt * std::sqrt(k.pc_tol / delta) : INFINITY;
+    const double lim = std::min(dt_c, dt_e);
+    const double nw = std::min(k.dt_max, lim / (1.0 + k.grow));
+    if (nw < k.dt_min) return nw;
+    if (dt > lim) return nw;
+    if (nw > dt && (nw >= (1.0 + k.grow) * dt || nw == k.dt_max)) return nw;
+    return dt;
 }
 
 }  // namespace
@@ -635,127 +671,6 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
 
     build_grid(c, p->r_nodes);
 
-    // banded LU factors: H_{|mu|,|k|} then L_{m,|k|} (pressure, P(1) = 0)
-    std::vector<double> fac((size_t)c->nfac * N * FACW);
-    std::vector<double> A;
-    const double cr = p->c / p->Re;
-    for (int mu = 0; mu < c->MU; ++mu)
-        for (int k = 0; k < K; ++k) {
-            build_lap(*c, mu, p->alpha * k, A);
-            for (size_t i = 0; i < A.size(); ++i) A[i] = -cr * A[i];
-            for (int n = 0; n < N; ++n) A[(size_t)n * N + n] += 1.0 / p->dt;
-            for (int j = 0; j < N; ++j) A[(size_t)(N - 1) * N + j] = j == N - 1 ? 1.0 : 0.0;
-            if (!band_lu(A, N, &fac[((size_t)mu * K + k) * N * FACW])) {
-                c->err = "Helmholtz factor unstable without pivoting";
-                delete c;
-                return OPF_E_NUMERIC;
-            }
-        }
-    for (int mi = 0; mi < M; ++mi)
-        for (int k = 0; k < K; ++k) {
-            double* F = &fac[((size_t)c->MU * K + (size_t)mi * K + k) * N * FACW];
-            if (mi == 0 && k == 0) {  // unused: (0,0) has no pressure solve
-                for (int n = 0; n < N; ++n) F[(size_t)n * FACW + 12] = 1.0;
-                continue;
-            }
-            build_lap(*c, p->mp * mi, p->alpha * k, A);
-            for (int j = 0; j < N; ++j) A[(size_t)(N - 1) * N + j] = j == N - 1 ? 1.0 : 0.0;
-            if (!band_lu(A, N, F)) {
-                c->err = "pressure factor unstable without pivoting";
-                delete c;
-                return OPF_E_NUMERIC;
-            }
-        }
-    auto Hf = [&](int mu, int k) { return &fac[((size_t)std::abs(mu) * K + k) * N * FACW]; };
-    auto Lf = [&](int mi, int k) { return &fac[((size_t)c->MU * K + (size_t)mi * K + k) * N * FACW]; };
-
-    // influence data per (m,|k|) and inverse influence matrices per (m,k)
-    std::vector<double> hom((size_t)M * K * NHOM * N, 0.0);
-    std::vector<double> ainv((size_t)M * nk * 32, 0.0);
-    const int e = N - 1;
-    auto d1row = [&](int par, const std::vector<double>& v) {
-        double acc = 0.0;
-        for (int j = 0; j < W9; ++j) acc += c->d1[(par * N + e) * W9 + j] * v[c->s0[e] + j];
-        return acc;
-    };
-    for (int mi = 0; mi < M; ++mi) {
-        const int m = p->mp * mi;
-        for (int ka = 0; ka < K; ++ka) {
-            if (mi == 0 && ka == 0) continue;
-            double* h = &hom[((size_t)mi * K + ka) * NHOM * N];
-            std::vector<double> P1(N, 0.0), gp(N), gm(N), v(N);
-            P1[N - 1] = 1.0;
-            band_solve(Lf(mi, ka), N, P1.data());
-            for (int n = 0; n < N; ++n) {
-                double dP = 0.0;
-                for (int j = 0; j < W9; ++j) dP += c->d1[((m & 1) * N + n) * W9 + j] * P1[c->s0[n] + j];
-                gp[n] = dP - m * P1[n] * c->rinv[n];
-                gm[n] = dP + m * P1[n] * c->rinv[n];
-            }
-            std::vector<double> h1p(N), h1m(N), q(N), h2(N, 0.0), h3(N, 0.0), h4(N, 0.0);
-            for (int n = 0; n < N; ++n) { h1p[n] = -gp[n]; h1m[n] = -gm[n]; q[n] = P1[n]; }
-            h1p[N - 1] = h1m[N - 1] = q[N - 1] = 0.0;
-            h2[N - 1] = h3[N - 1] = h4[N - 1] = 1.0;
-            band_solve(Hf(m + 1, ka), N, h1p.data());
-            band_solve(Hf(m - 1, ka), N, h1m.data());
-            band_solve(Hf(m, ka), N, q.data());
-            band_solve(Hf(m + 1, ka), N, h2.data());
-            band_solve(Hf(m - 1, ka), N, h3.data());
-            band_solve(Hf(m, ka), N, h4.data());
-            for (int n = 0; n < N; ++n) {
-                h[n] = h1p[n];
-                h[N + n] = h1m[n];
-                h[2 * N + n] = q[n];
-                h[3 * N + n] = h2[n];
-                h[4 * N + n] = h3[n];
-                h[5 * N + n] = h4[n];
-                h[6 * N + n] = P1[n];
-            }
-            const int po = (m + 1) & 1;
-            const double re = c->rinv[e];
-            for (int sg = -1; sg <= 1; sg += 2) {
-                const int k = sg * ka;
-                if (ka == 0 && sg < 0) continue;
-                const double kap = p->alpha * k;
-                // g(v) = (v+(1), v-(1), v_z(1), div v(1)) for each homogeneous solution
-                auto divw = [&](const std::vector<double>& vp, const std::vector<double>& vm) {
-                    return 0.5 * (d1row(po, vp) + (1 + m) * vp[e] * re) + 0.5 * (d1row(po, vm) + (1 - m) * vm[e] * re);
-                };
-                const std::vector<double> zero(N, 0.0);
-                cd Am[4][4], Ai[4][4];
-                const cd I(0.0, 1.0);
-                // h1: (h1p, h1m, -i kappa q)
-                Am[0][0] = h1p[e];
-                Am[1][0] = h1m[e];
-                Am[2][0] = -I * kap * q[e];
-                Am[3][0] = divw(h1p, h1m) + I * kap * (-I * kap * q[e]);
-                Am[0][1] = h2[e]; Am[1][1] = 0.0; Am[2][1] = 0.0; Am[3][1] = divw(h2, zero);
-                Am[0][2] = 0.0; Am[1][2] = h3[e]; Am[2][2] = 0.0; Am[3][2] = divw(zero, h3);
-                Am[0][3] = 0.0; Am[1][3] = 0.0; Am[2][3] = h4[e]; Am[3][3] = I * kap * h4[e];
-                if (!invert4(Am, Ai)) {
-                    c->err = "singular influence matrix";
-                    delete c;
-                    return OPF_E_NUMERIC;
-                }
-                double* dst = &ainv[(((size_t)mi * nk + (k + K - 1)) * 16) * 2];
-                for (int i = 0; i < 4; ++i)
-                    for (int j = 0; j < 4; ++j) {
-                        dst[2 * (4 * i + j)] = Ai[i][j].real();
-                        dst[2 * (4 * i + j) + 1] = Ai[i][j].imag();
-                    }
-            }
-        }
-    }
-    // flux Green's function: H_0 u_G = 1 (interior), u_G(1) = 0
-    c->green.assign(N, 1.0);
-    c->green[N - 1] = 0.0;
-    band_solve(Hf(0, 0), N, c->green.data());
-    {
-        double qg = 0.0;
-        for (int n = 0; n < N; ++n) qg += c->quad[n] * c->green[n];
-        c->qG_inv = 1.0 / qg;
-    }
-
     // FFT twiddles e^{-2 pi i t / L}
     const bool mixed = p->precision == OPF_MIXED;
     auto twiddles = [&](int L, std::vector<double>& d, std::vector<float>& f) {
@@ -786,10 +701,6 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     if (he == hipSuccess) he = up(Lo.d1, c->d1.data(), c->d1.size() * 8);
     if (he == hipSuccess) he = up(Lo.d2, c->d2.data(), c->d2.size() * 8);
     if (he == hipSuccess) he = up(Lo.s0, c->s0.data(), N * 4);
-    if (he == hipSuccess) he = up(Lo.fac, fac.data(), fac.size() * 8);
-    if (he == hipSuccess) he = up(Lo.hom, hom.data(), hom.size() * 8);
-    if (he == hipSuccess) he = up(Lo.ainv, ainv.data(), ainv.size() * 8);
-    if (he == hipSuccess) he = up(Lo.green, c->green.data(), N * 8);
     // CFL weights: 1/dr_n (nearer neighbour; the axis mirror -r_0 for n = 0) and 1/(r_n dtheta)
     std::vector<double> cflw(2 * N);
     for (int n = 0; n < N; ++n) {
@@ -835,6 +746,12 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->dpart = reinterpret_cast<double*>(ws + Lo.dpart);
     c->cflw = reinterpret_cast<double*>(ws + Lo.cflw);
     c->cpart = reinterpret_cast<double*>(ws + Lo.cpart);
+    // banded LU factors, influence data and Green's function on the device
+    const opf_status st2 = device_tables(c, true);
+    if (st2 != OPF_OK) {
+        delete c;
+        return st2;
+    }
     *out = c;
     return OPF_OK;
 }
@@ -859,6 +776,7 @@ opf_status opf_set_state(opf_ctx* c, const void* u) {
     const opf_status st = refresh_derived(c);
     if (st != OPF_OK) return st;
     c->have_state = true;
+    c->pc_valid = false;
     return OPF_OK;
 }
 
@@ -895,6 +813,7 @@ opf_status opf_step(opf_ctx* c, int32_t nsteps) {
         }
     }
     for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    if (nsteps > 0) c->pc_valid = true;
     return OPF_OK;
 }
 
@@ -956,6 +875,7 @@ opf_status opf_profile_steps(opf_ctx* c, int32_t nsteps, double* ms, int32_t* la
         c->err = std::string("profile: ") + hipGetErrorString(he);
         return OPF_E_HIP;
     }
+    c->pc_valid = true;
     return OPF_OK;
 }
 
@@ -984,6 +904,7 @@ opf_status opf_nonlinear(opf_ctx* c, const void* u, void* n) {
     if (st != OPF_OK) return st;
     if (c->p.precision == OPF_MIXED) {
         float* uin = c->up32;
+        c->pc_valid = false;
         float* win = static_cast<float*>(c->w);
         float* nout = reinterpret_cast<float*>(c->Np);
         HIPCHK(c, to_f32(static_cast<const double*>(u), uin, cnt, c->stream));
@@ -1032,14 +953,8 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     HIPCHK(c, launch_vorticity(x, c->stream));
     HIPCHK(c, launch_energy(x, c->stream));
     HIPCHK(c, launch_divg(x, c->dpart, c->stream));
-    // CFL: z-inverse transform of u and omega, then theta-inverse of the velocity lines
-    const bool mixed = c->p.precision == OPF_MIXED;
-    const NLArgs nl = nl_args(c, mixed ? (const void*)c->u32 : (const void*)c->u, c->w, c->Nn);
-    HIPCHK(c, launch_nonlinear_stage(nl, c->p.precision, 0, c->stream));
-    HIPCHK(c, launch_cfl(nl, c->p.precision, c->cflw, c->cflw + N, c->p.alpha * 3 * K / (2.0 * M_PI), c->cpart,
-                         c->stream));
-    const int ncfl = N * ((3 * K + 3) / 4);
-    std::vector<double> dp(2 * (size_t)M * c->nk), cp(ncfl);
+    HIPCHK(c, enqueue_cfl(c));
+    std::vector<double> dp(2 * (size_t)M * c->nk), cp(cfl_parts(c));
     HIPCHK(c, hipMemcpyAsync(dp.data(), c->dpart, dp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(cp.data(), c->cpart, cp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     std::vector<double> part(2 * M), uz(2 * N);
@@ -1082,6 +997,107 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
         c->err = "CFL number above 1";
         return OPF_E_NUMERIC;
     }
+    return OPF_OK;
+}
+
+opf_status opf_set_dt(opf_ctx* c, double dt) {
+    if (!c || !(dt > 0) || !std::isfinite(dt)) return OPF_E_INVALID;
+    if (c->in_ensemble) {
+        c->err = "ensemble members keep the dt of their class graph";
+        return OPF_E_UNSUPPORTED;
+    }
+    if (dt == c->p.dt) return OPF_OK;
+    const double old = c->p.dt;
+    c->p.dt = dt;
+    // stream order puts the rebuild after every step already enqueued
+    const opf_status st = device_tables(c, false);
+    if (st != OPF_OK) {
+        const std::string why = c->err;
+        c->p.dt = old;
+        const opf_status back = device_tables(c, false);
+        c->err = why;
+        if (back != OPF_OK) c->have_state = false;  // tables lost: refuse to step
+        return st;
+    }
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return OPF_OK;
+}
+
+opf_status opf_pc_difference(opf_ctx* c, double* out) {
+    if (!c || !out) return OPF_E_INVALID;
+    if (!c->have_state || !c->pc_valid) return OPF_E_STATE;
+    HIPCHK(c, enqueue_pcdiff(c));
+    std::vector<double> part(c->p.M);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *out = weighted_norm(part);
+    return std::isfinite(*out) ? OPF_OK : OPF_E_NUMERIC;
+}
+
+opf_status opf_step_adaptive(opf_ctx* c, int32_t nsteps, const opf_dt_control* k, double* trace,
+                             opf_dt_report* rep) {
+    if (!c || !k || !rep || nsteps < 0) return OPF_E_INVALID;
+    *rep = opf_dt_report{};
+    rep->dt = c->p.dt;
+    if (c->in_ensemble) {
+        c->err = "ensemble members keep the dt of their class graph";
+        return OPF_E_UNSUPPORTED;
+    }
+    if (!(k->courant > 0) || !(k->pc_tol >= 0) || !(k->dt_min > 0) || !(k->dt_max >= k->dt_min) ||
+        !(k->grow >= 0) || k->check_every < 1 || !std::isfinite(k->dt_max) || !std::isfinite(k->grow))
+        return OPF_E_INVALID;
+    if (c->p.dt < k->dt_min || c->p.dt > k->dt_max) {
+        c->err = "dt outside [dt_min, dt_max]";
+        return OPF_E_INVALID;
+    }
+    if (!c->have_state) return OPF_E_STATE;
+    const int M = c->p.M;
+    std::vector<double> part(M), cp(cfl_parts(c));
+    int done = 0;
+    while (done < nsteps) {
+        const int run = std::min(nsteps - done, k->check_every - done % k->check_every);
+        for (int i = 0; i < run; ++i) {
+            if (trace) trace[done + i] = c->p.dt;
+            rep->t += c->p.dt;
+        }
+        const opf_status st = opf_step(c, run);
+        if (st != OPF_OK) return st;
+        done += run;
+        rep->steps = done;
+        if (done % k->check_every != 0) break;  // only at the end of the run
+        HIPCHK(c, enqueue_cfl(c));
+        HIPCHK(c, enqueue_pcdiff(c));
+        HIPCHK(c, hipMemcpyAsync(cp.data(), c->cpart, cp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, M * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double cm = 0.0;
+        for (double v : cp) cm = std::max(cm, v);
+        const double dt = c->p.dt;
+        rep->cfl = dt * cm;
+        rep->pc_diff = weighted_norm(part);
+        rep->checks += 1;
+        if (!std::isfinite(rep->cfl) || !std::isfinite(rep->pc_diff)) {
+            c->err = "non-finite CFL number or correction";
+            return OPF_E_NUMERIC;
+        }
+        const double nw = next_dt(dt, rep->cfl, rep->pc_diff, *k);
+        if (nw < k->dt_min) {
+            c->err = "time step below dt_min";
+            return OPF_E_NUMERIC;
+        }
+        if (nw != dt) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const opf_status s2 = opf_set_dt(c, nw);
+            rep->rebuild_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (s2 != OPF_OK) return s2;
+            rep->changes += 1;
+            rep->dt = nw;
+        }
+    }
+    rep->dt = c->p.dt;
     return OPF_OK;
 }
 
@@ -1466,6 +1482,7 @@ opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* w
             delete e;
             return st;
         }
+        c->in_ensemble = true;
         e->members.push_back(c);
     }
     for (int i = 0; i < count; ++i) {

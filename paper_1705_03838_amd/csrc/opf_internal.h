@@ -84,6 +84,30 @@ struct AuxArgs {
     Tables t;
 };
 
+// Arguments of the operator-table kernels (banded LU factors, influence
+// data, flux Green's function), written into the workspace tables.
+struct FactorArgs {
+    int N, M, K, MU, mp;
+    double alpha;
+    double cr;          // c / Re
+    double inv_dt;      // 1 / dt
+    const double* rinv;
+    const double* quad;
+    const double* d1;
+    const double* d2;
+    const int* s0;
+    double* fac;        // [MU K + M K][N][FACW]: H_{|mu|,|k|} then L_{m,|k|}
+    double* hom;        // [M][K][NHOM][N]
+    double* ainv;       // [M][2K-1][16][2]
+    double* green;      // [N]
+    int* flags;         // [MU K + M K] factor status, then [M (2K-1)] influence status
+    double* qg;         // int_0^1 u_G r dr (device scalar)
+};
+// Factor the Helmholtz operators (and, with pressure, the pressure
+// operators and the unit-wall pressure P1), then the homogeneous solutions,
+// inverse influence matrices and Green's function.
+hipError_t launch_operator_tables(const FactorArgs& a, bool pressure, hipStream_t s);
+
 // Launchers (return the first HIP error).
 hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s);
 // One of the three transform kernels: 0 z-inverse, 1 theta + product, 2 z-forward.
