@@ -24,8 +24,8 @@ used here:
     sets Delta = ||dx|| / 2 when rho < 0.25.  The first Delta is delta0, or
     the length of the first unconstrained step when delta0 <= 0.
 
-Here the subproblem is solved from the normal equations with a bracketing
-root finder; the library solves it through an SVD of Hb.
+Here the subproblem is solved as a damped least-squares problem with a
+bracketing root finder for mu; the library solves it through an SVD of Hb.
 """
 import numpy as np
 from scipy.optimize import brentq
@@ -41,18 +41,23 @@ def hook_subproblem(Hb, beta, delta):
     y, *_ = np.linalg.lstsq(Hb, b, rcond=None)
     mu = 0.0
     if np.linalg.norm(y) > delta:
-        A = Hb.T @ Hb
-        g = Hb.T @ b
-        I = np.eye(k)
+        # y(mu) solves the damped least-squares problem
+        # min ||[Hb; sqrt(mu) I] y - [b; 0]||, whose normal equations are
+        # (Hb^T Hb + mu I) y = Hb^T b (solved by QR, not squaring cond(Hb))
+        zeros = np.zeros(k)
+
+        def y_of(m):
+            return np.linalg.lstsq(np.vstack([Hb, np.sqrt(m) * np.eye(k)]), np.concatenate([b, zeros]),
+                                   rcond=None)[0]
 
         def excess(m):
-            return np.linalg.norm(np.linalg.solve(A + m * I, g)) - delta
+            return np.linalg.norm(y_of(m)) - delta
 
-        hi = max(np.linalg.norm(g) / delta, 1e-300)
+        hi = max(np.linalg.norm(Hb.T @ b) / delta, 1e-300)
         while excess(hi) > 0:
             hi *= 2.0
         mu = brentq(excess, 0.0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
-        y = np.linalg.solve(A + mu * I, g)
+        y = y_of(mu)
     return y, mu, float(np.linalg.norm(b - Hb @ y))
 
 
