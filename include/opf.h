@@ -201,7 +201,20 @@ typedef struct opf_mlp opf_mlp;
  * record_dev: NULL, or device memory for record_capacity pairs of
  * external-layout vectors; each product J z the solver forms is stored as
  * pair i = (z at vector 2i, J z at vector 2i+1) until the capacity is
- * reached (training data for the network). */
+ * reached (training data for the network).
+ *
+ * hookstep != 0 replaces restarts and the line search by the Krylov
+ * trust-region step of the paper's Newton solver (Section 2, after
+ * Viswanath 2007): one Arnoldi cycle from v_1 = -F/||F|| (up to gmres_m
+ * products, stopping at the gmres_tol least-squares residual) gives
+ * J V_k = V_{k+1} Hb; dx = V_k y with y from opf_hookstep_solve for the
+ * current radius Delta.  rho = (||F||^2 - ||F(x+dx)||^2) / (||F||^2 - r^2)
+ * (r the model residual): rho < 0.1 rejects the step and retries with
+ * Delta = ||dx||/2 on the same basis (at most max_hook tries, then the
+ * search stops unconverged); an accepted step doubles Delta (up to
+ * tr_delta_max) if rho > 0.75 and ||dx|| >= 0.99 Delta, and sets
+ * Delta = ||dx||/2 if rho < 0.25.  Not combined with precond (returns
+ * OPF_E_UNSUPPORTED). */
 typedef struct {
     int32_t gmres_m;     /* Krylov dimension per restart, e.g. 40             */
     int32_t max_newton;  /* Newton iterations                                  */
@@ -212,6 +225,11 @@ typedef struct {
     opf_mlp* precond;
     void* record_dev;
     int32_t record_capacity;
+    int32_t hookstep;      /* 0: restarted GMRES + line search; 1: hookstep  */
+    double tr_delta0;      /* first trust radius (energy norm); <= 0: the
+                              length of the first unconstrained step        */
+    double tr_delta_max;   /* largest radius; <= 0: unbounded                */
+    int32_t max_hook;      /* tries per Newton step; <= 0: 12                */
 } opf_nk_opts;
 
 typedef struct {
@@ -220,7 +238,21 @@ typedef struct {
     double residual_history[32];   /* ||F|| / ||x|| after each Newton step   */
     int32_t recorded;              /* pairs written to record_dev            */
     int32_t precond_applies;       /* applications of the preconditioner     */
+    int32_t residual_evals;        /* evaluations of F (each T/dt steps), JVPs excluded */
+    int32_t hook_trials;           /* hookstep candidates evaluated          */
+    int32_t stalled;               /* hookstep: max_hook tries all rejected  */
+    double tr_delta;               /* hookstep: trust radius on return       */
 } opf_nk_report;
+
+/* The hookstep subproblem (host only, no device): y minimising
+ * ||beta e_1 - Hb y|| subject to ||y|| <= delta, for the (k+1) x k matrix Hb
+ * (host, row-major; k >= 1).  Through the SVD Hb = U S W^T (one-sided Jacobi)
+ * with p = beta U^T e_1: y = W z, z_j = p_j s_j / (s_j^2 + mu) (z_j = 0 for
+ * s_j <= 1e-14 max s), mu = 0 if that fits, else the mu > 0 with ||z|| =
+ * delta (safeguarded Newton on 1/||z||).  Outputs: y_host[k], *mu_host and
+ * *resid_host = ||beta e_1 - Hb y||.  delta may be +infinity. */
+opf_status opf_hookstep_solve(const double* hb_host, int32_t k, double beta, double delta,
+                              double* y_host, double* mu_host, double* resid_host);
 
 /* Device bytes for opf_nk_solve: (gmres_m + 5) vectors, plus gmres_m more
  * (the preconditioned directions) when preconditioned != 0. */

@@ -28,7 +28,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
-           "opf_step_adaptive", "opf_status_string", "opf_last_error"]
+           "opf_step_adaptive", "opf_hookstep_solve", "opf_status_string", "opf_last_error"]
 
 
 class opf_params(ctypes.Structure):
@@ -63,14 +63,18 @@ class opf_nk_opts(ctypes.Structure):
                 ("max_jvps", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("gmres_tol", ctypes.c_double), ("fd_eps", ctypes.c_double),
                 ("precond", ctypes.c_void_p), ("record_dev", ctypes.c_void_p),
-                ("record_capacity", ctypes.c_int32)]
+                ("record_capacity", ctypes.c_int32), ("hookstep", ctypes.c_int32),
+                ("tr_delta0", ctypes.c_double), ("tr_delta_max", ctypes.c_double),
+                ("max_hook", ctypes.c_int32)]
 
 
 class opf_nk_report(ctypes.Structure):
     _fields_ = [("newton_iterations", ctypes.c_int32), ("gmres_iterations", ctypes.c_int32),
                 ("jvps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("residual_history", ctypes.c_double * 32),
-                ("recorded", ctypes.c_int32), ("precond_applies", ctypes.c_int32)]
+                ("recorded", ctypes.c_int32), ("precond_applies", ctypes.c_int32),
+                ("residual_evals", ctypes.c_int32), ("hook_trials", ctypes.c_int32),
+                ("stalled", ctypes.c_int32), ("tr_delta", ctypes.c_double)]
 
 
 class opf_mlp_config(ctypes.Structure):
@@ -145,6 +149,8 @@ def load_library(path=LIB_PATH):
         "opf_set_dt": ([vp, dbl], i32),
         "opf_pc_difference": ([vp, P(ctypes.c_double)], i32),
         "opf_step_adaptive": ([vp, i32, P(opf_dt_control), P(ctypes.c_double), P(opf_dt_report)], i32),
+        "opf_hookstep_solve": ([P(ctypes.c_double), i32, dbl, dbl, P(ctypes.c_double), P(ctypes.c_double),
+                                P(ctypes.c_double)], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -154,6 +160,23 @@ def load_library(path=LIB_PATH):
         f.restype = res
     _lib = lib
     return lib
+
+
+def hookstep_solve(Hb, beta, delta):
+    """Host-only hookstep subproblem (no device): (y, mu, model residual)."""
+    import numpy as np
+    lib = load_library()
+    Hb = np.ascontiguousarray(Hb, dtype=np.float64)
+    k = Hb.shape[1]
+    assert Hb.shape == (k + 1, k)
+    y = np.zeros(k)
+    mu, r = ctypes.c_double(), ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.opf_hookstep_solve(Hb.ctypes.data_as(dp), k, float(beta), float(delta), y.ctypes.data_as(dp),
+                                ctypes.byref(mu), ctypes.byref(r))
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+    return y, mu.value, r.value
 
 
 def make_params(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01, c=0.5, n_corr=1,
@@ -350,11 +373,14 @@ class Solver:
         return out.value
 
     def nk_solve(self, x, T, shift, gmres_m=40, max_newton=20, max_jvps=400, tol=1e-8,
-                 gmres_tol=1e-3, fd_eps=1e-7, precond=None, record=None):
+                 gmres_tol=1e-3, fd_eps=1e-7, precond=None, record=None, hookstep=False, tr_delta0=0.0,
+                 tr_delta_max=0.0, max_hook=12):
         """Newton-Krylov travelling-wave search; returns (solution, report dict).
         precond: an Mlp (flexible GMRES with it as right preconditioner) or None.
         record: None, or a complex128 device tensor [n, 2, 3, M, 2K-1, N] that
-        receives the pairs (z, J z) of the products the solver forms."""
+        receives the pairs (z, J z) of the products the solver forms.
+        hookstep: the Krylov trust-region step instead of restarted GMRES and
+        a line search (tr_delta0 <= 0: first radius = first Newton step)."""
         x = self._dev(x, self.shape).clone()
         nbytes = ctypes.c_size_t()
         self._check(self.lib.opf_nk_workspace_size(self.ctx, int(gmres_m), int(precond is not None),
@@ -367,7 +393,8 @@ class Solver:
             cap = record.shape[0]
         o = opf_nk_opts(int(gmres_m), int(max_newton), int(max_jvps), float(tol), float(gmres_tol),
                         float(fd_eps), precond.handle if precond is not None else None,
-                        record.data_ptr() if record is not None else None, int(cap))
+                        record.data_ptr() if record is not None else None, int(cap), int(bool(hookstep)),
+                        float(tr_delta0), float(tr_delta_max), int(max_hook))
         rep = opf_nk_report()
         self._check(self.lib.opf_nk_solve(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
                                           ctypes.byref(o), ctypes.c_void_p(kry.data_ptr()),
@@ -376,7 +403,9 @@ class Solver:
         return x, {"newton_iterations": n, "gmres_iterations": rep.gmres_iterations,
                    "jvps": rep.jvps, "converged": bool(rep.converged), "residual": rep.residual,
                    "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
-                   "recorded": rep.recorded, "precond_applies": rep.precond_applies}
+                   "recorded": rep.recorded, "precond_applies": rep.precond_applies,
+                   "residual_evals": rep.residual_evals, "hook_trials": rep.hook_trials,
+                   "stalled": bool(rep.stalled), "tr_delta": rep.tr_delta}
 
     def probe_pairs(self, x, T, shift, n, seed=1, fd_eps=1e-7, batch=1):
         """n Jacobian probes (z, J z) of the travelling-wave residual at x:

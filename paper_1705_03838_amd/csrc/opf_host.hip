@@ -1147,6 +1147,106 @@ opf_status opf_newton_residual(opf_ctx* c, const void* x, double T, double shift
     return OPF_OK;
 }
 
+opf_status opf_hookstep_solve(const double* hb, int32_t k, double beta, double delta, double* y, double* mu_out,
+                              double* resid) {
+    if (!hb || !y || !mu_out || !resid || k < 1 || !(beta >= 0) || !(delta > 0)) return OPF_E_INVALID;
+    const int rows = k + 1;
+    // one-sided Jacobi SVD: rotate the columns of A = Hb until they are
+    // orthogonal; A W = U S, W the accumulated rotations
+    std::vector<double> A(hb, hb + (size_t)rows * k), W((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) W[(size_t)j * k + j] = 1.0;
+    auto col = [&](std::vector<double>& M, int nr, int nc, int i, int j) -> double& { return M[(size_t)i * nc + j]; };
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = 0; i < rows; ++i) {
+                    const double x = col(A, rows, k, i, p), z = col(A, rows, k, i, q);
+                    a += x * x;
+                    b += z * z;
+                    g += x * z;
+                }
+                if (g == 0.0 || std::fabs(g) <= 1e-15 * std::sqrt(a * b)) continue;
+                rotated = true;
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < rows; ++i) {
+                    const double x = col(A, rows, k, i, p), z = col(A, rows, k, i, q);
+                    col(A, rows, k, i, p) = cs * x - sn * z;
+                    col(A, rows, k, i, q) = sn * x + cs * z;
+                }
+                for (int i = 0; i < k; ++i) {
+                    const double x = col(W, k, k, i, p), z = col(W, k, k, i, q);
+                    col(W, k, k, i, p) = cs * x - sn * z;
+                    col(W, k, k, i, q) = sn * x + cs * z;
+                }
+            }
+        if (!rotated) break;
+    }
+    std::vector<double> sv(k), pv(k);
+    double smax = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double s2 = 0.0;
+        for (int i = 0; i < rows; ++i) s2 += col(A, rows, k, i, j) * col(A, rows, k, i, j);
+        sv[j] = std::sqrt(s2);
+        smax = std::max(smax, sv[j]);
+    }
+    for (int j = 0; j < k; ++j) {
+        if (!(sv[j] > 1e-14 * smax)) sv[j] = 0.0;
+        pv[j] = sv[j] > 0 ? beta * col(A, rows, k, 0, j) / sv[j] : 0.0;  // beta u_j[0]
+    }
+    auto zlen = [&](double mu, double* dsum) {
+        double l2 = 0.0, d = 0.0;
+        for (int j = 0; j < k; ++j) {
+            if (sv[j] == 0.0) continue;
+            const double den = sv[j] * sv[j] + mu, z = pv[j] * sv[j] / den;
+            l2 += z * z;
+            d += z * z / den;
+        }
+        if (dsum) *dsum = d;
+        return std::sqrt(l2);
+    };
+    double mu = 0.0;
+    if (zlen(0.0, nullptr) > delta) {
+        // ||z(mu)|| decreases from above delta at 0 to 0: bracket, then Newton
+        // on 1/||z|| - 1/delta, falling back to bisection
+        double lo = 0.0, hi = 1.0;
+        double pmax = 0.0;
+        for (int j = 0; j < k; ++j) pmax = std::max(pmax, std::fabs(pv[j]) * sv[j]);
+        hi = std::max(pmax * std::sqrt((double)k) / delta, 1e-300);
+        while (zlen(hi, nullptr) > delta) hi *= 2.0;
+        mu = 0.5 * (lo + hi);
+        for (int it = 0; it < 300; ++it) {
+            double d = 0.0;
+            const double L = zlen(mu, &d);
+            if (L > delta) lo = mu;
+            else hi = mu;
+            if (std::fabs(L - delta) <= 4e-16 * delta || hi - lo <= 4e-16 * hi) break;
+            // d||z||/dmu = -d / ||z||; Newton step on 1/||z|| - 1/delta
+            double next = d > 0 ? mu + (1.0 / delta - 1.0 / L) * L * L * L / d : -1.0;
+            if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+            mu = next;
+        }
+    }
+    for (int i = 0; i < k; ++i) y[i] = 0.0;
+    for (int j = 0; j < k; ++j) {
+        if (sv[j] == 0.0) continue;
+        const double z = pv[j] * sv[j] / (sv[j] * sv[j] + mu);
+        for (int i = 0; i < k; ++i) y[i] += col(W, k, k, i, j) * z;
+    }
+    double r2 = 0.0;
+    for (int i = 0; i < rows; ++i) {
+        double acc = i == 0 ? beta : 0.0;
+        for (int j = 0; j < k; ++j) acc -= hb[(size_t)i * k + j] * y[j];
+        r2 += acc * acc;
+    }
+    *mu_out = mu;
+    *resid = std::sqrt(r2);
+    return std::isfinite(*resid) ? OPF_OK : OPF_E_NUMERIC;
+}
+
 opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, int32_t preconditioned, size_t* bytes) {
     if (!c || !bytes || m < 1) return OPF_E_INVALID;
     *bytes = (size_t)(m + 5 + (preconditioned ? m : 0)) * 3 * field_entries(c) * 16;
@@ -1162,6 +1262,14 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
     if (opf_nk_workspace_size(c, m, pre ? 1 : 0, &need) != OPF_OK || krylov_bytes < need) return OPF_E_NOMEM;
     if (o->record_capacity < 0 || (o->record_capacity > 0 && !o->record_dev)) return OPF_E_INVALID;
     *rep = opf_nk_report{};
+    const bool hook = o->hookstep != 0;
+    if (hook && pre) {
+        c->err = "the hookstep is not combined with a preconditioner";
+        return OPF_E_UNSUPPORTED;
+    }
+    const int max_hook = o->max_hook > 0 ? o->max_hook : 12;
+    const double delta_max = o->tr_delta_max > 0 ? o->tr_delta_max : INFINITY;
+    double delta = o->tr_delta0;
     const size_t vb = 3 * field_entries(c) * 16;  // bytes per vector
     unsigned char* base = static_cast<unsigned char*>(krylov_dev);
     auto vec = [&](int i) { return static_cast<void*>(base + (size_t)i * vb); };
@@ -1187,6 +1295,7 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
     } while (0)
     double fn = 0.0, xn = 0.0;
     NKCHK(opf_newton_residual(c, x, T, shift, F0, &fn));
+    rep->residual_evals = 1;
     NKCHK(nrm(x, &xn));
     rep->residual_history[0] = fn / xn;
     rep->residual = fn / xn;
@@ -1210,6 +1319,84 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
             }
             return OPF_OK;
         };
+        if (hook) {
+            // one Arnoldi cycle from v_1 = -F / ||F||; Hr keeps the raw
+            // Hessenberg matrix, Hw its Givens-rotated copy for the estimate
+            NKCHK(opf_vec_axpby(c, -1.0 / fn, F0, 0.0, vec(0)));
+            std::vector<double> Hr((size_t)(m + 1) * m, 0.0), Hw((size_t)(m + 1) * m, 0.0);
+            std::vector<double> cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+            g[0] = fn;
+            int k = 0;
+            for (int j = 0; j < m; ++j) {
+                NKCHK(jv(vec(j), 1.0));
+                for (int i = 0; i <= j; ++i) {
+                    NKCHK(dot(w, vec(i), &Hr[(size_t)i * m + j]));
+                    NKCHK(opf_vec_axpby(c, -Hr[(size_t)i * m + j], vec(i), 1.0, w));
+                }
+                double hn = 0.0;
+                NKCHK(nrm(w, &hn));
+                Hr[(size_t)(j + 1) * m + j] = hn;
+                for (int i = 0; i <= j + 1; ++i) Hw[(size_t)i * m + j] = Hr[(size_t)i * m + j];
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * Hw[(size_t)i * m + j] + sn[i] * Hw[(size_t)(i + 1) * m + j];
+                    Hw[(size_t)(i + 1) * m + j] = -sn[i] * Hw[(size_t)i * m + j] + cs[i] * Hw[(size_t)(i + 1) * m + j];
+                    Hw[(size_t)i * m + j] = t;
+                }
+                const double d = std::hypot(Hw[(size_t)j * m + j], hn);
+                cs[j] = d == 0.0 ? 1.0 : Hw[(size_t)j * m + j] / d;
+                sn[j] = d == 0.0 ? 0.0 : hn / d;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                rep->gmres_iterations += 1;
+                if (std::fabs(g[k]) <= o->gmres_tol * fn || hn == 0.0 || rep->jvps >= o->max_jvps) break;
+                NKCHK(opf_vec_axpby(c, 1.0 / hn, w, 0.0, vec(j + 1)));
+            }
+            std::vector<double> hb((size_t)(k + 1) * k), y(k);
+            for (int i = 0; i <= k; ++i)
+                for (int j = 0; j < k; ++j) hb[(size_t)i * k + j] = Hr[(size_t)i * m + j];
+            double mu = 0.0, r = 0.0;
+            if (!(delta > 0)) {
+                NKCHK(opf_hookstep_solve(hb.data(), k, fn, INFINITY, y.data(), &mu, &r));
+                double l2 = 0.0;
+                for (double v : y) l2 += v * v;
+                delta = std::sqrt(l2);
+            }
+            bool accepted = false;
+            double fnew = 0.0;
+            for (int trial = 0; trial < max_hook; ++trial) {
+                NKCHK(opf_hookstep_solve(hb.data(), k, fn, delta, y.data(), &mu, &r));
+                double dn2 = 0.0;
+                for (double v : y) dn2 += v * v;
+                const double dn = std::sqrt(dn2);
+                NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
+                for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, w));
+                NKCHK(opf_newton_residual(c, w, T, shift, tmp, &fnew));
+                rep->residual_evals += 1;
+                rep->hook_trials += 1;
+                const double den = fn * fn - r * r;
+                const double rho = den > 0 ? (fn * fn - fnew * fnew) / den : -INFINITY;
+                if (rho >= 0.1) {
+                    accepted = true;
+                    if (rho > 0.75 && dn >= 0.99 * delta) delta = std::min(2.0 * delta, delta_max);
+                    else if (rho < 0.25) delta = 0.5 * dn;
+                    break;
+                }
+                delta = 0.5 * dn;
+            }
+            rep->tr_delta = delta;
+            if (!accepted) {
+                rep->stalled = 1;
+                break;
+            }
+            NKCHK(opf_vec_axpby(c, 1.0, w, 0.0, x));
+            HIPCHK(c, hipMemcpyAsync(F0, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
+            fn = fnew;
+            NKCHK(nrm(x, &xn));
+            rep->residual = fn / xn;
+            if (it + 1 < 32) rep->residual_history[it + 1] = rep->residual;
+            continue;
+        }
         // GMRES(m) for J dx = -F0, x0 = 0, one cycle per restart
         NKCHK(opf_vec_axpby(c, 0.0, F0, 0.0, dx));
         double bn = fn;
@@ -1284,6 +1471,7 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
             NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
             NKCHK(opf_vec_axpby(c, lam, dx, 1.0, w));
             NKCHK(opf_newton_residual(c, w, T, shift, tmp, &fnew));
+            rep->residual_evals += 1;
             if (fnew < fn || lam < 1e-3) break;
             lam *= 0.5;
         }
