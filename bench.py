@@ -140,8 +140,9 @@ def run_adaptive(w, steps, warmup, courant=0.5, check_every=10, dt_max=0.01):
 def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
-    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain,
-    then with the learned preconditioner trained on Jacobian probes at
+    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain
+    (restarted GMRES and a line search), then with the Krylov trust-region
+    hookstep, then with the learned preconditioner trained on Jacobian probes at
     laminar flow, run 32 at a time as ensemble members (probing and training
     timed separately: they are made once per grid, Re and T and serve every
     later search)."""
@@ -153,10 +154,11 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
     x0 = torch.from_numpy(workload_state(w, s.nodes()))
 
-    def search(precond=None):
+    def search(precond=None, hookstep=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond)
+        _, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond,
+                            hookstep=hookstep)
         torch.cuda.synchronize()
         rep["wall_s"] = round(time.perf_counter() - t0, 3)
         rep["history"] = [float(f"{h:.3e}") for h in rep["history"]]
@@ -164,6 +166,8 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
 
     plain = search()
     progress(f"nk plain: {plain['jvps']} jvps, {plain['wall_s']} s")
+    hook = search(hookstep=True)
+    progress(f"nk hookstep: {hook['jvps']} jvps, {hook['residual_evals']} residuals, {hook['wall_s']} s")
     t0 = time.perf_counter()
     lam = torch.from_numpy(laminar_state(w["N"], w["M"], w["K"], s.nodes()))
     pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11, batch=32)
@@ -177,7 +181,7 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     del pairs
     pre = search(net)
     flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
-    out = {"plain": plain, "preconditioned": pre,
+    out = {"plain": plain, "hookstep": hook, "preconditioned": pre,
            "wall_speedup": round(plain["wall_s"] / pre["wall_s"], 3),
            "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
            "steps_per_residual": int(round(w["T"] / w["dt"])),
