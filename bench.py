@@ -142,7 +142,8 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
     near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain
     (restarted GMRES and a line search), then with the Krylov trust-region
-    hookstep, then with the learned preconditioner trained on Jacobian probes at
+    hookstep, then the Arnoldi stability of the solution found, then with the
+    learned preconditioner trained on Jacobian probes at
     laminar flow, run 32 at a time as ensemble members (probing and training
     timed separately: they are made once per grid, Re and T and serve every
     later search)."""
@@ -157,14 +158,26 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     def search(precond=None, hookstep=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond,
-                            hookstep=hookstep)
+        xs, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond,
+                             hookstep=hookstep)
         torch.cuda.synchronize()
         rep["wall_s"] = round(time.perf_counter() - t0, 3)
         rep["history"] = [float(f"{h:.3e}") for h in rep["history"]]
+        search.last = xs
         return rep
 
     plain = search()
+    # stability of the solution found: leading Floquet multipliers by Arnoldi
+    v0 = torch.from_numpy(workload_state(dict(w, seed=w["seed"] + 1), s.nodes()) -
+                          laminar_state(w["N"], w["M"], w["K"], s.nodes()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, arep = s.arnoldi(search.last, w["T"], 0.0, v0, m=40, nev=6, tol=1e-6, check_every=5)
+    arn_s = time.perf_counter() - t0
+    stability = {"products": arep["products"], "converged": arep["converged"], "wall_s": round(arn_s, 3),
+                 "multipliers": [[float(f"{z.real:.6e}"), float(f"{z.imag:.6e}")] for z in ev],
+                 "growth_rates": [float(f"{np.log(abs(z)) / w['T']:.6e}") for z in ev]}
+    progress(f"nk arnoldi: {arep['products']} products, {arn_s:.1f} s")
     progress(f"nk plain: {plain['jvps']} jvps, {plain['wall_s']} s")
     hook = search(hookstep=True)
     progress(f"nk hookstep: {hook['jvps']} jvps, {hook['residual_evals']} residuals, {hook['wall_s']} s")
@@ -181,7 +194,7 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     del pairs
     pre = search(net)
     flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
-    out = {"plain": plain, "hookstep": hook, "preconditioned": pre,
+    out = {"plain": plain, "hookstep": hook, "preconditioned": pre, "stability_arnoldi": stability,
            "wall_speedup": round(plain["wall_s"] / pre["wall_s"], 3),
            "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
            "steps_per_residual": int(round(w["T"] / w["dt"])),

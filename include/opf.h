@@ -261,6 +261,41 @@ opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, int32_t pr
 opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
 
+/* ---- Stability: Arnoldi iteration on the linearised time-T map -------------
+ * Floquet multipliers of an invariant solution x (Section 3: the leading
+ * eigenvalue of a travelling wave): eigenvalues mu of
+ * J = d shift(Phi_T(x), -s)/dx, growth rate log|mu| / T.  J v is the forward
+ * difference (P(x + eps v) - P(x)) / eps, P(x) = shift(Phi_T(x), -s),
+ * eps = fd_eps max(||x||, 1) / ||v||.  Arnoldi with modified Gram-Schmidt in
+ * the energy inner product from v0 (normalised, any nonzero field), without
+ * restart; every check_every products, at breakdown and after m products the
+ * Ritz values (eigenvalues of the leading k x k Hessenberg block,
+ * opf_hessenberg_eigvals) are ordered by decreasing modulus, then decreasing
+ * imaginary part, and the search stops when the leading nev moved by at most
+ * tol |mu_1| since the previous check.  work_dev: opf_arnoldi_workspace_size
+ * bytes.  ritz_re/ritz_im (host, nev each) receive the leading Ritz values;
+ * hess_host ((m+1) x m row-major, or NULL) the Hessenberg matrix.  The
+ * context's state is overwritten.  Synchronises. */
+typedef struct {
+    int32_t products;    /* Jacobian products (each T/dt steps + one residual) */
+    int32_t converged;   /* 1 if the tol test passed or the space is invariant */
+    int32_t checks;      /* Ritz-value checks made                              */
+} opf_arnoldi_report;
+opf_status opf_arnoldi_workspace_size(const opf_ctx* ctx, int32_t m, size_t* bytes);
+opf_status opf_arnoldi(opf_ctx* ctx, const void* x_dev, double T, double shift, const void* v0_dev, int32_t m,
+                       int32_t nev, double tol, int32_t check_every, double fd_eps, void* work_dev,
+                       size_t work_bytes, double* ritz_re_host, double* ritz_im_host, double* hess_host,
+                       opf_arnoldi_report* report);
+
+/* Eigenvalues of a k x k upper Hessenberg matrix (host only, no device):
+ * Francis double-shift QR iteration with deflation at subdiagonal entries
+ * below 2^-52 times the neighbouring diagonal, 2 x 2 blocks solved in closed
+ * form.  h_host: row-major, entries below the subdiagonal ignored.  re/im
+ * (host, k each) receive the eigenvalues in the order above (modulus, then
+ * imaginary part, decreasing).  OPF_E_NUMERIC if the iteration does not
+ * converge in 60 k double steps. */
+opf_status opf_hessenberg_eigvals(const double* h_host, int32_t k, double* re_host, double* im_host);
+
 /* Jacobian probes of the travelling-wave residual at x_dev (training data
  * for the learned preconditioner, in the layout opf_nk_solve records):
  * pair i = (z_i, J z_i) at vectors 2i, 2i+1 of pairs_dev.  z_i: independent

@@ -28,7 +28,8 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
-           "opf_step_adaptive", "opf_hookstep_solve", "opf_status_string", "opf_last_error"]
+           "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
+           "opf_hessenberg_eigvals", "opf_status_string", "opf_last_error"]
 
 
 class opf_params(ctypes.Structure):
@@ -56,6 +57,10 @@ class opf_dt_report(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("checks", ctypes.c_int32), ("changes", ctypes.c_int32),
                 ("t", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("pc_diff", ctypes.c_double), ("rebuild_ms", ctypes.c_double)]
+
+
+class opf_arnoldi_report(ctypes.Structure):
+    _fields_ = [("products", ctypes.c_int32), ("converged", ctypes.c_int32), ("checks", ctypes.c_int32)]
 
 
 class opf_nk_opts(ctypes.Structure):
@@ -151,6 +156,10 @@ def load_library(path=LIB_PATH):
         "opf_step_adaptive": ([vp, i32, P(opf_dt_control), P(ctypes.c_double), P(opf_dt_report)], i32),
         "opf_hookstep_solve": ([P(ctypes.c_double), i32, dbl, dbl, P(ctypes.c_double), P(ctypes.c_double),
                                 P(ctypes.c_double)], i32),
+        "opf_arnoldi_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
+        "opf_arnoldi": ([vp, vp, dbl, dbl, vp, i32, i32, dbl, i32, dbl, vp, ctypes.c_size_t, P(ctypes.c_double),
+                         P(ctypes.c_double), P(ctypes.c_double), P(opf_arnoldi_report)], i32),
+        "opf_hessenberg_eigvals": ([P(ctypes.c_double), i32, P(ctypes.c_double), P(ctypes.c_double)], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -406,6 +415,29 @@ class Solver:
                    "recorded": rep.recorded, "precond_applies": rep.precond_applies,
                    "residual_evals": rep.residual_evals, "hook_trials": rep.hook_trials,
                    "stalled": bool(rep.stalled), "tr_delta": rep.tr_delta}
+
+    def arnoldi(self, x, T, shift, v0, m=40, nev=6, tol=1e-8, check_every=5, fd_eps=1e-7):
+        """Leading Floquet multipliers of the time-T map at x (shifted by
+        -shift): (complex numpy array of nev Ritz values, report dict with
+        the Hessenberg matrix)."""
+        import numpy as np
+        x = self._dev(x, self.shape)
+        v0 = self._dev(v0, self.shape)
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.opf_arnoldi_workspace_size(self.ctx, int(m), ctypes.byref(nbytes)))
+        work = self.torch.empty(nbytes.value, dtype=self.torch.uint8, device=self.device)
+        re, im = np.zeros(int(nev)), np.zeros(int(nev))
+        hess = np.zeros((int(m) + 1, int(m)))
+        rep = opf_arnoldi_report()
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.opf_arnoldi(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
+                                         ctypes.c_void_p(v0.data_ptr()), int(m), int(nev), float(tol),
+                                         int(check_every), float(fd_eps), ctypes.c_void_p(work.data_ptr()),
+                                         ctypes.c_size_t(nbytes.value), re.ctypes.data_as(dp), im.ctypes.data_as(dp),
+                                         hess.ctypes.data_as(dp), ctypes.byref(rep)))
+        k = rep.products
+        return re + 1j * im, {"products": k, "converged": bool(rep.converged), "checks": rep.checks,
+                              "hessenberg": hess[:k + 1, :k]}
 
     def probe_pairs(self, x, T, shift, n, seed=1, fd_eps=1e-7, batch=1):
         """n Jacobian probes (z, J z) of the travelling-wave residual at x:

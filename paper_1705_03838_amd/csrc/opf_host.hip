@@ -1247,6 +1247,203 @@ opf_status opf_hookstep_solve(const double* hb, int32_t k, double beta, double d
     return std::isfinite(*resid) ? OPF_OK : OPF_E_NUMERIC;
 }
 
+opf_status opf_hessenberg_eigvals(const double* h, int32_t k, double* re, double* im) {
+    if (!h || !re || !im || k < 1) return OPF_E_INVALID;
+    std::vector<double> A((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+        for (int j = std::max(0, i - 1); j < k; ++j) A[(size_t)i * k + j] = h[(size_t)i * k + j];
+    auto a = [&](int i, int j) -> double& { return A[(size_t)i * k + j]; };
+    std::vector<std::pair<double, double>> ev;
+    const double eps = std::ldexp(1.0, -52);
+    int n = k - 1, iter = 0, total = 0;
+    while (n >= 0) {
+        // deflate at the lowest negligible subdiagonal entry of the active block
+        int l = n;
+        for (; l > 0; --l) {
+            const double s0 = std::fabs(a(l - 1, l - 1)) + std::fabs(a(l, l));
+            if (std::fabs(a(l, l - 1)) <= eps * (s0 > 0 ? s0 : 1.0)) {
+                a(l, l - 1) = 0.0;
+                break;
+            }
+        }
+        if (l == n) {  // 1 x 1 block
+            ev.push_back({a(n, n), 0.0});
+            n -= 1;
+            iter = 0;
+            continue;
+        }
+        if (l == n - 1) {  // 2 x 2 block in closed form
+            const double p = a(n - 1, n - 1), q = a(n - 1, n), r = a(n, n - 1), d = a(n, n);
+            const double half = 0.5 * (p - d), disc = half * half + q * r;
+            if (disc >= 0) {
+                const double z = half + (half >= 0 ? 1.0 : -1.0) * std::sqrt(disc);
+                const double l1 = d + z, l2 = z != 0.0 ? d - q * r / z : d;
+                ev.push_back({l1, 0.0});
+                ev.push_back({l2, 0.0});
+            } else {
+                const double w = std::sqrt(-disc);
+                ev.push_back({d + half, w});
+                ev.push_back({d + half, -w});
+            }
+            n -= 2;
+            iter = 0;
+            continue;
+        }
+        if (++total > 60 * k) return OPF_E_NUMERIC;
+        ++iter;
+        // double shift: the eigenvalues of the trailing 2 x 2 block, or an
+        // exceptional shift every 10 stalled steps
+        double sh = a(n - 1, n - 1) + a(n, n);
+        double tq = a(n - 1, n - 1) * a(n, n) - a(n - 1, n) * a(n, n - 1);
+        if (iter % 10 == 0) {
+            const double x0 = std::fabs(a(n, n - 1)) + std::fabs(a(n - 1, n - 2));
+            sh = 1.5 * x0;
+            tq = x0 * x0;
+        }
+        double x = a(l, l) * a(l, l) + a(l, l + 1) * a(l + 1, l) - sh * a(l, l) + tq;
+        double y = a(l + 1, l) * (a(l, l) + a(l + 1, l + 1) - sh);
+        double z = a(l + 1, l) * a(l + 2, l + 1);
+        for (int q = l; q <= n - 1; ++q) {
+            const int nr = q < n - 1 ? 3 : 2;  // reflector size
+            double v[3] = {x, y, nr == 3 ? z : 0.0};
+            const double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (nv > 0.0) {
+                v[0] += v[0] >= 0 ? nv : -nv;
+                const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                // left: rows q..q+nr-1, columns of the active block
+                for (int j = std::max(l, q - 1); j <= n; ++j) {
+                    double dot = 0.0;
+                    for (int t = 0; t < nr; ++t) dot += v[t] * a(q + t, j);
+                    const double f = 2.0 * dot / vv;
+                    for (int t = 0; t < nr; ++t) a(q + t, j) -= f * v[t];
+                }
+                // right: columns q..q+nr-1, rows of the active block
+                for (int i = l; i <= std::min(n, q + 3); ++i) {
+                    double dot = 0.0;
+                    for (int t = 0; t < nr; ++t) dot += a(i, q + t) * v[t];
+                    const double f = 2.0 * dot / vv;
+                    for (int t = 0; t < nr; ++t) a(i, q + t) -= f * v[t];
+                }
+            }
+            if (q < n - 1) {
+                x = a(q + 1, q);
+                y = a(q + 2, q);
+                if (q < n - 2) z = a(q + 3, q);
+            }
+        }
+        // restore exact zeros below the subdiagonal of the active block
+        for (int i = l + 2; i <= n; ++i)
+            for (int j = l; j < i - 1; ++j) a(i, j) = 0.0;
+    }
+    std::stable_sort(ev.begin(), ev.end(), [](const std::pair<double, double>& p, const std::pair<double, double>& q) {
+        const double mp = std::hypot(p.first, p.second), mq = std::hypot(q.first, q.second);
+        if (mp != mq) return mp > mq;
+        return p.second > q.second;
+    });
+    for (int i = 0; i < k; ++i) {
+        re[i] = ev[i].first;
+        im[i] = ev[i].second;
+    }
+    return OPF_OK;
+}
+
+opf_status opf_arnoldi_workspace_size(const opf_ctx* c, int32_t m, size_t* bytes) {
+    if (!c || !bytes || m < 1) return OPF_E_INVALID;
+    *bytes = (size_t)(m + 4) * 3 * field_entries(c) * 16;
+    return OPF_OK;
+}
+
+opf_status opf_arnoldi(opf_ctx* c, const void* x_dev, double T, double shift, const void* v0, int32_t m,
+                       int32_t nev, double tol, int32_t check_every, double fd_eps, void* work, size_t work_bytes,
+                       double* ritz_re, double* ritz_im, double* hess, opf_arnoldi_report* rep) {
+    if (!c || !x_dev || !v0 || !work || !ritz_re || !ritz_im || !rep || m < 1 || nev < 1 || nev > m ||
+        check_every < 1 || !(tol >= 0) || !(fd_eps > 0))
+        return OPF_E_INVALID;
+    size_t need = 0;
+    if (opf_arnoldi_workspace_size(c, m, &need) != OPF_OK || work_bytes < need) return OPF_E_NOMEM;
+    *rep = opf_arnoldi_report{};
+    const size_t vb = 3 * field_entries(c) * 16;
+    unsigned char* base = static_cast<unsigned char*>(work);
+    auto vec = [&](int i) { return static_cast<void*>(base + (size_t)i * vb); };
+    void* P0 = vec(m + 1);   // P(x) = shift(Phi_T(x), -s)
+    void* xe = vec(m + 2);   // x + eps v
+    void* Fe = vec(m + 3);   // F(x + eps v)
+    const void* x = x_dev;
+    auto nrm = [&](const void* v, double* out) {
+        double s2 = 0.0;
+        const opf_status st = opf_vec_dot(c, v, v, &s2);
+        *out = std::sqrt(std::max(s2, 0.0));
+        return st;
+    };
+#define ARCHK(call)                    \
+    do {                               \
+        const opf_status st_ = (call); \
+        if (st_ != OPF_OK) return st_; \
+    } while (0)
+    double xn = 0.0, vn = 0.0;
+    ARCHK(opf_newton_residual(c, x, T, shift, P0, nullptr));
+    ARCHK(opf_vec_axpby(c, 1.0, x, 1.0, P0));
+    ARCHK(nrm(x, &xn));
+    xn = std::max(xn, 1.0);
+    ARCHK(nrm(v0, &vn));
+    if (!(vn > 0)) return OPF_E_INVALID;
+    ARCHK(opf_vec_axpby(c, 1.0 / vn, v0, 0.0, vec(0)));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), prev, cur(2 * (size_t)m);
+    bool have_prev = false;
+    for (int j = 0; j < m; ++j) {
+        // J v_j into v_{j+1}: (F(x + eps v) + (x + eps v) - P(x)) / eps, ||v_j|| = 1
+        const double eps = fd_eps * xn;
+        ARCHK(opf_vec_axpby(c, 1.0, x, 0.0, xe));
+        ARCHK(opf_vec_axpby(c, eps, vec(j), 1.0, xe));
+        ARCHK(opf_newton_residual(c, xe, T, shift, Fe, nullptr));
+        ARCHK(opf_vec_axpby(c, 1.0, Fe, 0.0, vec(j + 1)));
+        ARCHK(opf_vec_axpby(c, 1.0 / eps, xe, 1.0 / eps, vec(j + 1)));
+        ARCHK(opf_vec_axpby(c, -1.0 / eps, P0, 1.0, vec(j + 1)));
+        rep->products += 1;
+        for (int i = 0; i <= j; ++i) {
+            ARCHK(opf_vec_dot(c, vec(j + 1), vec(i), &H[(size_t)i * m + j]));
+            ARCHK(opf_vec_axpby(c, -H[(size_t)i * m + j], vec(i), 1.0, vec(j + 1)));
+        }
+        double hn = 0.0;
+        ARCHK(nrm(vec(j + 1), &hn));
+        H[(size_t)(j + 1) * m + j] = hn;
+        const int k = j + 1;
+        if (k % check_every == 0 || k == m || hn == 0.0) {
+            std::vector<double> hk((size_t)k * k), er(k), ei(k);
+            for (int i = 0; i < k; ++i)
+                for (int q = 0; q < k; ++q) hk[(size_t)i * k + q] = H[(size_t)i * m + q];
+            ARCHK(opf_hessenberg_eigvals(hk.data(), k, er.data(), ei.data()));
+            const int ne = std::min(nev, k);
+            for (int i = 0; i < nev; ++i) {
+                ritz_re[i] = i < ne ? er[i] : 0.0;
+                ritz_im[i] = i < ne ? ei[i] : 0.0;
+            }
+            rep->checks += 1;
+            bool done = hn == 0.0;
+            if (have_prev && (int)prev.size() == 2 * ne) {
+                double dmax = 0.0;
+                for (int i = 0; i < ne; ++i) dmax = std::max(dmax, std::hypot(er[i] - prev[2 * i], ei[i] - prev[2 * i + 1]));
+                if (dmax <= tol * std::hypot(er[0], ei[0])) done = true;
+            }
+            prev.assign(2 * ne, 0.0);
+            for (int i = 0; i < ne; ++i) {
+                prev[2 * i] = er[i];
+                prev[2 * i + 1] = ei[i];
+            }
+            have_prev = true;
+            if (done) {
+                rep->converged = 1;
+                break;
+            }
+        }
+        if (hn == 0.0) break;
+        ARCHK(opf_vec_axpby(c, 1.0 / hn, vec(j + 1), 0.0, vec(j + 1)));
+    }
+#undef ARCHK
+    if (hess) std::copy(H.begin(), H.end(), hess);
+    return OPF_OK;
+}
+
 opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, int32_t preconditioned, size_t* bytes) {
     if (!c || !bytes || m < 1) return OPF_E_INVALID;
     *bytes = (size_t)(m + 5 + (preconditioned ? m : 0)) * 3 * field_entries(c) * 16;
