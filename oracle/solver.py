@@ -37,6 +37,7 @@ import numpy as np
 
 from .grid import radial_nodes, fd_matrices, quadrature_weights
 from .spectral import to_pm, from_pm, vorticity, nonlinear, to_physical
+from .forcing import coriolis
 
 
 @dataclass
@@ -53,6 +54,7 @@ class Params:
     fixed_flux: bool = True
     nonlinear: bool = True
     stencil: int = 9
+    rotation: tuple = (0.0, 0.0, 0.0)   # Omega of the Coriolis force -2 Omega x u (forcing.py)
     r: Optional[np.ndarray] = field(default=None, repr=False)
 
 
@@ -232,9 +234,13 @@ class Oracle:
         return vorticity(u, self.g)
 
     def nonlinear(self, u):
+        """u x omega, plus the Coriolis force when a rotation is set."""
         if not self.p.nonlinear:
             return np.zeros_like(u)
-        return nonlinear(u, self.g)
+        n = nonlinear(u, self.g)
+        if any(o != 0.0 for o in self.p.rotation):
+            n = n + coriolis(u, self.p.mp, self.p.rotation)
+        return n
 
     def step(self, u):
         """One predictor-corrector step u^n -> u^{n+1} (r,theta,z spectral)."""
