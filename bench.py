@@ -137,6 +137,31 @@ def run_adaptive(w, steps, warmup, courant=0.5, check_every=10, dt_max=0.01):
             "cfl_last_check": rep["cfl"]}
 
 
+def run_rotation(w, steps, warmup):
+    """The pipe64 FP64 step with the Coriolis force of the paper's example
+    (rotation axis perpendicular to the pipe, Ekman number 1): the theta
+    kernel variant that adds -2 Omega x u at every dealiased point."""
+    import torch
+
+    import paper_1705_03838_amd as opf
+    from inputs import workload_state
+
+    om = 1.0 / (8.0 * 1.0 * w["Re"])  # E = nu / (2 Omega D^2) = 1
+    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
+    s.set_rotation(om, 0.0, 0.0)
+    s.set_state(torch.from_numpy(workload_state(w, s.nodes())))
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps
+    prof = s.profile_steps(20)
+    s.close()
+    return {"ekman": 1.0, "omega": om, "steps_per_s": round(1.0 / ms, 2), "ms_per_step": round(ms * 1e3, 4),
+            "theta_us": round(prof["theta"][0] / max(prof["theta"][1], 1) * 1e3, 2)}
+
+
 def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
@@ -406,6 +431,8 @@ def main():
                         "kernel_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
                         "roofline": roofline(prof32, True, "mixed")}
     if not args.no_adaptive:
+        out["coriolis"] = run_rotation(w, args.steps, args.warmup)
+        progress(f"coriolis: {out['coriolis']['steps_per_s']} steps/s")
         ad = run_adaptive(w, args.steps, args.warmup)
         ad["fixed_dt_steps_per_s"] = out["value"]
         ad["fixed_dt_sim_time_per_s"] = round(w["dt"] / ms64, 4)

@@ -403,6 +403,20 @@ const char* opf_mlp_last_error(const opf_mlp* net);
  * OPF_E_NUMERIC, with *out filled, when a value is not finite or cfl > 1. */
 opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
 
+/* ---- Forcing: Coriolis force ---------------------------------------------
+ * Section 3.1: the Earth's rotation is modelled by adding the Coriolis force
+ * to the nonlinear terms just after they are evaluated.  With the rotation
+ * vector Omega = (ox, oy, oz) in Cartesian components (z the pipe axis,
+ * theta measured from x), units U_cl / R, every later nonlinear term (steps,
+ * opf_nonlinear, Newton residuals) is u x omega - 2 Omega x u, formed at the
+ * points of the dealiased grid and truncated with it.  An Ekman number
+ * E = nu / (2 Omega D^2) gives |Omega| = 1 / (8 E Re).  (0, 0, 0) switches
+ * the force off (the default).  OPF_E_UNSUPPORTED for a transverse axis
+ * (ox or oy nonzero) with mp != 1 (the force couples m to m +- 1), for
+ * nonlinear = 0 and for an ensemble member.  The step graph is captured
+ * again at the next opf_step. */
+opf_status opf_set_rotation(opf_ctx* ctx, double ox, double oy, double oz);
+
 /* ---- Automatic time-step control ------------------------------------------
  * Section 2: the predictor-corrector scheme runs with automatic time-step
  * control.  The paper gives no rule; the one implemented here:

@@ -29,7 +29,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
            "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
-           "opf_hessenberg_eigvals", "opf_status_string", "opf_last_error"]
+           "opf_hessenberg_eigvals", "opf_set_rotation", "opf_status_string", "opf_last_error"]
 
 
 class opf_params(ctypes.Structure):
@@ -160,6 +160,7 @@ def load_library(path=LIB_PATH):
         "opf_arnoldi": ([vp, vp, dbl, dbl, vp, i32, i32, dbl, i32, dbl, vp, ctypes.c_size_t, P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double), P(opf_arnoldi_report)], i32),
         "opf_hessenberg_eigvals": ([P(ctypes.c_double), i32, P(ctypes.c_double), P(ctypes.c_double)], i32),
+        "opf_set_rotation": ([vp, dbl, dbl, dbl], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -301,6 +302,11 @@ class Solver:
 
     def step(self, n=1):
         self._check(self.lib.opf_step(self.ctx, int(n)))
+
+    def set_rotation(self, ox, oy, oz):
+        """Coriolis force -2 Omega x u on the nonlinear term (Omega Cartesian,
+        z the pipe axis, units U_cl / R; all zero switches it off)."""
+        self._check(self.lib.opf_set_rotation(self.ctx, float(ox), float(oy), float(oz)))
 
     def set_dt(self, dt):
         """Rebuild the dt-dependent operator tables for a new step size."""

@@ -38,6 +38,7 @@ struct opf_ctx {
     bool have_state = false;
     bool pc_valid = false;  // up / up32 hold the iterate before the last corrector of the last step
     bool in_ensemble = false;  // member of an ensemble: its step runs in the class graph, dt is fixed
+    double rot[3] = {0.0, 0.0, 0.0};  // Coriolis rotation vector (opf_set_rotation)
     std::string err;
 };
 
@@ -412,6 +413,8 @@ NLArgs nl_args(const opf_ctx* c, const void* u, const void* w, void* out) {
     a.twz = c->twz;
     a.twt = c->twt;
     a.scale = 1.0 / (9.0 * c->p.K * c->p.M);
+    for (int i = 0; i < 3; ++i) a.rot[i] = c->rot[i];
+    a.rotating = c->rot[0] != 0.0 || c->rot[1] != 0.0 || c->rot[2] != 0.0;
     return a;
 }
 
@@ -1020,6 +1023,24 @@ opf_status opf_set_dt(opf_ctx* c, double dt) {
         return st;
     }
     if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return OPF_OK;
+}
+
+opf_status opf_set_rotation(opf_ctx* c, double ox, double oy, double oz) {
+    if (!c || !std::isfinite(ox) || !std::isfinite(oy) || !std::isfinite(oz)) return OPF_E_INVALID;
+    if (c->in_ensemble || !c->p.nonlinear || ((ox != 0.0 || oy != 0.0) && c->p.mp != 1)) {
+        c->err = c->in_ensemble ? "ensemble members step without forcing"
+                 : !c->p.nonlinear ? "the force is added to the nonlinear term, which is switched off"
+                                   : "a transverse rotation axis couples m to m +- 1 and needs mp = 1";
+        return OPF_E_UNSUPPORTED;
+    }
+    c->rot[0] = ox;
+    c->rot[1] = oy;
+    c->rot[2] = oz;
+    if (c->graph) {  // the step graph holds the previous value
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
     }

@@ -52,6 +52,8 @@ struct NLArgs {
     const void* twz;    // e^{-2 pi i t / 3K}, t < 3K (compute type)
     const void* twt;    // e^{-2 pi i t / 3M}, t < 3M (compute type)
     double scale;       // 1 / (9 K M)
+    double rot[3];      // rotation vector Omega (Cartesian, z the pipe axis) of the Coriolis force
+    int rotating;       // nonzero: add -2 Omega x u to u x omega (mp = 1 unless Omega is axial)
 };
 
 // Arguments of one substep solve (one kernel).

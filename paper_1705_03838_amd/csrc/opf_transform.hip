@@ -269,11 +269,25 @@ __global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
     k_zinv_body<TS, T, L>(a);
 }
 
+// Coriolis force -2 Omega x u added to (nr, nt, nz) at theta point t of the
+// dealiased line: angle 2 pi t / 3M (a transverse axis needs mp = 1), with
+// tw[t] = exp(-2 pi i t / 3M) giving its cosine and sine.
+template <typename T>
+__device__ __forceinline__ void add_coriolis(const NLArgs& a, const cpx<T>* tw, int t, T ur, T ut, T uz, T& nr,
+                                             T& nt, T& nz) {
+    const T c = tw[t].x, s = -tw[t].y;
+    const T ox = T(a.rot[0]), oy = T(a.rot[1]), oz = T(a.rot[2]);
+    const T o_r = ox * c + oy * s, o_t = oy * c - ox * s;
+    nr -= T(2) * (o_t * uz - oz * ut);
+    nt -= T(2) * (oz * ur - o_r * uz);
+    nz -= T(2) * (o_r * ut - o_t * ur);
+}
+
 // ---------------------------------------------------------------------------
 // k_theta: per (n, TILE axial points): inverse theta transforms of the six
 // fields packed two per complex line, u x omega, forward transforms of
 // (N_r + i N_t) and (N_z + i 0), unpack, scale by 1/(9KM), write G.
-template <typename T, int L>
+template <typename T, int L, bool ROT>
 __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
@@ -347,8 +361,10 @@ __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const T ur = u[0][r].x, ut = u[0][r].y, uz = u[1][r].x, wr = u[1][r].y, wt = u[2][r].x, wz = u[2][r].y;
-            u[0][r] = {ut * wz - uz * wt, uz * wr - ur * wz};
-            u[1][r] = {ur * wt - ut * wr, T(0)};
+            T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
+            if constexpr (ROT) add_coriolis<T>(a, tw, jb + r * RA, ur, ut, uz, nr, nt, nz);  // theta point jb + r RA
+            u[0][r] = {nr, nt};
+            u[1][r] = {nz, T(0)};
         }
         dftn<T, RB>(u[0], -1, tw, L);
         dftn<T, RB>(u[1], -1, tw, L);
@@ -401,12 +417,12 @@ __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
     }
 }
 
-template <typename T, int L>
-__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) { k_theta_body<T, L>(a); }
+template <typename T, int L, bool ROT>
+__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) { k_theta_body<T, L, ROT>(a); }
 template <typename T, int L>
 __global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) {
     const NLArgs a = aa[blockIdx.y];
-    k_theta_body<T, L>(a);
+    k_theta_body<T, L, false>(a);  // ensemble members carry no forcing
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +444,7 @@ __device__ __forceinline__ int xcd_pair_tile(int b, int total) {
     return g * 16 + 2 * (w % 8) + w / 8;
 }
 
-template <typename T, int L>
+template <typename T, int L, bool ROT>
 __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
@@ -505,7 +521,9 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             const int pt = jb + r * RA;
             const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZ + zb) * LS + pt], l2 = buf[(2 * TZ + zb) * LS + pt];
             const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
-            u[r] = p == 0 ? cpx<T>{ut * wz - uz * wt, uz * wr - ur * wz} : cpx<T>{ur * wt - ut * wr, T(0)};
+            T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
+            if constexpr (ROT) add_coriolis<T>(a, tw, pt, ur, ut, uz, nr, nt, nz);
+            u[r] = p == 0 ? cpx<T>{nr, nt} : cpx<T>{nz, T(0)};
         }
         dftn<T, RB>(u, -1, tw, L);
     }
@@ -553,12 +571,12 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     }
 }
 
-template <typename T, int L>
-__global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L>(a); }
+template <typename T, int L, bool ROT>
+__global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L, ROT>(a); }
 template <typename T, int L>
 __global__ __launch_bounds__(NT3) void k_theta_lp_b(const NLArgs* __restrict__ aa) {
     const NLArgs a = aa[blockIdx.y];
-    k_theta_lp_body<T, L>(a);
+    k_theta_lp_body<T, L, false>(a);  // ensemble members carry no forcing
 }
 
 // ---------------------------------------------------------------------------
@@ -769,7 +787,8 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
 #define OPF_CASE(V)                                                                    \
     case V:                                                                            \
         if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), l3, s, batch);    \
-        else hipLaunchKernelGGL((k_theta_lp<T, V>), g, dim3(NT3), l3, s, a);            \
+        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, V, true>), g, dim3(NT3), l3, s, a); \
+        else hipLaunchKernelGGL((k_theta_lp<T, V, false>), g, dim3(NT3), l3, s, a);     \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -781,7 +800,8 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
 #define OPF_CASE(V)                                                              \
     case V:                                                                      \
         if (b) hipLaunchKernelGGL((k_theta_b<T, V>), g, dim3(NT2), lt, s, batch); \
-        else hipLaunchKernelGGL((k_theta<T, V>), g, dim3(NT2), lt, s, a);         \
+        else if (a.rotating) hipLaunchKernelGGL((k_theta<T, V, true>), g, dim3(NT2), lt, s, a); \
+        else hipLaunchKernelGGL((k_theta<T, V, false>), g, dim3(NT2), lt, s, a);  \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE

@@ -1,0 +1,113 @@
+"""GPU parity of the Coriolis forcing (opf_set_rotation): the nonlinear term
+u x omega - 2 Omega x u and whole steps against the oracle, including the
+full-size pipe64 grid and the paper's example setup (axis perpendicular to
+the pipe, Ekman number 1, Re 5300).
+
+Tolerances as for the unforced path: 1e-13 relative for the nonlinear term
+in FP64 (transforms only), 1e-11 per step, 1e-5 in mixed precision."""
+import numpy as np
+import pytest
+
+from inputs import WORKLOADS, laminar_state, make_state, workload_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "tiny": (dict(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01), (0.03, -0.05, 0.02)),
+    "ragged_axial": (dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007), (0.0, 0.0, 0.04)),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def setup(kw, rot, **extra):
+    import paper_1705_03838_amd as opf
+    from oracle import Oracle, Params
+    s = opf.Solver(**kw, **extra)
+    s.set_rotation(*rot)
+    o = Oracle(Params(r=s.nodes(), rotation=tuple(rot), **kw))
+    return s, o
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nonlinear_term_with_rotation(torch_cuda, case):
+    import paper_1705_03838_amd as opf
+    kw, rot = CASES[case]
+    say("coriolis nonlinear", case, kw, rot)
+    s, o = setup(kw, rot)
+    u = make_state(kw["N"], kw["M"], kw["K"], kw["mp"], kw["alpha"], s.nodes(), 5e-2, 4.0, 4.0, 41)
+    ref = o.nonlinear(u)
+    assert rel(s.nonlinear(torch_cuda.from_numpy(u)).cpu().numpy(), ref) < 1e-13
+    m, _ = setup(kw, rot, precision=opf.OPF_MIXED)
+    assert rel(m.nonlinear(torch_cuda.from_numpy(u)).cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_steps_with_rotation(torch_cuda, case):
+    kw, rot = CASES[case]
+    say("coriolis steps", case)
+    s, o = setup(kw, rot)
+    u = make_state(kw["N"], kw["M"], kw["K"], kw["mp"], kw["alpha"], s.nodes(), 1e-2, 4.0, 4.0, 42)
+    s.set_state(torch_cuda.from_numpy(u))
+    s.step(5)
+    ref = o.run(u, 5)
+    assert rel(s.get_state().cpu().numpy(), ref) < 5e-11
+
+
+def test_ekman_number_one_from_laminar_flow(torch_cuda):
+    """The paper's setup: axis perpendicular to the pipe (x), E = 1, Re 5300.
+    Laminar flow is no longer steady: an m = 1 secondary flow grows, as the
+    oracle's does."""
+    from oracle.forcing import ekman_rotation
+    kw = dict(N=24, M=4, K=2, mp=1, alpha=1.25, Re=5300.0, dt=0.01)
+    rot = (ekman_rotation(1.0, 5300.0), 0.0, 0.0)
+    say("ekman 1", kw, rot)
+    s, o = setup(kw, rot)
+    lam = laminar_state(24, 4, 2, s.nodes())
+    s.set_state(torch_cuda.from_numpy(lam))
+    s.step(20)
+    got = s.get_state().cpu().numpy()
+    ref = o.run(lam, 20)
+    assert rel(got, ref) < 1e-11
+    dev = got - lam
+    assert np.max(np.abs(dev[:, 1])) > 1e-6       # m = 1 response
+    assert np.max(np.abs(dev[:, 2:])) <= 1e-3 * np.max(np.abs(dev[:, 1]))
+
+
+def test_pipe64_nonlinear_with_rotation(torch_cuda):
+    """Full-size grid (N=64, |m| < 48, |k| < 64), transverse axis."""
+    import paper_1705_03838_amd as opf
+    from oracle import Oracle, Params
+    w = WORKLOADS["pipe64"]
+    kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
+    rot = (0.02, 0.01, 0.005)
+    say("pipe64 coriolis nonlinear", rot)
+    s = opf.Solver(**kw)
+    s.set_rotation(*rot)
+    o = Oracle(Params(r=s.nodes(), rotation=rot, **kw))
+    u = workload_state(w, s.nodes())
+    assert rel(s.nonlinear(torch_cuda.from_numpy(u)).cpu().numpy(), o.nonlinear(u)) < 1e-13
+
+
+def test_rotation_refused_where_unsupported(torch_cuda):
+    import paper_1705_03838_amd as opf
+    s = opf.Solver(**CASES["ragged_axial"][0])
+    with pytest.raises(opf.OpfError):
+        s.set_rotation(0.1, 0.0, 0.0)   # transverse axis with mp = 2
+    s.set_rotation(0.0, 0.0, 0.1)       # axial is fine
+    t = opf.Solver(**CASES["tiny"][0], nonlinear=False)
+    with pytest.raises(opf.OpfError):
+        t.set_rotation(0.0, 0.0, 0.1)
