@@ -261,6 +261,47 @@ opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, int32_t pr
 opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
 
+/* ---- Relative periodic orbits by multiple shooting -------------------------
+ * Section 2: the Newton solver has a multiple-shooting option (an orbit split
+ * into sections) and uses the Krylov trust-region step.  Unknowns
+ * X = (x_1 .. x_S, T, s): S states (external layout, contiguous in x_dev),
+ * the period T and the axial shift s.  Each section runs n steps of
+ * dt = T / (S n) (opf_set_dt is applied as T changes; the context's dt is
+ * restored on return).  Residual G_i = Phi_{T/S}(x_i) - x_{i+1} (i < S),
+ * G_S = shift(Phi_{T/S}(x_S), -s) - x_1.  free_T / free_s add the phase
+ * conditions <xdot_1, dx_1> = 0 (xdot_1 = (Phi_dt(x_1) - x_1) / dt) and
+ * <d_z x_1, dx_1> = 0 (d_z = i alpha k) on the update.  Inner product: the
+ * energy inner product summed over sections plus the products of the T and s
+ * entries.  J V is the forward difference of the whole residual,
+ * eps = fd_eps max(||X||, 1) / ||V||, plus the phase rows.  The Newton step
+ * is the hookstep of opf_nk_solve (one Arnoldi cycle of at most gmres_m
+ * products, opf_hookstep_solve, the same trust-region rule).  Stops when
+ * ||G|| / ||X|| <= tol.  x_dev, *T_inout, *shift_inout: guess in, solution
+ * out.  The context's state is overwritten.  Synchronises. */
+typedef struct {
+    int32_t sections;      /* S >= 1                                            */
+    int32_t steps;         /* n >= 1 steps per section                          */
+    int32_t free_T, free_s;
+    int32_t gmres_m, max_newton;
+    double tol, gmres_tol, fd_eps;
+    double tr_delta0;      /* <= 0: the first unconstrained step length          */
+    double tr_delta_max;   /* <= 0: unbounded                                     */
+    int32_t max_hook;      /* <= 0: 12                                            */
+} opf_shoot_opts;
+
+typedef struct {
+    int32_t newton_iterations, products, residual_evals, hook_trials, converged, stalled;
+    double residual;               /* final ||G|| / ||X||                    */
+    double residual_history[32];
+    double T, shift, tr_delta;
+} opf_shoot_report;
+
+/* Device bytes for opf_shoot_solve: (gmres_m + 6) S + 3 fields. */
+opf_status opf_shoot_workspace_size(const opf_ctx* ctx, int32_t sections, int32_t gmres_m, size_t* bytes);
+opf_status opf_shoot_solve(opf_ctx* ctx, void* x_dev, double* T_inout, double* shift_inout,
+                           const opf_shoot_opts* opts, void* work_dev, size_t work_bytes,
+                           opf_shoot_report* report);
+
 /* ---- Stability: Arnoldi iteration on the linearised time-T map -------------
  * Floquet multipliers of an invariant solution x (Section 3: the leading
  * eigenvalue of a travelling wave): eigenvalues mu of

@@ -29,7 +29,8 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
            "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
-           "opf_hessenberg_eigvals", "opf_set_rotation", "opf_status_string", "opf_last_error"]
+           "opf_hessenberg_eigvals", "opf_set_rotation", "opf_shoot_workspace_size", "opf_shoot_solve",
+           "opf_status_string", "opf_last_error"]
 
 
 class opf_params(ctypes.Structure):
@@ -61,6 +62,21 @@ class opf_dt_report(ctypes.Structure):
 
 class opf_arnoldi_report(ctypes.Structure):
     _fields_ = [("products", ctypes.c_int32), ("converged", ctypes.c_int32), ("checks", ctypes.c_int32)]
+
+
+class opf_shoot_opts(ctypes.Structure):
+    _fields_ = [("sections", ctypes.c_int32), ("steps", ctypes.c_int32), ("free_T", ctypes.c_int32),
+                ("free_s", ctypes.c_int32), ("gmres_m", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("gmres_tol", ctypes.c_double), ("fd_eps", ctypes.c_double),
+                ("tr_delta0", ctypes.c_double), ("tr_delta_max", ctypes.c_double), ("max_hook", ctypes.c_int32)]
+
+
+class opf_shoot_report(ctypes.Structure):
+    _fields_ = [("newton_iterations", ctypes.c_int32), ("products", ctypes.c_int32),
+                ("residual_evals", ctypes.c_int32), ("hook_trials", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("stalled", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("residual_history", ctypes.c_double * 32), ("T", ctypes.c_double), ("shift", ctypes.c_double),
+                ("tr_delta", ctypes.c_double)]
 
 
 class opf_nk_opts(ctypes.Structure):
@@ -161,6 +177,9 @@ def load_library(path=LIB_PATH):
                          P(ctypes.c_double), P(ctypes.c_double), P(opf_arnoldi_report)], i32),
         "opf_hessenberg_eigvals": ([P(ctypes.c_double), i32, P(ctypes.c_double), P(ctypes.c_double)], i32),
         "opf_set_rotation": ([vp, dbl, dbl, dbl], i32),
+        "opf_shoot_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], i32),
+        "opf_shoot_solve": ([vp, vp, P(ctypes.c_double), P(ctypes.c_double), P(opf_shoot_opts), vp, ctypes.c_size_t,
+                             P(opf_shoot_report)], i32),
         "opf_status_string": ([i32], ctypes.c_char_p),
         "opf_last_error": ([vp], ctypes.c_char_p),
     }
@@ -421,6 +440,31 @@ class Solver:
                    "recorded": rep.recorded, "precond_applies": rep.precond_applies,
                    "residual_evals": rep.residual_evals, "hook_trials": rep.hook_trials,
                    "stalled": bool(rep.stalled), "tr_delta": rep.tr_delta}
+
+    def shoot_solve(self, xs, T, shift, steps, free_T=True, free_s=True, gmres_m=40, max_newton=20, tol=1e-8,
+                    gmres_tol=1e-3, fd_eps=1e-7, tr_delta0=0.0, tr_delta_max=0.0, max_hook=12):
+        """Relative periodic orbit by multiple shooting: xs [S, 3, M, 2K-1, N]
+        section states, period T, shift s, `steps` steps per section.
+        Returns (sections, T, s, report dict)."""
+        xs = self._dev(xs, tuple(xs.shape[:1]) + tuple(self.shape)).clone()
+        S = xs.shape[0]
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.opf_shoot_workspace_size(self.ctx, int(S), int(gmres_m), ctypes.byref(nbytes)))
+        work = self.torch.empty(nbytes.value, dtype=self.torch.uint8, device=self.device)
+        o = opf_shoot_opts(int(S), int(steps), int(bool(free_T)), int(bool(free_s)), int(gmres_m), int(max_newton),
+                           float(tol), float(gmres_tol), float(fd_eps), float(tr_delta0), float(tr_delta_max),
+                           int(max_hook))
+        Tc, sc = ctypes.c_double(T), ctypes.c_double(shift)
+        rep = opf_shoot_report()
+        self._check(self.lib.opf_shoot_solve(self.ctx, ctypes.c_void_p(xs.data_ptr()), ctypes.byref(Tc),
+                                             ctypes.byref(sc), ctypes.byref(o), ctypes.c_void_p(work.data_ptr()),
+                                             ctypes.c_size_t(nbytes.value), ctypes.byref(rep)))
+        n = rep.newton_iterations
+        return xs, Tc.value, sc.value, {
+            "newton_iterations": n, "products": rep.products, "residual_evals": rep.residual_evals,
+            "hook_trials": rep.hook_trials, "converged": bool(rep.converged), "stalled": bool(rep.stalled),
+            "residual": rep.residual, "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
+            "tr_delta": rep.tr_delta}
 
     def arnoldi(self, x, T, shift, v0, m=40, nev=6, tol=1e-8, check_every=5, fd_eps=1e-7):
         """Leading Floquet multipliers of the time-T map at x (shifted by

@@ -284,6 +284,17 @@ __global__ void k_shift_sub(const double* __restrict__ u, const double* __restri
     F[2 * i + 1] = ur * sn + ui * c - x[2 * i + 1];
 }
 
+// Axial derivative d_z x: out_k = i alpha k x_k (complex128 external layout).
+__global__ void k_ddz(const double* __restrict__ x, double* __restrict__ out, int N, int nk, int K, size_t total,
+                      double alpha) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const double ka = alpha * ((int)((i / N) % nk) - (K - 1));
+    const double xr = x[2 * i], xi = x[2 * i + 1];
+    out[2 * i] = -ka * xi;
+    out[2 * i + 1] = ka * xr;
+}
+
 // Per-m partial sums of w_n Re(a conj(b)) over components, k and n (the
 // energy inner product before the m weights); fixed summation order.
 __global__ __launch_bounds__(256) void k_wdot(const double* __restrict__ a, const double* __restrict__ b,
@@ -1266,6 +1277,260 @@ opf_status opf_hookstep_solve(const double* hb, int32_t k, double beta, double d
     *mu_out = mu;
     *resid = std::sqrt(r2);
     return std::isfinite(*resid) ? OPF_OK : OPF_E_NUMERIC;
+}
+
+opf_status opf_shoot_workspace_size(const opf_ctx* c, int32_t S, int32_t m, size_t* bytes) {
+    if (!c || !bytes || S < 1 || m < 1) return OPF_E_INVALID;
+    *bytes = ((size_t)(m + 6) * S + 3) * 3 * field_entries(c) * 16;
+    return OPF_OK;
+}
+
+opf_status opf_shoot_solve(opf_ctx* c, void* x_dev, double* T_io, double* s_io, const opf_shoot_opts* o,
+                           void* work, size_t work_bytes, opf_shoot_report* rep) {
+    if (!c || !x_dev || !T_io || !s_io || !o || !work || !rep) return OPF_E_INVALID;
+    const int S = o->sections, n = o->steps, m = o->gmres_m;
+    if (S < 1 || n < 1 || m < 1 || o->max_newton < 0 || !(*T_io > 0) || !std::isfinite(*s_io) ||
+        !(o->fd_eps > 0) || !(o->tol >= 0) || !(o->gmres_tol >= 0))
+        return OPF_E_INVALID;
+    size_t need = 0;
+    if (opf_shoot_workspace_size(c, S, m, &need) != OPF_OK || work_bytes < need) return OPF_E_NOMEM;
+    if (c->in_ensemble) {
+        c->err = "ensemble members keep the dt of their class graph";
+        return OPF_E_UNSUPPORTED;
+    }
+    *rep = opf_shoot_report{};
+    const double dt0 = c->p.dt;
+    const size_t total = 3 * field_entries(c), vb = total * 16, eb = (size_t)S * vb;
+    unsigned char* base = static_cast<unsigned char*>(work);
+    // extended vectors: S fields on the device, (T, s) entries on the host
+    const int nvec = m + 6;
+    auto ev = [&](int i) { return base + (size_t)i * eb; };
+    auto fld = [&](unsigned char* e, int sec) { return static_cast<void*>(e + (size_t)sec * vb); };
+    std::vector<double> sc(2 * (size_t)nvec, 0.0);  // host (T, s) entries per extended vector
+    const int iG0 = m + 1, iW = m + 2, iGt = m + 3, iXe = m + 4, iGe = m + 5;
+    unsigned char* extra = base + (size_t)nvec * eb;
+    void* phT = extra;           // xdot_1
+    void* phS = extra + vb;      // d_z x_1
+    void* tmp = extra + 2 * vb;  // scratch field
+    unsigned char* X = static_cast<unsigned char*>(x_dev);
+    double XT = *T_io, Xs = *s_io;
+    const int max_hook = o->max_hook > 0 ? o->max_hook : 12;
+    const double delta_max = o->tr_delta_max > 0 ? o->tr_delta_max : INFINITY;
+    double delta = o->tr_delta0;
+#define SHCHK(call)                    \
+    do {                               \
+        const opf_status st_ = (call); \
+        if (st_ != OPF_OK) {           \
+            (void)opf_set_dt(c, dt0);  \
+            return st_;                \
+        }                              \
+    } while (0)
+    // <A, B> over the sections plus the scalar entries (a, b: host pairs)
+    auto xdot = [&](unsigned char* A, const double* a, unsigned char* B, const double* b, double* out) -> opf_status {
+        double acc = a[0] * b[0] + a[1] * b[1];
+        for (int i = 0; i < S; ++i) {
+            double d = 0.0;
+            const opf_status st = opf_vec_dot(c, fld(A, i), fld(B, i), &d);
+            if (st != OPF_OK) return st;
+            acc += d;
+        }
+        *out = acc;
+        return OPF_OK;
+    };
+    // Y = a A + b Y
+    auto xaxpby = [&](double a, unsigned char* A, const double* as, double b, unsigned char* Y, double* ys) {
+        for (int i = 0; i < S; ++i) {
+            const opf_status st = opf_vec_axpby(c, a, fld(A, i), b, fld(Y, i));
+            if (st != OPF_OK) return st;
+        }
+        ys[0] = a * as[0] + b * ys[0];
+        ys[1] = a * as[1] + b * ys[1];
+        return OPF_OK;
+    };
+    auto set_T = [&](double T) -> opf_status { return opf_set_dt(c, T / ((double)S * n)); };
+    // G(Y) into Gout (scalar entries 0)
+    auto residual = [&](unsigned char* Y, const double* ys, unsigned char* Gout, double* gs) -> opf_status {
+        opf_status st = set_T(ys[0]);
+        if (st != OPF_OK) return st;
+        for (int i = 0; i < S; ++i) {
+            if ((st = opf_set_state(c, fld(Y, i))) != OPF_OK) return st;
+            if ((st = opf_step(c, n)) != OPF_OK) return st;
+            const void* next = fld(Y, i + 1 < S ? i + 1 : 0);
+            hipLaunchKernelGGL(k_shift_sub, dim3((total + 255) / 256), dim3(256), 0, c->stream, c->u,
+                               static_cast<const double*>(next), static_cast<double*>(fld(Gout, i)), c->p.N, c->nk,
+                               c->p.K, total, c->p.alpha, i + 1 < S ? 0.0 : ys[1]);
+            HIPCHK(c, hipGetLastError());
+        }
+        gs[0] = gs[1] = 0.0;
+        rep->residual_evals += 1;
+        return OPF_OK;
+    };
+    auto nrm = [&](unsigned char* A, const double* a, double* out) -> opf_status {
+        double d = 0.0;
+        const opf_status st = xdot(A, a, A, a, &d);
+        *out = std::sqrt(std::max(d, 0.0));
+        return st;
+    };
+    // copy the guess into W, evaluate G0
+    double* sW = &sc[2 * iW];
+    HIPCHK(c, hipMemcpyAsync(ev(iW), X, eb, hipMemcpyDeviceToDevice, c->stream));
+    sW[0] = XT;
+    sW[1] = Xs;
+    double* sG0 = &sc[2 * iG0];
+    SHCHK(residual(ev(iW), sW, ev(iG0), sG0));
+    double fn = 0.0, xn = 0.0;
+    SHCHK(nrm(ev(iG0), sG0, &fn));
+    SHCHK(nrm(ev(iW), sW, &xn));
+    rep->residual_history[0] = rep->residual = fn / xn;
+    int it = 0;
+    for (; it < o->max_newton && rep->residual > o->tol; ++it) {
+        // phase vectors at x_1 and T
+        if (o->free_T) {
+            SHCHK(set_T(sW[0]));
+            SHCHK(opf_set_state(c, fld(ev(iW), 0)));
+            SHCHK(opf_step(c, 1));
+            HIPCHK(c, hipMemcpyAsync(phT, c->u, vb, hipMemcpyDeviceToDevice, c->stream));
+            SHCHK(opf_vec_axpby(c, -1.0 / c->p.dt, fld(ev(iW), 0), 1.0 / c->p.dt, phT));
+        }
+        if (o->free_s) {
+            hipLaunchKernelGGL(k_ddz, dim3((total + 255) / 256), dim3(256), 0, c->stream,
+                               static_cast<const double*>(fld(ev(iW), 0)), static_cast<double*>(phS), c->p.N, c->nk,
+                               c->p.K, total, c->p.alpha);
+            HIPCHK(c, hipGetLastError());
+        }
+        // J V into extended vector `out` (V has unit norm)
+        auto jv = [&](int iv, int iout) -> opf_status {
+            double* sv = &sc[2 * iv];
+            if (!o->free_T) sv[0] = 0.0;
+            if (!o->free_s) sv[1] = 0.0;
+            double vn = 0.0;
+            opf_status st = nrm(ev(iv), sv, &vn);
+            if (st != OPF_OK) return st;
+            double* so = &sc[2 * iout];
+            if (!(vn > 0)) {
+                for (int i = 0; i < S; ++i)
+                    if ((st = opf_vec_axpby(c, 0.0, fld(ev(iv), i), 0.0, fld(ev(iout), i))) != OPF_OK) return st;
+                so[0] = so[1] = 0.0;
+                return OPF_OK;
+            }
+            const double eps = o->fd_eps * std::max(xn, 1.0) / vn;
+            double* sXe = &sc[2 * iXe];
+            double* sGe = &sc[2 * iGe];
+            HIPCHK(c, hipMemcpyAsync(ev(iXe), ev(iW), eb, hipMemcpyDeviceToDevice, c->stream));
+            sXe[0] = sW[0];
+            sXe[1] = sW[1];
+            if ((st = xaxpby(eps, ev(iv), sv, 1.0, ev(iXe), sXe)) != OPF_OK) return st;
+            if ((st = residual(ev(iXe), sXe, ev(iGe), sGe)) != OPF_OK) return st;
+            HIPCHK(c, hipMemcpyAsync(ev(iout), ev(iGe), eb, hipMemcpyDeviceToDevice, c->stream));
+            so[0] = so[1] = 0.0;
+            if ((st = xaxpby(-1.0 / eps, ev(iG0), sG0, 1.0 / eps, ev(iout), so)) != OPF_OK) return st;
+            so[0] = so[1] = 0.0;
+            if (o->free_T && (st = opf_vec_dot(c, phT, fld(ev(iv), 0), &so[0])) != OPF_OK) return st;
+            if (o->free_s && (st = opf_vec_dot(c, phS, fld(ev(iv), 0), &so[1])) != OPF_OK) return st;
+            rep->products += 1;
+            return OPF_OK;
+        };
+        // Arnoldi from v_1 = -G / ||G||
+        {
+            double* s0v = &sc[0];
+            s0v[0] = s0v[1] = 0.0;
+            for (int i = 0; i < S; ++i) SHCHK(opf_vec_axpby(c, -1.0 / fn, fld(ev(iG0), i), 0.0, fld(ev(0), i)));
+            s0v[0] = -sG0[0] / fn;
+            s0v[1] = -sG0[1] / fn;
+        }
+        std::vector<double> Hr((size_t)(m + 1) * m, 0.0), Hw((size_t)(m + 1) * m, 0.0);
+        std::vector<double> cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+        g[0] = fn;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            SHCHK(jv(j, j + 1));
+            for (int i = 0; i <= j; ++i) {
+                double h = 0.0;
+                SHCHK(xdot(ev(j + 1), &sc[2 * (j + 1)], ev(i), &sc[2 * i], &h));
+                Hr[(size_t)i * m + j] = h;
+                SHCHK(xaxpby(-h, ev(i), &sc[2 * i], 1.0, ev(j + 1), &sc[2 * (j + 1)]));
+            }
+            double hn = 0.0;
+            SHCHK(nrm(ev(j + 1), &sc[2 * (j + 1)], &hn));
+            Hr[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i <= j + 1; ++i) Hw[(size_t)i * m + j] = Hr[(size_t)i * m + j];
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hw[(size_t)i * m + j] + sn[i] * Hw[(size_t)(i + 1) * m + j];
+                Hw[(size_t)(i + 1) * m + j] = -sn[i] * Hw[(size_t)i * m + j] + cs[i] * Hw[(size_t)(i + 1) * m + j];
+                Hw[(size_t)i * m + j] = t;
+            }
+            const double d = std::hypot(Hw[(size_t)j * m + j], hn);
+            cs[j] = d == 0.0 ? 1.0 : Hw[(size_t)j * m + j] / d;
+            sn[j] = d == 0.0 ? 0.0 : hn / d;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (std::fabs(g[k]) <= o->gmres_tol * fn || hn == 0.0) break;
+            SHCHK(xaxpby(1.0 / hn, ev(j + 1), &sc[2 * (j + 1)], 0.0, ev(j + 1), &sc[2 * (j + 1)]));
+        }
+        std::vector<double> hb((size_t)(k + 1) * k), y(k);
+        for (int i = 0; i <= k; ++i)
+            for (int j = 0; j < k; ++j) hb[(size_t)i * k + j] = Hr[(size_t)i * m + j];
+        double mu = 0.0, r = 0.0;
+        if (!(delta > 0)) {
+            SHCHK(opf_hookstep_solve(hb.data(), k, fn, INFINITY, y.data(), &mu, &r));
+            double l2 = 0.0;
+            for (double v : y) l2 += v * v;
+            delta = std::sqrt(l2);
+        }
+        // trial X + dx in Xe, its residual in Gt
+        bool accepted = false;
+        double fnew = 0.0;
+        double* sXe = &sc[2 * iXe];
+        double* sGt = &sc[2 * iGt];
+        for (int trial = 0; trial < max_hook; ++trial) {
+            SHCHK(opf_hookstep_solve(hb.data(), k, fn, delta, y.data(), &mu, &r));
+            double dn2 = 0.0;
+            for (double v : y) dn2 += v * v;
+            const double dn = std::sqrt(dn2);
+            HIPCHK(c, hipMemcpyAsync(ev(iXe), ev(iW), eb, hipMemcpyDeviceToDevice, c->stream));
+            sXe[0] = sW[0];
+            sXe[1] = sW[1];
+            for (int i = 0; i < k; ++i) SHCHK(xaxpby(y[i], ev(i), &sc[2 * i], 1.0, ev(iXe), sXe));
+            SHCHK(residual(ev(iXe), sXe, ev(iGt), sGt));
+            SHCHK(nrm(ev(iGt), sGt, &fnew));
+            rep->hook_trials += 1;
+            const double den = fn * fn - r * r;
+            const double rho = den > 0 ? (fn * fn - fnew * fnew) / den : -INFINITY;
+            if (rho >= 0.1) {
+                accepted = true;
+                if (rho > 0.75 && dn >= 0.99 * delta) delta = std::min(2.0 * delta, delta_max);
+                else if (rho < 0.25) delta = 0.5 * dn;
+                break;
+            }
+            delta = 0.5 * dn;
+        }
+        rep->tr_delta = delta;
+        if (!accepted) {
+            rep->stalled = 1;
+            break;
+        }
+        HIPCHK(c, hipMemcpyAsync(ev(iW), ev(iXe), eb, hipMemcpyDeviceToDevice, c->stream));
+        sW[0] = sXe[0];
+        sW[1] = sXe[1];
+        HIPCHK(c, hipMemcpyAsync(ev(iG0), ev(iGt), eb, hipMemcpyDeviceToDevice, c->stream));
+        sG0[0] = sGt[0];
+        sG0[1] = sGt[1];
+        fn = fnew;
+        SHCHK(nrm(ev(iW), sW, &xn));
+        rep->residual = fn / xn;
+        if (it + 1 < 32) rep->residual_history[it + 1] = rep->residual;
+    }
+#undef SHCHK
+    HIPCHK(c, hipMemcpyAsync(X, ev(iW), eb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *T_io = sW[0];
+    *s_io = sW[1];
+    rep->T = sW[0];
+    rep->shift = sW[1];
+    rep->newton_iterations = it;
+    rep->converged = rep->residual <= o->tol ? 1 : 0;
+    return opf_set_dt(c, dt0);
 }
 
 opf_status opf_hessenberg_eigvals(const double* h, int32_t k, double* re, double* im) {
