@@ -55,6 +55,9 @@ class Params:
     nonlinear: bool = True
     stencil: int = 9
     rotation: tuple = (0.0, 0.0, 0.0)   # Omega of the Coriolis force -2 Omega x u (forcing.py)
+    # wall velocity per mode, [3][M][2K-1] complex (r, theta, z) components at
+    # r = 1, or None for no slip; (0,0) takes theta and z only, m = 0 uses k >= 0
+    wall: Optional[np.ndarray] = field(default=None, repr=False)
     r: Optional[np.ndarray] = field(default=None, repr=False)
 
 
@@ -195,7 +198,11 @@ class Oracle:
                 ub.append(_bsolve(self.helm(mu, kap), b))
             ub = np.stack(ub)
             h, P1, A = self.homogeneous(mi)
-            a = _bsolve(A[ks], -self.gvec(m, kap, ub))
+            gv = self.gvec(m, kap, ub)
+            if p.wall is not None:  # drive g to the wall values instead of 0
+                br, bt, bz = p.wall[0, mi, ks], p.wall[1, mi, ks], p.wall[2, mi, ks]
+                gv = gv - np.stack([br + 1j * bt, br - 1j * bt, bz, np.zeros_like(bz)], axis=-1)
+            a = _bsolve(A[ks], -gv)
             for j in range(4):
                 ub += a[None, :, j, None] * h[j][:, ks]
             P = P + a[:, 0, None] * P1[ks]
@@ -206,11 +213,11 @@ class Oracle:
         k0 = K - 1
         Rth = ((R[0, 0, k0] - R[1, 0, k0]) / 2j).real
         b = Rth.copy()
-        b[-1] = 0.0
+        b[-1] = p.wall[1, 0, k0].real if p.wall is not None else 0.0
         u[:, 0, k0] = 0.0
         u[1, 0, k0] = np.linalg.solve(self.helm(1, [0.0])[0], b)
         b = R[2, 0, k0].real.copy()
-        b[-1] = 0.0
+        b[-1] = p.wall[2, 0, k0].real if p.wall is not None else 0.0
         H0 = self.helm(0, [0.0])[0]
         ua = np.linalg.solve(H0, b)
         if p.fixed_flux:
@@ -295,16 +302,19 @@ class Oracle:
 
     def boundary_and_divergence(self, u):
         """Largest boundary-condition residual over the modes,
-        max_mk max(|u_+(1)|, |u_-(1)|, |u_z(1)|, |div u(1)|) (the vector g of
-        Section 2), and the largest interior divergence max_mk max_{n<N-1}
-        |div u_mk(r_n)|, with div u = (1/r) d(r u_r)/dr + (i m/r) u_theta +
-        i kappa u_z written in the (+,-,z) form."""
+        max_mk max(|u_+(1) - b_+|, |u_-(1) - b_-|, |u_z(1) - b_z|, |div u(1)|)
+        (the vector g of Section 2, b the wall velocity, zero for no slip), and
+        the largest interior divergence max_mk max_{n<N-1} |div u_mk(r_n)|,
+        with div u = (1/r) d(r u_r)/dr + (i m/r) u_theta + i kappa u_z written
+        in the (+,-,z) form."""
         v = to_pm(u)
+        b = np.zeros(v.shape[:3], dtype=complex) if self.p.wall is None else to_pm(self.p.wall[..., None])[..., 0]
         gmax = dmax = 0.0
         for mi in range(self.M):
             m = self.p.mp * mi
             dv = self.div_pm(m, self.kap, v[0, mi], v[1, mi], v[2, mi])
-            bc = np.stack([v[0, mi][:, -1], v[1, mi][:, -1], v[2, mi][:, -1], dv[:, -1]])
+            bc = np.stack([v[0, mi][:, -1] - b[0, mi], v[1, mi][:, -1] - b[1, mi], v[2, mi][:, -1] - b[2, mi],
+                           dv[:, -1]])
             gmax = max(gmax, float(np.max(np.abs(bc))))
             dmax = max(dmax, float(np.max(np.abs(dv[:, :-1]))))
         return gmax, dmax
