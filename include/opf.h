@@ -458,6 +458,22 @@ opf_status opf_diagnostics(opf_ctx* ctx, opf_diag* out);
  * again at the next opf_step. */
 opf_status opf_set_rotation(opf_ctx* ctx, double ox, double oy, double oz);
 
+/* ---- Boundary conditions through the influence-matrix vector g -------------
+ * Section 2: the boundary conditions enter through the vector g, which the
+ * influence matrix drives to its target.  A prescribed wall velocity b (the
+ * target of u(1)) replaces no slip: b_host is host complex128 [3][M][2K-1]
+ * (components r, theta, z; the external mode layout) or NULL for no slip.
+ * For every mode other than (0,0) the correction solves A a = -(g(u_b) - g_b)
+ * with g_b = (b_r + i b_theta, b_r - i b_theta, b_z, 0); mode (0,0) takes
+ * b_theta and b_z as the Dirichlet values of its Helmholtz solves (the
+ * fixed-flux correction keeps the flux).  m = 0, k < 0 values are replaced
+ * by the conjugates of k > 0 and the (0,0) imaginary parts are dropped (a
+ * real field); a nonzero (0,0) radial entry (net flux through the wall) is
+ * OPF_E_INVALID.  Applies to steps, opf_radial_solve and everything built on
+ * them; opf_diagnostics reports g_norm against b.  OPF_E_UNSUPPORTED for an
+ * ensemble member.  Synchronises; the step graph is captured again. */
+opf_status opf_set_wall_velocity(opf_ctx* ctx, const double* b_host);
+
 /* ---- Automatic time-step control ------------------------------------------
  * Section 2: the predictor-corrector scheme runs with automatic time-step
  * control.  The paper gives no rule; the one implemented here:

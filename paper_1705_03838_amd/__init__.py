@@ -29,7 +29,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
            "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
-           "opf_hessenberg_eigvals", "opf_set_rotation", "opf_shoot_workspace_size", "opf_shoot_solve",
+           "opf_hessenberg_eigvals", "opf_set_rotation", "opf_shoot_workspace_size", "opf_shoot_solve", "opf_set_wall_velocity",
            "opf_status_string", "opf_last_error"]
 
 
@@ -177,6 +177,7 @@ def load_library(path=LIB_PATH):
                          P(ctypes.c_double), P(ctypes.c_double), P(opf_arnoldi_report)], i32),
         "opf_hessenberg_eigvals": ([P(ctypes.c_double), i32, P(ctypes.c_double), P(ctypes.c_double)], i32),
         "opf_set_rotation": ([vp, dbl, dbl, dbl], i32),
+        "opf_set_wall_velocity": ([vp, P(ctypes.c_double)], i32),
         "opf_shoot_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], i32),
         "opf_shoot_solve": ([vp, vp, P(ctypes.c_double), P(ctypes.c_double), P(opf_shoot_opts), vp, ctypes.c_size_t,
                              P(opf_shoot_report)], i32),
@@ -321,6 +322,18 @@ class Solver:
 
     def step(self, n=1):
         self._check(self.lib.opf_step(self.ctx, int(n)))
+
+    def set_wall_velocity(self, b):
+        """Prescribed wall velocity b [3, M, 2K-1] complex (r, theta, z at
+        r = 1) through the influence-matrix vector g; None restores no slip."""
+        import numpy as np
+        if b is None:
+            self._check(self.lib.opf_set_wall_velocity(self.ctx, None))
+            return
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        if b.shape != tuple(self.shape[:3]):
+            raise OpfError(OPF_E_INVALID, f"expected shape {tuple(self.shape[:3])}, got {b.shape}")
+        self._check(self.lib.opf_set_wall_velocity(self.ctx, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def set_rotation(self, ox, oy, oz):
         """Coriolis force -2 Omega x u on the nonlinear term (Omega Cartesian,

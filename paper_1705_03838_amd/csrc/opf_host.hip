@@ -39,6 +39,8 @@ struct opf_ctx {
     bool pc_valid = false;  // up / up32 hold the iterate before the last corrector of the last step
     bool in_ensemble = false;  // member of an ensemble: its step runs in the class graph, dt is fixed
     double rot[3] = {0.0, 0.0, 0.0};  // Coriolis rotation vector (opf_set_rotation)
+    double* wall = nullptr;           // wall velocity [3][M][nk] complex in the workspace
+    bool has_wall = false;            // opf_set_wall_velocity set a moving wall
     std::string err;
 };
 
@@ -206,7 +208,7 @@ void build_grid(opf_ctx* c, const double* r_nodes) {
 }
 
 struct Layout {
-    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, flags, qg, twz, twt;
+    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, flags, qg, wall, twz, twt;
     size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, dpart, cflw, cpart, total;
 };
 
@@ -231,6 +233,7 @@ Layout layout(const opf_params& p) {
     L.green = take(N * 8);
     L.flags = take((nfac + M * nk) * 4);
     L.qg = take(8);
+    L.wall = take(3 * M * nk * 16);
     L.twz = take(3 * K * 16);
     L.twt = take(3 * M * 16);
     L.u = take(3 * S * 16);
@@ -447,6 +450,7 @@ SolveArgs solve_args(const opf_ctx* c, int kind) {
     a.aexp = (1.0 - c->p.c) / c->p.Re;
     a.force = 4.0 / c->p.Re;
     a.beta_out = c->beta;
+    a.wall = c->has_wall ? c->wall : nullptr;
     a.t = c->t;
     return a;
 }
@@ -760,6 +764,7 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->dpart = reinterpret_cast<double*>(ws + Lo.dpart);
     c->cflw = reinterpret_cast<double*>(ws + Lo.cflw);
     c->cpart = reinterpret_cast<double*>(ws + Lo.cpart);
+    c->wall = reinterpret_cast<double*>(ws + Lo.wall);
     // banded LU factors, influence data and Green's function on the device
     const opf_status st2 = device_tables(c, true);
     if (st2 != OPF_OK) {
@@ -963,6 +968,7 @@ opf_status opf_diagnostics(opf_ctx* c, opf_diag* d) {
     x.u = c->u;
     x.w = c->w64;
     x.partial = c->partial;
+    x.wall = c->has_wall ? c->wall : nullptr;
     x.t = c->t;
     HIPCHK(c, launch_vorticity(x, c->stream));
     HIPCHK(c, launch_energy(x, c->stream));
@@ -1034,6 +1040,41 @@ opf_status opf_set_dt(opf_ctx* c, double dt) {
         return st;
     }
     if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return OPF_OK;
+}
+
+opf_status opf_set_wall_velocity(opf_ctx* c, const double* b) {
+    if (!c) return OPF_E_INVALID;
+    if (c->in_ensemble) {
+        c->err = "ensemble members keep a no-slip wall";
+        return OPF_E_UNSUPPORTED;
+    }
+    const int M = c->p.M, K = c->p.K, nk = c->nk;
+    if (b) {
+        const size_t n = (size_t)3 * M * nk * 2;
+        std::vector<double> w(b, b + n);
+        auto at = [&](int comp, int mi, int kk) { return &w[(((size_t)comp * M + mi) * nk + kk) * 2]; };
+        for (int comp = 0; comp < 3; ++comp) {
+            for (size_t i = 0; i < n / 3; ++i)
+                if (!std::isfinite(w[comp * (n / 3) + i])) return OPF_E_INVALID;
+            at(comp, 0, K - 1)[1] = 0.0;  // (0,0) of a real field
+            for (int kp = 1; kp < K; ++kp) {  // m = 0, k < 0: conjugates of k > 0
+                at(comp, 0, K - 1 - kp)[0] = at(comp, 0, K - 1 + kp)[0];
+                at(comp, 0, K - 1 - kp)[1] = -at(comp, 0, K - 1 + kp)[1];
+            }
+        }
+        if (at(0, 0, K - 1)[0] != 0.0) {
+            c->err = "the (0,0) radial wall velocity (net flux through the wall) must be zero";
+            return OPF_E_INVALID;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->wall, w.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->has_wall = b != nullptr;
+    if (c->graph) {  // the step graph holds the previous boundary condition
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
     }

@@ -72,6 +72,7 @@ struct SolveArgs {
     double* p_out;      // pressure head [M][nk][N] complex128 (nullable)
     double* beta_out;   // flux correction beta (device scalar)
     double* g_out;      // [M*K] largest |g| after correction, per workgroup (nullable)
+    const double* wall; // wall velocity [3][M][nk] complex (r, theta, z) at r = 1, or null (no slip)
     Tables t;
 };
 
@@ -83,6 +84,7 @@ struct AuxArgs {
     const double* u;    // complex128 external layout
     double* w;          // complex128 output (vorticity)
     double* partial;    // [M][2] per-m sums of |u|^2 and |omega|^2 (quadrature weighted)
+    const double* wall; // wall velocity as in SolveArgs, or null
     Tables t;
 };
 

@@ -365,6 +365,11 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             const double kap = a.alpha * slot_k(q);
             if (n == N - 1) {
                 sX[q][0][n] = sX[q][1][n] = sX[q][2][n] = dcplx{0.0, 0.0};
+                if (m == 0 && kap == 0.0 && a.wall) {  // (0,0): Dirichlet values u_theta(1), u_z(1)
+                    const size_t w0 = (size_t)(K - 1) * 2, ws = (size_t)a.M * nk * 2;
+                    sX[q][0][n] = dcplx{a.wall[ws + w0], 0.0};
+                    sX[q][2][n] = dcplx{a.wall[2 * ws + w0], 0.0};
+                }
             } else if (m == 0 && kap == 0.0) {
                 const dcplx d = sX[q][0][n] - sX[q][1][n];  // 2 i R_theta
                 sX[q][0][n] = dcplx{0.5 * d.y, 0.0};
@@ -407,7 +412,14 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             const double* w1 = t.d1 + (((m + 1) & 1) * N + e) * W9;
             const dcplx ap = stencil(w1, sX[q][0], s0) + (double(1 + m) * rinv) * sX[q][0][e];
             const dcplx am = stencil(w1, sX[q][1], s0) + (double(1 - m) * rinv) * sX[q][1][e];
-            const dcplx g[4] = {sX[q][0][e], sX[q][1][e], sX[q][2][e], 0.5 * (ap + am) + kap * ix(sX[q][2][e])};
+            dcplx g[4] = {sX[q][0][e], sX[q][1][e], sX[q][2][e], 0.5 * (ap + am) + kap * ix(sX[q][2][e])};
+            if (a.wall) {  // drive g to the wall velocity (b_r +- i b_theta, b_z, 0) instead of 0
+                const size_t wi = ((size_t)mi * nk + (k + K - 1)) * 2, ws = (size_t)a.M * nk * 2;
+                const dcplx br = {a.wall[wi], a.wall[wi + 1]}, bt = {a.wall[ws + wi], a.wall[ws + wi + 1]};
+                g[0] = g[0] - (br + ix(bt));
+                g[1] = g[1] - (br - ix(bt));
+                g[2] = g[2] - dcplx{a.wall[2 * ws + wi], a.wall[2 * ws + wi + 1]};
+            }
             const double* A = t.ainv + (((size_t)mi * nk + (k + K - 1)) * 16) * 2;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -633,8 +645,17 @@ __global__ __launch_bounds__(64) void k_divg(AuxArgs a, double* __restrict__ par
         const dcplx d = 0.5 * (ap + am) + kap * ix(uz);
         const double ad = sqrt(d.x * d.x + d.y * d.y);
         if (n == N - 1) {
-            const double a1 = sqrt(up.x * up.x + up.y * up.y), a2 = sqrt(um.x * um.x + um.y * um.y);
-            const double a3 = sqrt(uz.x * uz.x + uz.y * uz.y);
+            dcplx bp = {0.0, 0.0}, bm = {0.0, 0.0}, bz = {0.0, 0.0};
+            if (a.wall) {  // residual against the wall velocity
+                const size_t wi = (size_t)q * 2, ws = (size_t)a.M * nk * 2;
+                const dcplx br = {a.wall[wi], a.wall[wi + 1]}, bt = {a.wall[ws + wi], a.wall[ws + wi + 1]};
+                bp = br + ix(bt);
+                bm = br - ix(bt);
+                bz = dcplx{a.wall[2 * ws + wi], a.wall[2 * ws + wi + 1]};
+            }
+            const dcplx ep = up - bp, em = um - bm, ez = uz - bz;
+            const double a1 = sqrt(ep.x * ep.x + ep.y * ep.y), a2 = sqrt(em.x * em.x + em.y * em.y);
+            const double a3 = sqrt(ez.x * ez.x + ez.y * ez.y);
             gv = fmax(fmax(a1, a2), fmax(a3, ad));
         } else {
             dv = ad;
