@@ -516,8 +516,8 @@ template <typename TNL, int NB>
 __global__ __launch_bounds__(256) void k_solve(SolveArgs a) { k_solve_body<TNL, NB>(a); }
 template <typename TNL, int NB>
 __global__ __launch_bounds__(256) void k_solve_b(const SolveArgs* __restrict__ aa) {
-    const SolveArgs a = aa[blockIdx.y];
-    k_solve_body<TNL, NB>(a);
+    // the member's record is read in place (a private copy would live in scratch)
+    k_solve_body<TNL, NB>(aa[blockIdx.y]);
 }
 
 // Standalone vorticity of an external-layout state.  With a.mirror set

@@ -265,8 +265,7 @@ template <typename TS, typename T, int L>
 __global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L>(a); }
 template <typename TS, typename T, int L>
 __global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
-    const NLArgs a = aa[blockIdx.y];
-    k_zinv_body<TS, T, L>(a);
+    k_zinv_body<TS, T, L>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
 // Coriolis force -2 Omega x u added to (nr, nt, nz) at theta point t of the
@@ -421,8 +420,7 @@ template <typename T, int L, bool ROT>
 __global__ __launch_bounds__(NT2) void k_theta(NLArgs a) { k_theta_body<T, L, ROT>(a); }
 template <typename T, int L>
 __global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) {
-    const NLArgs a = aa[blockIdx.y];
-    k_theta_body<T, L, false>(a);  // ensemble members carry no forcing
+    k_theta_body<T, L, false>(aa[blockIdx.y]);  // ensemble members carry no forcing
 }
 
 // ---------------------------------------------------------------------------
@@ -575,8 +573,7 @@ template <typename T, int L, bool ROT>
 __global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L, ROT>(a); }
 template <typename T, int L>
 __global__ __launch_bounds__(NT3) void k_theta_lp_b(const NLArgs* __restrict__ aa) {
-    const NLArgs a = aa[blockIdx.y];
-    k_theta_lp_body<T, L, false>(a);  // ensemble members carry no forcing
+    k_theta_lp_body<T, L, false>(aa[blockIdx.y]);  // ensemble members carry no forcing
 }
 
 // ---------------------------------------------------------------------------
@@ -743,8 +740,7 @@ template <typename TS, typename T, int L>
 __global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L>(a); }
 template <typename TS, typename T, int L>
 __global__ __launch_bounds__(NT2) void k_zfwd_b(const NLArgs* __restrict__ aa) {
-    const NLArgs a = aa[blockIdx.y];
-    k_zfwd_body<TS, T, L>(a);
+    k_zfwd_body<TS, T, L>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
 // ---------------------------------------------------------------------------
