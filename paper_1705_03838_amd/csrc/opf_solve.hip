@@ -396,6 +396,14 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     __syncthreads();
 
     // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
+    // The influence data of this wave's m (one radial row per lane) is loaded
+    // now, so its latency overlaps the influence step of the first lanes.
+    double hv[NHOM];
+    {
+        const double* h = t.hom + ((size_t)min(m0 + w, a.M - 1) * K + kabs) * NHOM * N;
+#pragma unroll
+        for (int j = 0; j < NHOM; ++j) hv[j] = h[j * N + nr];
+    }
     if (tid < NSLOT && slot_ok(tid)) {
         const int q = tid;
         const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
@@ -445,9 +453,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
                 sY[q][n] = dcplx{0.0, 0.0};
             } else {
                 const double kap = a.alpha * k;
-                const double* h = t.hom + ((size_t)mi * K + kabs) * NHOM * N;
-                const double h1p = h[n], h1m = h[N + n], qv = h[2 * N + n];
-                const double h2 = h[3 * N + n], h3 = h[4 * N + n], h4 = h[5 * N + n], P1 = h[6 * N + n];
+                const double h1p = hv[0], h1m = hv[1], qv = hv[2], h2 = hv[3], h3 = hv[4], h4 = hv[5], P1 = hv[6];
                 const dcplx a1 = sA[q][0], a2 = sA[q][1], a3 = sA[q][2], a4 = sA[q][3];
                 sX[q][0][n] = sX[q][0][n] + h1p * a1 + h2 * a2;
                 sX[q][1][n] = sX[q][1][n] + h1m * a1 + h3 * a3;
