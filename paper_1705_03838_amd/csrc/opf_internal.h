@@ -20,9 +20,10 @@ constexpr int NMAX = 64;  // radial points handled by one solve workgroup
 constexpr int TILE = 8;   // radial lines per z-transform workgroup, z lines per theta workgroup
 
 // Complex number used by the kernels (interleaved re/im, same layout as
-// complex128 / complex64 in memory).
+// complex128 / complex64 in memory).  Aligned to its full size so that one
+// value is one 16-byte (FP64) or 8-byte (FP32) load or store, in HBM and LDS.
 template <typename T>
-struct cpx {
+struct alignas(2 * sizeof(T)) cpx {
     T x, y;
 };
 

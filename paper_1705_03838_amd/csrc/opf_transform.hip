@@ -142,11 +142,51 @@ __device__ __forceinline__ cpx<TO> cvt(cpx<TI> a) { return {TO(a.x), TO(a.y)}; }
 // Small DFT of length R in registers, R in {2,3,4,6,8,9,12,16}.  Composite R
 // = R1 R2 (R1 in {3,4}) by one Cooley-Tukey split: R2 DFTs of length R1 on
 // stride-R2 subsets, twiddles W_R^{n2 k1}, R1 DFTs of length R2; output
-// index k1 + R1 k2.  tw holds e^{-2 pi i t / L} (R divides L).
+// index k1 + R1 k2.  The twiddles W_R^e are compile-time constants.
 template <int R> struct Split1 { static constexpr int R1 = (R == 6 || R == 9) ? 3 : 4; };
 
+// cos and sin of 2 pi e / R, evaluated by the compiler: the angle is reduced
+// exactly to y = 2 pi e / R - o pi / 2 with |y| <= pi / 4 (o the nearest
+// quarter turn), and cos y, sin y are summed from their Taylor series to
+// well below double rounding.
+constexpr double kPi = 3.14159265358979323846;
+constexpr double taylor_cos(double y) {
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i <= 12; ++i) { t *= -y * y / ((2 * i - 1) * (2 * i)); s += t; }
+    return s;
+}
+constexpr double taylor_sin(double y) {
+    double t = y, s = y;
+    for (int i = 1; i <= 12; ++i) { t *= -y * y / ((2 * i) * (2 * i + 1)); s += t; }
+    return s;
+}
+template <int R>
+struct UnitRoots {
+    double c[R], s[R];  // cos, sin of 2 pi e / R
+    constexpr UnitRoots() : c(), s() {
+        for (int e = 0; e < R; ++e) {
+            const int o = (8 * e + R) / (2 * R);  // nearest multiple of R / 4 to e, in quarters
+            const double y = (kPi / 2) * double(4 * e - o * R) / double(R);
+            const double cy = taylor_cos(y), sy = taylor_sin(y);
+            switch (o % 4) {
+                case 0: c[e] = cy; s[e] = sy; break;
+                case 1: c[e] = -sy; s[e] = cy; break;
+                case 2: c[e] = -cy; s[e] = -sy; break;
+                default: c[e] = sy; s[e] = -cy; break;
+            }
+        }
+    }
+};
+template <int R> struct RootTable { static constexpr UnitRoots<R> v{}; };
+
+// W_R^e = e^{-2 pi i e / R}
 template <typename T, int R>
-__device__ __forceinline__ void dftn(cpx<T>* v, int sign, const cpx<T>* tw, int L) {
+__device__ __forceinline__ cpx<T> unit_root(int e) {
+    return {T(RootTable<R>::v.c[e]), T(-RootTable<R>::v.s[e])};
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftn(cpx<T>* v, int sign) {
     if constexpr (R <= 4) {
         dft<T, R>(v, sign);
     } else {
@@ -158,12 +198,11 @@ __device__ __forceinline__ void dftn(cpx<T>* v, int sign, const cpx<T>* tw, int 
             for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[R2 * n1 + n2];
             dft<T, R1>(y[n2], sign);
         }
-        const int step = L / R;
 #pragma unroll
         for (int n2 = 1; n2 < R2; ++n2)
 #pragma unroll
             for (int k1 = 1; k1 < R1; ++k1) {
-                const cpx<T> w = tw[((n2 * k1) % R) * step];
+                const cpx<T> w = unit_root<T, R>((n2 * k1) % R);
                 y[n2][k1] = sign < 0 ? cmul(y[n2][k1], w) : cmulc(y[n2][k1], w);
             }
 #pragma unroll
@@ -240,7 +279,7 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     }
     __syncthreads();  // twiddles
     if (ja < RB) {
-        dftn<T, RA>(v, +1, tw, L);
+        dftn<T, RA>(v, +1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
     }
@@ -254,7 +293,7 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
             const cpx<T> x = buf[nb * LS + jb + r * RA];
             u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
         }
-        dftn<T, RB>(u, +1, tw, L);
+        dftn<T, RB>(u, +1);
         cpx<T>* dst = reinterpret_cast<cpx<T>*>(a.H) + ((size_t)f * N * M + (size_t)(n0 + nb) * M + m) * L;
 #pragma unroll
         for (int r = 0; r < RB; ++r) dst[jb + r * RA] = u[r];
@@ -270,11 +309,10 @@ __global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
 
 // Coriolis force -2 Omega x u added to (nr, nt, nz) at theta point t of the
 // dealiased line: angle 2 pi t / 3M (a transverse axis needs mp = 1), with
-// tw[t] = exp(-2 pi i t / 3M) giving its cosine and sine.
+// w = exp(-2 pi i t / 3M) giving its cosine and sine.
 template <typename T>
-__device__ __forceinline__ void add_coriolis(const NLArgs& a, const cpx<T>* tw, int t, T ur, T ut, T uz, T& nr,
-                                             T& nt, T& nz) {
-    const T c = tw[t].x, s = -tw[t].y;
+__device__ __forceinline__ void add_coriolis(const NLArgs& a, cpx<T> w, T ur, T ut, T uz, T& nr, T& nt, T& nz) {
+    const T c = w.x, s = -w.y;
     const T ox = T(a.rot[0]), oy = T(a.rot[1]), oz = T(a.rot[2]);
     const T o_r = ox * c + oy * s, o_t = oy * c - ox * s;
     nr -= T(2) * (o_t * uz - oz * ut);
@@ -331,7 +369,7 @@ __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
     __syncthreads();  // twiddles
     if (ja < RB) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p) dftn<T, RA>(v[p], +1, tw, L);
+        for (int p = 0; p < 3; ++p) dftn<T, RA>(v[p], +1);
     }
     // transposes, one line at a time; pass B threads (zz, j)
     const int zb = tid / RA, jb = tid % RA;
@@ -356,17 +394,17 @@ __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
     // inverse pass B, product, forward pass A' (radix RB on the same points)
     if (actB) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p) dftn<T, RB>(u[p], +1, tw, L);
+        for (int p = 0; p < 3; ++p) dftn<T, RB>(u[p], +1);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const T ur = u[0][r].x, ut = u[0][r].y, uz = u[1][r].x, wr = u[1][r].y, wt = u[2][r].x, wz = u[2][r].y;
             T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
-            if constexpr (ROT) add_coriolis<T>(a, tw, jb + r * RA, ur, ut, uz, nr, nt, nz);  // theta point jb + r RA
+            if constexpr (ROT) add_coriolis<T>(a, tw[jb + r * RA], ur, ut, uz, nr, nt, nz);  // theta point jb + r RA
             u[0][r] = {nr, nt};
             u[1][r] = {nz, T(0)};
         }
-        dftn<T, RB>(u[0], -1, tw, L);
-        dftn<T, RB>(u[1], -1, tw, L);
+        dftn<T, RB>(u[0], -1);
+        dftn<T, RB>(u[1], -1);
     }
     // forward pass B' (radix RA, Ns = RB): thread (zz, j), j < RB, takes y[j + r RB]
     const int zc2 = tid / RB, jc = tid % RB;
@@ -394,7 +432,7 @@ __device__ __forceinline__ void k_theta_body(const NLArgs& a) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         if (actC) {
-            dftn<T, RA>(x2[p], -1, tw, L);
+            dftn<T, RA>(x2[p], -1);
 #pragma unroll
             for (int r = 0; r < RA; ++r) buf[zc2 * LS + jc + r * RB] = x2[p][r];
         }
@@ -433,8 +471,45 @@ __global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) 
 // tiles sharing a 128-byte line of H and G (FP64) run on the same XCD:
 // blocks g*16 + x and g*16 + x + 8 (x < 8) take tiles g*16 + 2x, g*16 + 2x + 1,
 // with consecutive block indices dispatched round-robin over the 8 XCDs.
+//
+// LDS layout.  Each wave owns TZ segments of LS slots (one per axial point).
+// Between the two radix passes of a transform, the r-th output of first-pass
+// lane j sits at slot r (R2 + 1) + j, R2 the number of first-pass lanes of a
+// line: the first pass stores at stride one across lanes and the second pass
+// loads at stride R2 + 1.  Theta points (for the product) and wavenumber
+// bins (for the unpacking) are kept in natural order.  LS >= L + max(RA, RB)
+// is the padding that, among the 17 values from there, spreads the kernel's
+// 16-byte accesses over the most LDS banks (64 four-byte banks, 16
+// consecutive lanes), counted access by access.  The twiddles between the
+// passes come from tw2[r RM + j] = W_L^{j r}, RM = max(RA, RB), read at
+// stride one; the roots inside each radix are compile-time constants.
 constexpr int TZ = 4;
 constexpr int NT3 = 192;
+
+template <int L> struct ThetaLayout;
+template <> struct ThetaLayout<6> { static constexpr int LS = 13; };
+template <> struct ThetaLayout<9> { static constexpr int LS = 19; };
+template <> struct ThetaLayout<12> { static constexpr int LS = 20; };
+template <> struct ThetaLayout<18> { static constexpr int LS = 28; };
+template <> struct ThetaLayout<24> { static constexpr int LS = 44; };
+template <> struct ThetaLayout<36> { static constexpr int LS = 54; };
+template <> struct ThetaLayout<48> { static constexpr int LS = 70; };
+template <> struct ThetaLayout<54> { static constexpr int LS = 70; };
+template <> struct ThetaLayout<72> { static constexpr int LS = 88; };
+template <> struct ThetaLayout<96> { static constexpr int LS = 120; };
+template <> struct ThetaLayout<108> { static constexpr int LS = 121; };
+template <> struct ThetaLayout<144> { static constexpr int LS = 156; };
+template <> struct ThetaLayout<192> { static constexpr int LS = 220; };
+
+template <int L>
+__host__ __device__ constexpr int theta_rm() {
+    return TwoPass<L>::RA > TwoPass<L>::RB ? TwoPass<L>::RA : TwoPass<L>::RB;
+}
+// LDS bytes of one k_theta_lp workgroup
+template <typename T, int L>
+constexpr size_t theta_lp_lds() {
+    return (size_t)(theta_rm<L>() * theta_rm<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
+}
 
 __device__ __forceinline__ int xcd_pair_tile(int b, int total) {
     const int g = b / 16, w = b % 16;
@@ -444,11 +519,12 @@ __device__ __forceinline__ int xcd_pair_tile(int b, int total) {
 
 template <typename T, int L, bool ROT>
 __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
-    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ThetaLayout<L>::LS, RM = theta_rm<L>();
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
+    static_assert(LS >= L + RM, "segment too short for the skewed layout");
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
-    cpx<T>* buf = tw + L;                                // [3][TZ][LS]
+    cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
+    cpx<T>* buf = tw2 + RM * RM;                         // [3][TZ][LS]
     const int N = a.N, M = a.M, L3K = 3 * a.K;
     const int nzt = (L3K + TZ - 1) / TZ;
     const int tile = xcd_pair_tile(blockIdx.x, N * nzt);
@@ -456,8 +532,8 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     const int z0 = (tile % nzt) * TZ;
     const int tid = threadIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
-    for (int t = tid; t < L; t += NT3) tw[t] = twg[t];
+    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);  // W_L^t, t < L
+    for (int t = tid; t < RM * RM; t += NT3) tw2[t] = twg[((t % RM) * (t / RM)) % L];
     const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
     const size_t fstride = (size_t)N * M * L3K;
     const size_t nbase = (size_t)n * M * L3K;
@@ -484,25 +560,23 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             }
             v[r] = val;
         }
-    }
-    __syncthreads();  // twiddles
-    if (ja < RB) {
-        dftn<T, RA>(v, +1, tw, L);
+        dftn<T, RA>(v, +1);
 #pragma unroll
-        for (int r = 0; r < RA; ++r) lb[za * LS + ja * RA + r] = v[r];
+        for (int r = 0; r < RA; ++r) lb[za * LS + r * (RB + 1) + ja] = v[r];
     }
-    __syncthreads();
-    // inverse pass B: lane (zz, j); the line's values at theta points j + r RA
+    __syncthreads();  // pass A results and tw2
+    // inverse pass B: lane (zz, j); output r of pass-A lane r', then theta
+    // points j + r RA in natural order
     const int zb = lane / RA, jb = lane % RA;
     const bool actB = zb < TZ;
     cpx<T> u[RB];
     if (actB) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const cpx<T> x = lb[zb * LS + jb + r * RA];
-            u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+            const cpx<T> x = lb[zb * LS + jb * (RB + 1) + r];
+            u[r] = r == 0 ? x : cmulc(x, tw2[r * RM + jb]);
         }
-        dftn<T, RB>(u, +1, tw, L);
+        dftn<T, RB>(u, +1);
     }
     __syncthreads();
     if (actB) {
@@ -520,28 +594,30 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZ + zb) * LS + pt], l2 = buf[(2 * TZ + zb) * LS + pt];
             const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
             T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
-            if constexpr (ROT) add_coriolis<T>(a, tw, pt, ur, ut, uz, nr, nt, nz);
+            // W_L^{jb + r RA} = W_L^{jb} W_RB^{r}
+            if constexpr (ROT) add_coriolis<T>(a, cmul(tw2[RM + jb], unit_root<T, RB>(r)), ur, ut, uz, nr, nt, nz);
             u[r] = p == 0 ? cpx<T>{nr, nt} : cpx<T>{nz, T(0)};
         }
-        dftn<T, RB>(u, -1, tw, L);
+        dftn<T, RB>(u, -1);
     }
     __syncthreads();  // every line has been read
     if (out && actB) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) lb[zb * LS + jb * RB + r] = u[r];
+        for (int r = 0; r < RB; ++r) lb[zb * LS + r * (RA + 1) + jb] = u[r];
     }
     __syncthreads();
-    // forward pass B' (radix RA, Ns = RB): lane (zz, j), j < RB, takes y[j + r RB]
+    // forward pass B' (radix RA): lane (zz, j), j < RB, takes output j of
+    // pass-A' lanes r = 0..RA-1; results are bins j + r RB
     const int zc2 = lane / RB, jc = lane % RB;
     const bool actC = out && zc2 < TZ;
     cpx<T> x2[RA];
     if (actC) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
-            const cpx<T> x = lb[zc2 * LS + jc + r * RB];
-            x2[r] = r == 0 ? x : cmul(x, tw[jc * r]);
+            const cpx<T> x = lb[zc2 * LS + jc * (RA + 1) + r];
+            x2[r] = r == 0 ? x : cmul(x, tw2[r * RM + jc]);
         }
-        dftn<T, RA>(x2, -1, tw, L);
+        dftn<T, RA>(x2, -1);
     }
     __syncthreads();
     if (actC) {
@@ -623,7 +699,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     }
     __syncthreads();  // twiddles
     if (ja < RB) {
-        dftn<T, RA>(v, +1, tw, L);
+        dftn<T, RA>(v, +1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) lb[za * LS + ja * RA + r] = v[r];
     }
@@ -637,7 +713,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
             const cpx<T> x = lb[zb * LS + jb + r * RA];
             u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
         }
-        dftn<T, RB>(u, +1, tw, L);
+        dftn<T, RB>(u, +1);
     }
     __syncthreads();
     if (actB) {
@@ -709,7 +785,7 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     }
     __syncthreads();
     if (na < TILE) {
-        dftn<T, RA>(v, -1, tw, L);
+        dftn<T, RA>(v, -1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
     }
@@ -723,7 +799,7 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
             const cpx<T> x = buf[nb * LS + jb + r * RA];
             u[r] = r == 0 ? x : cmul(x, tw[jb * r]);
         }
-        dftn<T, RB>(u, -1, tw, L);
+        dftn<T, RB>(u, -1);
         cpx<TS>* dst = reinterpret_cast<cpx<TS>*>(a.out[f]) + (size_t)m * nk * N + n0 + nb;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -778,13 +854,12 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
         }
     } else if (stage == 1 && sizeof(T) == 8) {  // FP64: line-parallel form
         const dim3 g(a.N * ((L3K + TZ - 1) / TZ), b ? members : 1);
-        const size_t l3 = (size_t)(L3M + 3 * TZ * (L3M + 1)) * sizeof(cpx<T>);
         switch (L3M) {
-#define OPF_CASE(V)                                                                    \
-    case V:                                                                            \
-        if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), l3, s, batch);    \
-        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, V, true>), g, dim3(NT3), l3, s, a); \
-        else hipLaunchKernelGGL((k_theta_lp<T, V, false>), g, dim3(NT3), l3, s, a);     \
+#define OPF_CASE(V)                                                                                          \
+    case V:                                                                                                  \
+        if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, batch);        \
+        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, V, true>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a); \
+        else hipLaunchKernelGGL((k_theta_lp<T, V, false>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a);        \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
