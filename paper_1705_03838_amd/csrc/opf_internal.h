@@ -17,7 +17,7 @@ constexpr int HALF = 4;   // points on each side of a centred stencil
 constexpr int FACW = 14;  // doubles per LU factor row: 8 of L, 4 of U, 1/U_ii, pad
 constexpr int NHOM = 7;   // real radial lines of influence data per (m,|k|)
 constexpr int NMAX = 64;  // radial points handled by one solve workgroup
-constexpr int TILE = 8;   // radial lines per z-transform workgroup, z lines per theta workgroup
+constexpr int TILE = 8;   // radial lines per z-transform workgroup
 
 // Complex number used by the kernels (interleaved re/im, same layout as
 // complex128 / complex64 in memory).  Aligned to its full size so that one

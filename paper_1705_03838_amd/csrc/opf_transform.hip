@@ -9,17 +9,18 @@
 //   k_zinv  : per (field, m, 8 radial nodes): 2K-1 axial coefficients ->
 //             3K points (inverse c2c, zero padded), written z-contiguous to
 //             H[field][n][m][z].
-//   k_theta : per (n, 8 axial points): the 6 fields' M azimuthal coefficients
-//             are packed two real fields per complex line, inverse FFT over
-//             3M points, u x omega at every point, forward FFT of
-//             (N_r + i N_t) and (N_z + i 0), unpacked and scaled by 1/(9KM)
-//             into G[comp][n][m][z].  Physical fields never leave LDS.
+//   k_theta_lp : per (n, 4 axial points): the 6 fields' M azimuthal
+//             coefficients are packed two real fields per complex line,
+//             inverse FFT over 3M points, u x omega at every point, forward
+//             FFT of (N_r + i N_t) and (N_z + i 0), unpacked and scaled by
+//             1/(9KM) into G[comp][n][m][z].  Physical fields never leave LDS.
 //   k_zfwd  : per (comp, m, 8 radial nodes): forward c2c over 3K points,
 //             |k| < K kept, written to the spectral layout.
 //
-// FFTs are radix-4/2/3 Stockham passes on lines held in LDS, each pass
-// staged through registers (read all, barrier, write all), with FP64 (or
-// FP32) twiddles from a host-built table staged in LDS.
+// Each length is split L = RA RB: a radix-RA DFT in registers per lane, a
+// reordering through LDS with the twiddles W_L^{j r} (host-built table staged
+// in LDS), then a radix-RB DFT; the roots inside each radix are compile-time
+// constants.
 #include "opf_internal.h"
 
 namespace opf {
@@ -36,15 +37,6 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
 __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
-
-__host__ __device__ constexpr int count2(int L) { int c = 0; while (L % 2 == 0) { L /= 2; ++c; } return c; }
-__host__ __device__ constexpr int count3(int L) { int c = 0; while (L % 3 == 0) { L /= 3; ++c; } return c; }
-template <int L>
-__host__ __device__ constexpr int n_stages() { return count2(L) / 2 + count2(L) % 2 + count3(L); }
-template <int L>
-__host__ __device__ constexpr int radix_of(int s) {
-    return s < count2(L) / 2 ? 4 : (s < count2(L) / 2 + count2(L) % 2 ? 2 : 3);
-}
 
 // In-register DFT of length R; sign = -1 forward, +1 inverse.
 template <typename T, int R>
@@ -72,68 +64,6 @@ __device__ __forceinline__ void dft(cpx<T>* v, int sign) {
         v[1] = cadd(t1, t3);
         v[3] = csub(t1, t3);
     }
-}
-
-// One Stockham pass of radix R over NLINE lines of length L (stride LS) in
-// LDS; NS = product of the radices of the previous passes.
-template <typename T, int L, int NLINE, int LS, int NT, int R, int NS>
-__device__ __forceinline__ void fft_pass(cpx<T>* buf, const cpx<T>* tw, int sign) {
-    constexpr int NB = NLINE * (L / R);
-    constexpr int PER = (NB + NT - 1) / NT;
-    constexpr int TWS = L / (NS * R);
-    cpx<T> v[PER][R];
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * NT;
-        if (NB % NT == 0 || b < NB) {
-            const int line = b / (L / R), j = b % (L / R);
-            const cpx<T>* x = buf + line * LS;
-            const int k = j % NS;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                cpx<T> a = x[j + r * (L / R)];
-                if (NS > 1 && r > 0) {
-                    const cpx<T> w = tw[k * r * TWS];
-                    a = sign < 0 ? cmul(a, w) : cmulc(a, w);
-                }
-                v[p][r] = a;
-            }
-            dft<T, R>(v[p], sign);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * NT;
-        if (NB % NT == 0 || b < NB) {
-            const int line = b / (L / R), j = b % (L / R);
-            cpx<T>* x = buf + line * LS;
-            const int k = j % NS;
-            const int o = (j / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[o + r * NS] = v[p][r];
-        }
-    }
-    __syncthreads();
-}
-
-template <typename T, int L, int NLINE, int LS, int NT, int S, int NS>
-struct FFTStages {
-    static __device__ __forceinline__ void run(cpx<T>* buf, const cpx<T>* tw, int sign) {
-        if constexpr (S < n_stages<L>()) {
-            constexpr int R = radix_of<L>(S);
-            fft_pass<T, L, NLINE, LS, NT, R, NS>(buf, tw, sign);
-            FFTStages<T, L, NLINE, LS, NT, S + 1, NS * R>::run(buf, tw, sign);
-        }
-    }
-};
-
-// Unnormalised DFT of NLINE lines in LDS, in place:
-// sign -1: X_q = sum_j x_j e^{-2 pi i jq/L};  sign +1: e^{+2 pi i jq/L}.
-template <typename T, int L, int NLINE, int LS, int NT>
-__device__ __forceinline__ void lds_fft(cpx<T>* buf, const cpx<T>* tw, int sign) {
-    FFTStages<T, L, NLINE, LS, NT, 0, 1>::run(buf, tw, sign);
 }
 
 template <typename TO, typename TI>
@@ -321,156 +251,13 @@ __device__ __forceinline__ void add_coriolis(const NLArgs& a, cpx<T> w, T ur, T 
 }
 
 // ---------------------------------------------------------------------------
-// k_theta: per (n, TILE axial points): inverse theta transforms of the six
-// fields packed two per complex line, u x omega, forward transforms of
-// (N_r + i N_t) and (N_z + i 0), unpack, scale by 1/(9KM), write G.
-template <typename T, int L, bool ROT>
-__device__ __forceinline__ void k_theta_body(const NLArgs& a) {
-    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
-    extern __shared__ unsigned char smem_raw[];
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
-    cpx<T>* buf = tw + L;                                // [TILE][LS]: one line set
-    const int N = a.N, M = a.M, L3K = 3 * a.K;
-    const int nzt = (L3K + TILE - 1) / TILE;
-    const int n = blockIdx.x / nzt;
-    const int z0 = (blockIdx.x % nzt) * TILE;
-    const int tid = threadIdx.x;
-    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
-    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
-    const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
-    const size_t fstride = (size_t)N * M * L3K;
-    const size_t nbase = (size_t)n * M * L3K;
-    // inverse pass A: thread (j, zz), z fastest; bins j + r RB of the 3 lines
-    const int ja = tid / TILE, za = tid % TILE;
-    const int zc = min(z0 + za, L3K - 1);
-    cpx<T> v[3][RA];
-    if (ja < RB) {
-#pragma unroll
-        for (int r = 0; r < RA; ++r) {
-            const int bin = ja + r * RB;
-            int mm = -1;
-            bool neg = false;
-            if (bin < M) mm = bin;
-            else if (bin > L - M) { mm = L - bin; neg = true; }
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                cpx<T> val = {T(0), T(0)};
-                if (mm >= 0) {
-                    const size_t off = nbase + (size_t)mm * L3K + zc;
-                    const cpx<T> A = H[(2 * p) * fstride + off];
-                    const cpx<T> B = H[(2 * p + 1) * fstride + off];
-                    // Z = A + i B on m >= 0; conj(A) + i conj(B) on bins L - m
-                    val = neg ? cpx<T>{A.x + B.y, B.x - A.y} : cpx<T>{A.x - B.y, A.y + B.x};
-                }
-                v[p][r] = val;
-            }
-        }
-    }
-    __syncthreads();  // twiddles
-    if (ja < RB) {
-#pragma unroll
-        for (int p = 0; p < 3; ++p) dftn<T, RA>(v[p], +1);
-    }
-    // transposes, one line at a time; pass B threads (zz, j)
-    const int zb = tid / RA, jb = tid % RA;
-    const bool actB = zb < TILE;
-    cpx<T> u[3][RB];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        if (ja < RB) {
-#pragma unroll
-            for (int r = 0; r < RA; ++r) buf[za * LS + ja * RA + r] = v[p][r];
-        }
-        __syncthreads();
-        if (actB) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const cpx<T> x = buf[zb * LS + jb + r * RA];
-                u[p][r] = r == 0 ? x : cmulc(x, tw[jb * r]);
-            }
-        }
-        __syncthreads();
-    }
-    // inverse pass B, product, forward pass A' (radix RB on the same points)
-    if (actB) {
-#pragma unroll
-        for (int p = 0; p < 3; ++p) dftn<T, RB>(u[p], +1);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const T ur = u[0][r].x, ut = u[0][r].y, uz = u[1][r].x, wr = u[1][r].y, wt = u[2][r].x, wz = u[2][r].y;
-            T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
-            if constexpr (ROT) add_coriolis<T>(a, tw[jb + r * RA], ur, ut, uz, nr, nt, nz);  // theta point jb + r RA
-            u[0][r] = {nr, nt};
-            u[1][r] = {nz, T(0)};
-        }
-        dftn<T, RB>(u[0], -1);
-        dftn<T, RB>(u[1], -1);
-    }
-    // forward pass B' (radix RA, Ns = RB): thread (zz, j), j < RB, takes y[j + r RB]
-    const int zc2 = tid / RB, jc = tid % RB;
-    const bool actC = zc2 < TILE;
-    cpx<T> x2[2][RA];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        if (actB) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r) buf[zb * LS + jb * RB + r] = u[p][r];
-        }
-        __syncthreads();
-        if (actC) {
-#pragma unroll
-            for (int r = 0; r < RA; ++r) {
-                const cpx<T> x = buf[zc2 * LS + jc + r * RB];
-                x2[p][r] = r == 0 ? x : cmul(x, tw[jc * r]);
-            }
-        }
-        __syncthreads();
-    }
-    // forward result X[j + r RB] back to LDS line by line, unpack pairs
-    cpx<T>* G = reinterpret_cast<cpx<T>*>(a.G);
-    const T h = T(0.5) * T(a.scale);
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        if (actC) {
-            dftn<T, RA>(x2[p], -1);
-#pragma unroll
-            for (int r = 0; r < RA; ++r) buf[zc2 * LS + jc + r * RB] = x2[p][r];
-        }
-        __syncthreads();
-        for (int t = tid; t < M * TILE; t += NT2) {
-            const int mm = t / TILE, zz = t % TILE, z = z0 + zz;
-            if (z >= L3K) continue;
-            const int mc = mm == 0 ? 0 : L - mm;
-            const cpx<T> Z = buf[zz * LS + mm], Y = buf[zz * LS + mc];
-            const size_t off = nbase + (size_t)mm * L3K + z;
-            if (p == 0) {  // A = (Z + conj Y)/2 -> N_r, B = (Z - conj Y)/(2i) -> N_t
-                G[off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
-                G[fstride + off] = {h * (Z.y + Y.y), h * (Y.x - Z.x)};
-            } else {
-                G[2 * fstride + off] = {h * (Z.x + Y.x), h * (Z.y - Y.y)};
-            }
-        }
-        __syncthreads();
-    }
-}
-
-template <typename T, int L, bool ROT>
-__global__ __launch_bounds__(NT2) void k_theta(NLArgs a) { k_theta_body<T, L, ROT>(a); }
-template <typename T, int L>
-__global__ __launch_bounds__(NT2) void k_theta_b(const NLArgs* __restrict__ aa) {
-    k_theta_body<T, L, false>(aa[blockIdx.y]);  // ensemble members carry no forcing
-}
-
-// ---------------------------------------------------------------------------
-// k_theta_lp: the same computation as k_theta with the three packed lines
-// spread over the three waves of a 192-thread workgroup (wave p holds line
-// p), TZ = 4 axial points per workgroup.  A thread keeps one line's RA or RB
-// values instead of all three, so the FP64 kernel needs about half the
-// registers of k_theta and twice as many waves fit a CU; the product reads
-// the three lines from LDS.  Workgroups are ordered so that the two 4-point
-// tiles sharing a 128-byte line of H and G (FP64) run on the same XCD:
-// blocks g*16 + x and g*16 + x + 8 (x < 8) take tiles g*16 + 2x, g*16 + 2x + 1,
-// with consecutive block indices dispatched round-robin over the 8 XCDs.
+// k_theta_lp: per (n, TZ = 4 axial points), the three packed lines spread
+// over the three waves of a 192-thread workgroup (wave p holds line p).  A
+// thread keeps one line's RA or RB values, not all three (an FP64 thread
+// holding all three needs 208 VGPRs), and the product reads the three lines
+// from LDS.  Workgroups are ordered so that the tiles sharing a 128-byte
+// line of H and G (2 in FP64, 4 in FP32) run on the same XCD, consecutive
+// block indices being dispatched round-robin over the 8 XCDs.
 //
 // LDS layout.  Each wave owns TZ segments of LS slots (one per axial point).
 // Between the two radix passes of a transform, the r-th output of first-pass
@@ -511,15 +298,20 @@ constexpr size_t theta_lp_lds() {
     return (size_t)(theta_rm<L>() * theta_rm<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
 }
 
-__device__ __forceinline__ int xcd_pair_tile(int b, int total) {
-    const int g = b / 16, w = b % 16;
-    if ((g + 1) * 16 > total) return b;
-    return g * 16 + 2 * (w % 8) + w / 8;
+// Blocks g*8G + x + 8y (x < 8, y < G) take tiles g*8G + G x + y, so the G
+// tiles of one 128-byte line run on one XCD; a last partial group keeps the
+// identity order.
+template <int G>
+__device__ __forceinline__ int xcd_group_tile(int b, int total) {
+    const int g = b / (8 * G), w = b % (8 * G);
+    if ((g + 1) * 8 * G > total) return b;
+    return g * 8 * G + G * (w % 8) + w / 8;
 }
 
 template <typename T, int L, bool ROT>
 __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ThetaLayout<L>::LS, RM = theta_rm<L>();
+    constexpr int XG = 128 / (TZ * (int)sizeof(cpx<T>));  // tiles per 128-byte line of H and G
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
     extern __shared__ unsigned char smem_raw[];
@@ -527,7 +319,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     cpx<T>* buf = tw2 + RM * RM;                         // [3][TZ][LS]
     const int N = a.N, M = a.M, L3K = 3 * a.K;
     const int nzt = (L3K + TZ - 1) / TZ;
-    const int tile = xcd_pair_tile(blockIdx.x, N * nzt);
+    const int tile = xcd_group_tile<XG>(blockIdx.x, N * nzt);
     const int n = tile / nzt;
     const int z0 = (tile % nzt) * TZ;
     const int tid = threadIdx.x;
@@ -836,9 +628,7 @@ template <typename TS, typename T>
 static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
     const int ntile = (a.N + TILE - 1) / TILE;
-    const int nzt = (L3K + TILE - 1) / TILE;
     const size_t lz = (size_t)(L3K + TILE * (L3K + 1)) * sizeof(cpx<T>);
-    const size_t lt = (size_t)(L3M + TILE * (L3M + 1)) * sizeof(cpx<T>);
     const bool b = batch != nullptr;
     if (stage == 0) {
         const dim3 g(6 * a.M * ntile, b ? members : 1);
@@ -852,7 +642,7 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
 #undef OPF_CASE
             default: return hipErrorInvalidValue;
         }
-    } else if (stage == 1 && sizeof(T) == 8) {  // FP64: line-parallel form
+    } else if (stage == 1) {
         const dim3 g(a.N * ((L3K + TZ - 1) / TZ), b ? members : 1);
         switch (L3M) {
 #define OPF_CASE(V)                                                                                          \
@@ -860,19 +650,6 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
         if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, batch);        \
         else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, V, true>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a); \
         else hipLaunchKernelGGL((k_theta_lp<T, V, false>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a);        \
-        break;
-            OPF_FOR_LENGTHS(OPF_CASE)
-#undef OPF_CASE
-            default: return hipErrorInvalidValue;
-        }
-    } else if (stage == 1) {
-        const dim3 g(a.N * nzt, b ? members : 1);
-        switch (L3M) {
-#define OPF_CASE(V)                                                              \
-    case V:                                                                      \
-        if (b) hipLaunchKernelGGL((k_theta_b<T, V>), g, dim3(NT2), lt, s, batch); \
-        else if (a.rotating) hipLaunchKernelGGL((k_theta<T, V, true>), g, dim3(NT2), lt, s, a); \
-        else hipLaunchKernelGGL((k_theta<T, V, false>), g, dim3(NT2), lt, s, a);  \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
