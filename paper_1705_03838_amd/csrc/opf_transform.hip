@@ -165,11 +165,32 @@ template <> struct TwoPass<96> { static constexpr int RA = 8, RB = 12; };
 template <> struct TwoPass<108> { static constexpr int RA = 9, RB = 12; };
 template <> struct TwoPass<144> { static constexpr int RA = 12, RB = 12; };
 template <> struct TwoPass<192> { static constexpr int RA = 12, RB = 16; };
+template <int L>
+__host__ __device__ constexpr int radix_max() {
+    return TwoPass<L>::RA > TwoPass<L>::RB ? TwoPass<L>::RA : TwoPass<L>::RB;
+}
 
-template <typename T>
-__device__ __forceinline__ cpx<T> twid(const cpx<T>* tw, int e, int sign) {
-    const cpx<T> w = tw[e];
-    return sign < 0 ? w : cpx<T>{w.x, -w.y};
+// Segment strides of the z transforms' skewed LDS layout (the layout is
+// described at k_theta_lp): LSI for k_zinv, LSF for k_zfwd, chosen the same
+// way for these kernels' lane orders.
+template <int L> struct ZLayout;
+template <> struct ZLayout<6> { static constexpr int LSI = 10, LSF = 19; };
+template <> struct ZLayout<9> { static constexpr int LSI = 13, LSF = 19; };
+template <> struct ZLayout<12> { static constexpr int LSI = 18, LSF = 18; };
+template <> struct ZLayout<18> { static constexpr int LSI = 26, LSF = 38; };
+template <> struct ZLayout<24> { static constexpr int LSI = 30, LSF = 38; };
+template <> struct ZLayout<36> { static constexpr int LSI = 42, LSF = 54; };
+template <> struct ZLayout<48> { static constexpr int LSI = 70, LSF = 58; };
+template <> struct ZLayout<54> { static constexpr int LSI = 70, LSF = 73; };
+template <> struct ZLayout<72> { static constexpr int LSI = 81, LSF = 89; };
+template <> struct ZLayout<96> { static constexpr int LSI = 110, LSF = 110; };
+template <> struct ZLayout<108> { static constexpr int LSI = 126, LSF = 122; };
+template <> struct ZLayout<144> { static constexpr int LSI = 158, LSF = 158; };
+template <> struct ZLayout<192> { static constexpr int LSI = 210, LSF = 210; };
+// LDS bytes of one z-transform workgroup
+template <typename T, int L, bool INV>
+constexpr size_t z_lds() {
+    return (size_t)(radix_max<L>() * radix_max<L>() + TILE * (INV ? ZLayout<L>::LSI : ZLayout<L>::LSF)) * sizeof(cpx<T>);
 }
 
 constexpr int NT2 = 128;  // threads of a z-transform workgroup (TILE lines)
@@ -179,10 +200,11 @@ constexpr int NT2 = 128;  // threads of a z-transform workgroup (TILE lines)
 // padded).  Workgroup: field f, azimuthal index m, TILE radial nodes.
 template <typename TS, typename T, int L>
 __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
-    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSI, RM = radix_max<L>();
+    static_assert(LS >= L + RM, "segment too short for the skewed layout");
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
-    cpx<T>* buf = tw + L;                                // [TILE][LS]
+    cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
+    cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
     const int N = a.N, M = a.M, K = a.K, nk = a.nk;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
@@ -190,8 +212,8 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     const int f = blockIdx.x / (ntile * M);
     const int n0 = tile * TILE;
     const int tid = threadIdx.x;
-    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);
-    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
+    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);  // W_L^t, t < L
+    for (int t = tid; t < RM * RM; t += NT2) tw2[t] = twg[((t % RM) * (t / RM)) % L];
     const cpx<TS>* src = reinterpret_cast<const cpx<TS>*>(a.in[f]) + (size_t)m * nk * N;
     // pass A: thread (j, nn), radial node fastest (coalesced rows of the spectral layout)
     const int ja = tid / TILE, na = tid % TILE;
@@ -206,22 +228,19 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
             else if (bin > L - K) kk = bin - L + K - 1;
             v[r] = kk >= 0 ? cvt<T>(src[(size_t)kk * N + n]) : cpx<T>{T(0), T(0)};
         }
-    }
-    __syncthreads();  // twiddles
-    if (ja < RB) {
         dftn<T, RA>(v, +1);
 #pragma unroll
-        for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
+        for (int r = 0; r < RA; ++r) buf[na * LS + r * (RB + 1) + ja] = v[r];
     }
-    __syncthreads();
+    __syncthreads();  // pass A results and tw2
     // pass B: thread (nn, j), z fastest (coalesced z lines of H)
     const int nb = tid / RA, jb = tid % RA;
     if (nb < TILE && n0 + nb < N) {
         cpx<T> u[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const cpx<T> x = buf[nb * LS + jb + r * RA];
-            u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
+            const cpx<T> x = buf[nb * LS + jb * (RB + 1) + r];  // output jb of pass-A lane r
+            u[r] = r == 0 ? x : cmulc(x, tw2[r * RM + jb]);
         }
         dftn<T, RB>(u, +1);
         cpx<T>* dst = reinterpret_cast<cpx<T>*>(a.H) + ((size_t)f * N * M + (size_t)(n0 + nb) * M + m) * L;
@@ -288,14 +307,10 @@ template <> struct ThetaLayout<108> { static constexpr int LS = 121; };
 template <> struct ThetaLayout<144> { static constexpr int LS = 156; };
 template <> struct ThetaLayout<192> { static constexpr int LS = 220; };
 
-template <int L>
-__host__ __device__ constexpr int theta_rm() {
-    return TwoPass<L>::RA > TwoPass<L>::RB ? TwoPass<L>::RA : TwoPass<L>::RB;
-}
 // LDS bytes of one k_theta_lp workgroup
 template <typename T, int L>
 constexpr size_t theta_lp_lds() {
-    return (size_t)(theta_rm<L>() * theta_rm<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
+    return (size_t)(radix_max<L>() * radix_max<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
 }
 
 // Blocks g*8G + x + 8y (x < 8, y < G) take tiles g*8G + G x + y, so the G
@@ -310,7 +325,7 @@ __device__ __forceinline__ int xcd_group_tile(int b, int total) {
 
 template <typename T, int L, bool ROT>
 __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
-    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ThetaLayout<L>::LS, RM = theta_rm<L>();
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ThetaLayout<L>::LS, RM = radix_max<L>();
     constexpr int XG = 128 / (TZ * (int)sizeof(cpx<T>));  // tiles per 128-byte line of H and G
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
@@ -552,10 +567,11 @@ static hipError_t launch_cfl_typed(const NLArgs& a, const double* wr, const doub
 // k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
 template <typename TS, typename T, int L>
 __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
-    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
+    constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSF, RM = radix_max<L>();
+    static_assert(LS >= L + RM, "segment too short for the skewed layout");
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* buf = tw + L;
+    cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
+    cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
     const int N = a.N, M = a.M, K = a.K, nk = a.nk;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
@@ -563,8 +579,8 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     const int f = blockIdx.x / (ntile * M);
     const int n0 = tile * TILE;
     const int tid = threadIdx.x;
-    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);
-    for (int t = tid; t < L; t += NT2) tw[t] = twg[t];
+    const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);  // W_L^t, t < L
+    for (int t = tid; t < RM * RM; t += NT2) tw2[t] = twg[((t % RM) * (t / RM)) % L];
     const cpx<T>* src = reinterpret_cast<const cpx<T>*>(a.G) + (size_t)f * N * M * L;
     // pass A: thread (nn, j), z fastest
     const int na = tid / RB, ja = tid % RB;
@@ -574,22 +590,19 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
         const cpx<T>* line = src + ((size_t)n * M + m) * L;
 #pragma unroll
         for (int r = 0; r < RA; ++r) v[r] = line[ja + r * RB];
-    }
-    __syncthreads();
-    if (na < TILE) {
         dftn<T, RA>(v, -1);
 #pragma unroll
-        for (int r = 0; r < RA; ++r) buf[na * LS + ja * RA + r] = v[r];
+        for (int r = 0; r < RA; ++r) buf[na * LS + r * (RB + 1) + ja] = v[r];
     }
-    __syncthreads();
+    __syncthreads();  // pass A results and tw2
     // pass B: thread (j, nn), radial node fastest (coalesced spectral rows)
     const int jb = tid / TILE, nb = tid % TILE;
     if (jb < RA && n0 + nb < N) {
         cpx<T> u[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const cpx<T> x = buf[nb * LS + jb + r * RA];
-            u[r] = r == 0 ? x : cmul(x, tw[jb * r]);
+            const cpx<T> x = buf[nb * LS + jb * (RB + 1) + r];  // output jb of pass-A lane r
+            u[r] = r == 0 ? x : cmul(x, tw2[r * RM + jb]);
         }
         dftn<T, RB>(u, -1);
         cpx<TS>* dst = reinterpret_cast<cpx<TS>*>(a.out[f]) + (size_t)m * nk * N + n0 + nb;
@@ -628,15 +641,14 @@ template <typename TS, typename T>
 static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
     const int ntile = (a.N + TILE - 1) / TILE;
-    const size_t lz = (size_t)(L3K + TILE * (L3K + 1)) * sizeof(cpx<T>);
     const bool b = batch != nullptr;
     if (stage == 0) {
         const dim3 g(6 * a.M * ntile, b ? members : 1);
         switch (L3K) {
 #define OPF_CASE(V)                                                                  \
     case V:                                                                          \
-        if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, V>), g, dim3(NT2), lz, s, batch); \
-        else hipLaunchKernelGGL((k_zinv<TS, T, V>), g, dim3(NT2), lz, s, a);         \
+        if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, V>), g, dim3(NT2), (z_lds<T, V, true>()), s, batch); \
+        else hipLaunchKernelGGL((k_zinv<TS, T, V>), g, dim3(NT2), (z_lds<T, V, true>()), s, a);         \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -660,8 +672,8 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
         switch (L3K) {
 #define OPF_CASE(V)                                                                  \
     case V:                                                                          \
-        if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, V>), g, dim3(NT2), lz, s, batch); \
-        else hipLaunchKernelGGL((k_zfwd<TS, T, V>), g, dim3(NT2), lz, s, a);         \
+        if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, V>), g, dim3(NT2), (z_lds<T, V, false>()), s, batch); \
+        else hipLaunchKernelGGL((k_zfwd<TS, T, V>), g, dim3(NT2), (z_lds<T, V, false>()), s, a);         \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
