@@ -9,13 +9,15 @@
 // vector Laplacian decouples (L_{m+-1} on u+-, L_m on u_z and P), so every
 // system is a real banded matrix acting on complex data.
 //
-// One 64-lane workgroup handles the mode pair (m, +k), (m, -k): both use
-// the same four factors (they depend on |k|).  Lanes are radial nodes for
-// the stencil work; for the substitutions each lane owns one real
-// right-hand side (a real or imaginary part of one component of one mode)
-// and walks the rows with the factor staged in LDS.  m = 0 solves k >= 0
-// only and writes the conjugate into -k (Hermitian symmetry of a real
-// field); mode (0,0) has u_r = 0, no pressure and the fixed-flux correction.
+// One 4-wave workgroup handles |k| and GM consecutive m (GM = 4 for mp = 1),
+// both signs of k: up to eight modes, which share their factors (they depend
+// on |k|, and neighbouring m share Helmholtz operators).  Lanes are radial
+// nodes for the stencil work, wave w holding modes 2w and 2w+1; for the
+// substitutions each lane of wave 0 owns one real right-hand side (a real or
+// imaginary part of one component of one mode) and walks the rows with the
+// factor staged in LDS.  m = 0 solves k >= 0 only and writes the conjugate
+// into -k (Hermitian symmetry of a real field); mode (0,0) has u_r = 0, no
+// pressure and the fixed-flux correction.
 #include "opf_internal.h"
 
 namespace opf {
