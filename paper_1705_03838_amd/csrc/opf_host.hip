@@ -22,6 +22,7 @@ struct opf_ctx {
     std::vector<double> r, rinv, quad, d1, d2;  // host copies
     std::vector<int> s0;
     int nk = 0, MU = 0, nfac = 0, gm = 1;
+    int narrow = 0;  // see SolveArgs::narrow
     double qG_inv = 0.0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -182,6 +183,14 @@ void build_grid(opf_ctx* c, const double* r_nodes) {
             }
         }
     }
+    // Row i of every radial operator is zero left of column s0[i] (the wall
+    // row is the identity), and LU without pivoting fills nothing left of a
+    // row's first nonzero.  So L[i][j] != 0 with i > j + 4 needs a row with
+    // s0[i] <= j <= i - 5, and columns before the smallest such s0[i] have at
+    // most four nonzero entries below the diagonal.
+    c->narrow = N;
+    for (int i = 0; i < N - 1; ++i)
+        if (c->s0[i] <= i - 5) c->narrow = std::min(c->narrow, c->s0[i]);
 
     // quadrature: exact integral of each interval's stencil interpolant times r
     {
@@ -441,6 +450,7 @@ SolveArgs solve_args(const opf_ctx* c, int kind) {
     a.mp = c->p.mp;
     a.MU = c->MU;
     a.gm = c->gm;
+    a.narrow = c->narrow;
     a.kind = kind;
     a.fixed_flux = c->p.fixed_flux;
     a.alpha = c->p.alpha;

@@ -61,6 +61,7 @@ struct NLArgs {
 struct SolveArgs {
     int N, M, K, nk, mp, MU;
     int gm;             // consecutive m per workgroup (tile shape), see gm_ok
+    int narrow;         // LU columns j < narrow have L[i][j] = 0 for i > j + 4
     int kind;           // OPF_SOLVE_PRED / CORR / RAW
     int fixed_flux;
     double alpha, Re, c, inv_dt, aexp, force;

@@ -98,8 +98,10 @@ __device__ __forceinline__ void vort_row(const Tables& t, int N, int n, int m, d
 // kept in registers, so only one FMA per row lies on the dependency chain;
 // factor records and right-hand-side entries are fetched PF rows ahead.
 // Rows N..NB-1 of the factor and of `col` are zero (the padded tail stays
-// zero; no branches).
-template <int NB>
+// zero; no branches).  Columns j < NW have no nonzero L entry more than four
+// rows below the diagonal (SolveArgs::narrow >= NW): their rows read and
+// apply only the first four, with the same result.
+template <int NB, int NW>
 __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* col) {
     constexpr int PF = 3;
     double2 L[PF][4];
@@ -108,7 +110,7 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
     for (int p = 0; p < PF; ++p) {
         const double2* f = reinterpret_cast<const double2*>(F + p * FACW);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) L[p][j] = f[j];
+        for (int j = 0; j < (p < NW ? 2 : 4); ++j) L[p][j] = f[j];
         nb[p] = 8 + p < NB ? col[2 * (8 + p)] : 0.0;
     }
     double b0 = col[0], b1 = col[2], b2 = col[4], b3 = col[6];
@@ -121,7 +123,7 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
         if (i + PF < NB) {
             const double2* f = reinterpret_cast<const double2*>(F + (i + PF) * FACW);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) L[p][j] = f[j];
+            for (int j = 0; j < (i + PF < NW ? 2 : 4); ++j) L[p][j] = f[j];
             nb[p] = i + PF + 8 < NB ? col[2 * (i + PF + 8)] : 0.0;
         }
         const double y = b0;
@@ -130,10 +132,17 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
         b1 = b2 - l01.y * y;
         b2 = b3 - l23.x * y;
         b3 = b4 - l23.y * y;
-        b4 = b5 - l45.x * y;
-        b5 = b6 - l45.y * y;
-        b6 = b7 - l67.x * y;
-        b7 = next - l67.y * y;
+        if (i < NW) {
+            b4 = b5;
+            b5 = b6;
+            b6 = b7;
+            b7 = next;
+        } else {
+            b4 = b5 - l45.x * y;
+            b5 = b6 - l45.y * y;
+            b6 = b7 - l67.x * y;
+            b7 = next - l67.y * y;
+        }
     }
     double2 U[PF][3];  // (u1, u2), (u3, u4), (1/U_ii, pad)
     double nc[PF];     // col[i - 4] for the coming rows
@@ -218,7 +227,7 @@ __device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, 
     wz = 0.5 * ix(am - ap);
 }
 
-template <typename TNL, int NB>
+template <typename TNL, int NB, int NW>
 __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     constexpr int FS = NB * FACW + 4;  // factor stride (doubles): spreads LDS banks
     constexpr int XS = NB + 1;         // radial line stride (complex)
@@ -348,7 +357,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     __syncthreads();
     if (w == 0 && n < 2 * NSLOT) {
         const int q = n >> 1;
-        if (slot_ok(q)) lds_solve<NB>(sF + (q >> 1) * FS, &sY[q][0].x + (n & 1));
+        if (slot_ok(q)) lds_solve<NB, NW>(sF + (q >> 1) * FS, &sY[q][0].x + (n & 1));
     }
     __syncthreads();
 
@@ -392,7 +401,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         if (slot_ok(q)) {
             const int m = mp * (m0 + (q >> 1));
             const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
-            lds_solve<NB>(sF + (mu - mu_lo) * FS, &sX[q][c][0].x + (n & 1));
+            lds_solve<NB, NW>(sF + (mu - mu_lo) * FS, &sX[q][c][0].x + (n & 1));
         }
     }
     __syncthreads();
@@ -520,12 +529,12 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     }
 }
 
-template <typename TNL, int NB>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a) { k_solve_body<TNL, NB>(a); }
-template <typename TNL, int NB>
+template <typename TNL, int NB, int NW>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a) { k_solve_body<TNL, NB, NW>(a); }
+template <typename TNL, int NB, int NW>
 __global__ __launch_bounds__(256) void k_solve_b(const SolveArgs* __restrict__ aa) {
     // the member's record is read in place (a private copy would live in scratch)
-    k_solve_body<TNL, NB>(aa[blockIdx.y]);
+    k_solve_body<TNL, NB, NW>(aa[blockIdx.y]);
 }
 
 // Standalone vorticity of an external-layout state.  With a.mirror set
@@ -604,16 +613,24 @@ hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int me
                               hipStream_t s) {
     const bool b = batch != nullptr;
     const dim3 grid(a.K * ((a.M + a.gm - 1) / a.gm), b ? members : 1), block(256);
-#define OPF_SOLVE_LAUNCH(TNL, NB)                                                   \
-    if (b) hipLaunchKernelGGL((k_solve_b<TNL, NB>), grid, block, 0, s, batch); \
-    else hipLaunchKernelGGL((k_solve<TNL, NB>), grid, block, 0, s, a);
+    // narrow-window rows: the largest compiled count that a.narrow allows
+    // (NB - 9 when N = NB, NB - 25 when N >= NB - 16, else none); the members
+    // of a batch share N and with it narrow
+#define OPF_SOLVE_LAUNCH(TNL, NB, NW)                                                   \
+    if (b) hipLaunchKernelGGL((k_solve_b<TNL, NB, NW>), grid, block, 0, s, batch); \
+    else hipLaunchKernelGGL((k_solve<TNL, NB, NW>), grid, block, 0, s, a);
+#define OPF_SOLVE_NW(TNL, NB)                                                       \
+    if (a.narrow >= NB - 9) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 9) }                 \
+    else if (a.narrow >= NB - 25) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 25) }          \
+    else { OPF_SOLVE_LAUNCH(TNL, NB, 0) }
     if (a.N <= 32) {
-        if (precision == OPF_MIXED) { OPF_SOLVE_LAUNCH(float, 32) }
-        else { OPF_SOLVE_LAUNCH(double, 32) }
+        if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 32) }
+        else { OPF_SOLVE_NW(double, 32) }
     } else {
-        if (precision == OPF_MIXED) { OPF_SOLVE_LAUNCH(float, 64) }
-        else { OPF_SOLVE_LAUNCH(double, 64) }
+        if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 64) }
+        else { OPF_SOLVE_NW(double, 64) }
     }
+#undef OPF_SOLVE_NW
 #undef OPF_SOLVE_LAUNCH
     return hipGetLastError();
 }
