@@ -100,10 +100,12 @@ __device__ __forceinline__ void vort_row(const Tables& t, int N, int n, int m, d
 // Rows N..NB-1 of the factor and of `col` are zero (the padded tail stays
 // zero; no branches).  Columns j < NW have no nonzero L entry more than four
 // rows below the diagonal (SolveArgs::narrow >= NW): their rows read and
-// apply only the first four, with the same result.
+// apply only the first four, with the same result.  With all but the last
+// nine rows narrow, records are fetched 5 rows ahead instead of 3; with
+// fewer narrow rows a deeper prefetch would exceed 256 VGPRs.
 template <int NB, int NW>
 __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* col) {
-    constexpr int PF = 3;
+    constexpr int PF = NW >= NB - 9 ? 5 : 3;  // narrow rows leave registers for a deeper prefetch
     double2 L[PF][4];
     double nb[PF];  // col[i + 8] for the coming rows
 #pragma unroll
