@@ -24,8 +24,8 @@ __device__ inline double wave_max(double v) {
 // m = mp (q - MU K) / K, with P(1) = 0 (the unused (0,0) record gets
 // 1/U = 1).  The band (rows in LDS) is eliminated without pivoting, one
 // column per pass (8 rows x 4 columns of updates in parallel), then written
-// as column records: row i of the record holds L[i+1..i+8][i], U[i-1..i-4][i]
-// and 1/U_ii.  flags[q]: 0 ok, 1 entry outside the band, 2 pivot below
+// as column records: main record i holds L[i+1..i+4][i], U[i-1..i-4][i] and
+// 1/U_ii, tail record i holds L[i+5..i+8][i].  flags[q]: 0 ok, 1 entry outside the band, 2 pivot below
 // 1e-14 max|A|, 3 element growth (|U| > 1e3 max|A| or |L| > 1e3).
 __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     __shared__ double B[NMAX * BW];
@@ -36,8 +36,10 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     const int ka = helm ? q % a.K : (q - a.MU * a.K) % a.K;
     double* F = a.fac + (size_t)q * N * FACW;
     if (!helm && mu == 0 && ka == 0) {
-        if (n < N)
-            for (int d = 0; d < FACW; ++d) F[(size_t)n * FACW + d] = d == 12 ? 1.0 : 0.0;
+        if (n < N) {
+            for (int d = 0; d < FMAIN; ++d) F[(size_t)n * FMAIN + d] = d == 8 ? 1.0 : 0.0;
+            for (int d = 0; d < FTAIL; ++d) F[(size_t)N * FMAIN + (size_t)n * FTAIL + d] = 0.0;
+        }
         if (n == 0) a.flags[q] = 0;
         return;
     }
@@ -96,11 +98,16 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     umax = wave_max(umax);
     lmax = wave_max(lmax);
     if (n < N) {
-        double* f = F + (size_t)n * FACW;
-        for (int d = 0; d < 8; ++d) f[d] = n + 1 + d < N ? B[(n + 1 + d) * BW + (7 - d)] : 0.0;
-        for (int d = 0; d < 4; ++d) f[8 + d] = n - 1 - d >= 0 ? B[(n - 1 - d) * BW + (9 + d)] : 0.0;
-        f[12] = 1.0 / B[n * BW + 8];
-        f[13] = 0.0;
+        double* f = F + (size_t)n * FMAIN;
+        double* tl = F + (size_t)N * FMAIN + (size_t)n * FTAIL;
+        for (int d = 0; d < 8; ++d) {
+            const double l = n + 1 + d < N ? B[(n + 1 + d) * BW + (7 - d)] : 0.0;
+            if (d < 4) f[d] = l;
+            else tl[d - 4] = l;
+        }
+        for (int d = 0; d < 4; ++d) f[4 + d] = n - 1 - d >= 0 ? B[(n - 1 - d) * BW + (9 + d)] : 0.0;
+        f[8] = 1.0 / B[n * BW + 8];
+        f[9] = 0.0;
     }
     // the band check is per row: any lane's flag marks the system
     for (int o = 32; o > 0; o >>= 1) bad = max(bad, __shfl_xor(bad, o));
@@ -112,17 +119,18 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
 // in LDS column `lane` of v[n * 64 + lane].
 __device__ void rec_solve(const double* __restrict__ F, int N, double* v, int lane) {
     for (int i = 0; i < N; ++i) {
-        const double* f = F + (size_t)i * FACW;
+        const double* f = F + (size_t)i * FMAIN;
+        const double* tl = F + (size_t)N * FMAIN + (size_t)i * FTAIL;
         const double x = v[i * 64 + lane];
         for (int d = 0; d < 8; ++d)
-            if (i + 1 + d < N) v[(i + 1 + d) * 64 + lane] -= f[d] * x;
+            if (i + 1 + d < N) v[(i + 1 + d) * 64 + lane] -= (d < 4 ? f[d] : tl[d - 4]) * x;
     }
     for (int i = N - 1; i >= 0; --i) {
-        const double* f = F + (size_t)i * FACW;
-        const double x = v[i * 64 + lane] * f[12];
+        const double* f = F + (size_t)i * FMAIN;
+        const double x = v[i * 64 + lane] * f[8];
         v[i * 64 + lane] = x;
         for (int d = 0; d < 4; ++d)
-            if (i - 1 - d >= 0) v[(i - 1 - d) * 64 + lane] -= f[8 + d] * x;
+            if (i - 1 - d >= 0) v[(i - 1 - d) * 64 + lane] -= f[4 + d] * x;
     }
 }
 

@@ -15,6 +15,12 @@ namespace opf {
 constexpr int W9 = 9;     // finite-difference stencil width (Section 2: 9 points)
 constexpr int HALF = 4;   // points on each side of a centred stencil
 constexpr int FACW = 14;  // doubles per LU factor row: 8 of L, 4 of U, 1/U_ii, pad
+// In HBM the N rows of one factor are FMAIN-double main records (L[i+1..i+4][i],
+// U[i-1..i-4][i], 1/U_ii, pad) followed by FTAIL-double tail records
+// (L[i+5..i+8][i]), N FACW doubles in all; in LDS a row is one FACW record
+// (L[i+1..i+8][i], U[i-1..i-4][i], 1/U_ii, pad).
+constexpr int FMAIN = 10;
+constexpr int FTAIL = 4;
 constexpr int NHOM = 7;   // real radial lines of influence data per (m,|k|)
 constexpr int NMAX = 64;  // radial points handled by one solve workgroup
 constexpr int TILE = 8;   // radial lines per z-transform workgroup
@@ -36,7 +42,7 @@ struct Tables {
     const double* d1;     // [2][N][9] folded first-derivative weights, parity 0 even / 1 odd
     const double* d2;     // [2][N][9] folded second-derivative weights
     const int* s0;        // [N] first column of row n's 9-point window
-    const double* fac;    // [nfac][N][FACW] banded LU factors
+    const double* fac;    // [nfac] banded LU factors of N FACW doubles (main then tail records)
     const double* hom;    // [M][K][NHOM][N] influence data (h1+, h1-, q, h2, h3, h4, P1)
     const double* ainv;   // [M][2K-1][16][2] inverse influence matrices (complex)
     const double* green;  // [N] flux Green's function: H_0 u_G = 1, u_G(1) = 0
@@ -102,7 +108,7 @@ struct FactorArgs {
     const double* d1;
     const double* d2;
     const int* s0;
-    double* fac;        // [MU K + M K][N][FACW]: H_{|mu|,|k|} then L_{m,|k|}
+    double* fac;        // [MU K + M K] factors of N FACW doubles: H_{|mu|,|k|} then L_{m,|k|}
     double* hom;        // [M][K][NHOM][N]
     double* ainv;       // [M][2K-1][16][2]
     double* green;      // [N]

@@ -179,27 +179,41 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
 
 // Factors moving from global memory to LDS in two halves: load() issues all
 // 16-byte loads of this thread into registers (branch-free, clamped
-// indices), store() writes them to LDS slots of stride FS doubles and zeroes
-// rows N..NB-1.  Factor f has global index base + f * stride.
-template <int NB, int NFMAX, int NTHR>
+// indices), store() writes them into FACW-double row records at stride FS
+// doubles and zeroes rows N..NB-1.  Factor f has global index base + f *
+// stride.  A factor's main records (5 double2 per row) are copied whole, its
+// tail records (2 double2 per row) from row NW on: the narrow rows before NW
+// never read their tail, whose LDS slots are left as they are.
+template <int NB, int NFMAX, int NTHR, int NW>
 struct FactorStage {
-    static constexpr int MAXIT = (NFMAX * NB * FACW / 2 + NTHR - 1) / NTHR;
+    static constexpr int M2 = FMAIN / 2, T2 = FTAIL / 2, R2 = FACW / 2;
+    static constexpr int MAXIT = (NFMAX * (NB * M2 + (NB - NW) * T2) + NTHR - 1) / NTHR;
     double2 tmp[MAXIT];
+    // double2 r of a factor's copied part: offset in its HBM block, offset in LDS
+    __device__ __forceinline__ static int src(int r, int N) { return r < N * M2 ? r : r + NW * T2; }
+    __device__ __forceinline__ static int dst(int r, int N) {
+        if (r < N * M2) {
+            const int i = r / M2, s = r % M2;
+            return i * R2 + (s < 2 ? s : s + T2);  // L[1..4] -> slots 0, 1; U, 1/U -> 4, 5, 6
+        }
+        const int t = r - N * M2;
+        return (NW + t / T2) * R2 + 2 + t % T2;  // L[5..8] -> slots 2, 3
+    }
     __device__ __forceinline__ void load(const double* fac, size_t base, size_t stride, int nf, int N, int t) {
-        const int per = N * FACW / 2, total = nf * per;
+        const int per = N * M2 + (N - NW) * T2, total = nf * per;
         const size_t FSZ = (size_t)N * FACW;
 #pragma unroll
         for (int it = 0; it < MAXIT; ++it) {
             const int e = min(t + it * NTHR, total - 1);
-            tmp[it] = reinterpret_cast<const double2*>(fac + (base + (e / per) * stride) * FSZ)[e % per];
+            tmp[it] = reinterpret_cast<const double2*>(fac + (base + (e / per) * stride) * FSZ)[src(e % per, N)];
         }
     }
     __device__ __forceinline__ void store(double* sF, int FS, int nf, int N, int t) const {
-        const int per = N * FACW / 2, total = nf * per;
+        const int per = N * M2 + (N - NW) * T2, total = nf * per;
 #pragma unroll
         for (int it = 0; it < MAXIT; ++it) {
             const int e = t + it * NTHR;
-            if (e < total) reinterpret_cast<double2*>(sF + (e / per) * FS)[e % per] = tmp[it];
+            if (e < total) reinterpret_cast<double2*>(sF + (e / per) * FS)[dst(e % per, N)] = tmp[it];
         }
         const int zper = (NB - N) * FACW;
         for (int e = t; e < nf * zper; e += NTHR) sF[(e / zper) * FS + N * FACW + e % zper] = 0.0;
@@ -249,7 +263,6 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const int tid = threadIdx.x, n = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
     const size_t S = (size_t)a.M * nk * N;
-    const size_t FSZ = (size_t)N * FACW;
     const int mu_lo = max(mp * m0 - 1, 0);
     const int nr = n < N ? n : N - 1;  // lanes past the last row read a valid row
     RowW W1;  // first-derivative weights of this lane's row, both parities
@@ -335,7 +348,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
 
     // ---- pressure-Poisson right-hand side div R (P(1) = 0); stage L factors
     {  // pressure factors L_{m,|k|}, m0 <= m < m0 + GM (the u^n staging area is free now)
-        FactorStage<NB, 4, 256> ppe;
+        FactorStage<NB, 4, 256, NW> ppe;
         ppe.load(t.fac, (size_t)a.MU * K + (size_t)m0 * K + kabs, K, nfp, N, tid);
         ppe.store(sF, FS, nfp, N, tid);
     }
@@ -365,7 +378,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
 
     // ---- R -= grad P; (0,0): u_r = 0, real R_theta and R_z; stage H factors
     {  // Helmholtz factors H_{mu,|k|}, mu_lo <= mu <= mu_hi
-        FactorStage<NB, NFH, 256> helm;
+        FactorStage<NB, NFH, 256, NW> helm;
         helm.load(t.fac, (size_t)mu_lo * K + kabs, K, nfh, N, tid);
         helm.store(sF, FS, nfh, N, tid);
     }
