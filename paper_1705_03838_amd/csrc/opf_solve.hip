@@ -641,6 +641,9 @@ hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int me
     if (a.N <= 32) {
         if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 32) }
         else { OPF_SOLVE_NW(double, 32) }
+    } else if (a.N <= 48) {
+        if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 48) }
+        else { OPF_SOLVE_NW(double, 48) }
     } else {
         if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 64) }
         else { OPF_SOLVE_NW(double, 64) }
