@@ -332,7 +332,8 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
     cpx<T>* buf = tw2 + RM * RM;                         // [3][TZ][LS]
-    const int N = a.N, M = a.M, L3K = 3 * a.K;
+    constexpr int M = L / 3;  // the theta line is the 3/2-padded length 3M
+    const int N = a.N, L3K = 3 * a.K;
     const int nzt = (L3K + TZ - 1) / TZ;
     const int tile = xcd_group_tile<XG>(blockIdx.x, N * nzt);
     const int n = tile / nzt;
@@ -471,7 +472,8 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
     cpx<T>* buf = tw + L;                                // [2][TZ][LS]
-    const int N = a.N, M = a.M, L3K = 3 * a.K;
+    constexpr int M = L / 3;  // the theta line is the 3/2-padded length 3M
+    const int N = a.N, L3K = 3 * a.K;
     const int nzt = (L3K + TZ - 1) / TZ;
     const int n = blockIdx.x / nzt;
     const int z0 = (blockIdx.x % nzt) * TZ;
