@@ -205,7 +205,8 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
     cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
-    const int N = a.N, M = a.M, K = a.K, nk = a.nk;
+    constexpr int K = L / 3, nk = 2 * K - 1;  // the z line is the 3/2-padded length 3K
+    const int N = a.N, M = a.M;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
     const int m = (blockIdx.x / ntile) % M;
@@ -574,7 +575,8 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
     cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
-    const int N = a.N, M = a.M, K = a.K, nk = a.nk;
+    constexpr int K = L / 3, nk = 2 * K - 1;  // the z line is the 3/2-padded length 3K
+    const int N = a.N, M = a.M;
     const int ntile = (N + TILE - 1) / TILE;
     const int tile = blockIdx.x % ntile;
     const int m = (blockIdx.x / ntile) % M;
