@@ -258,8 +258,13 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const int N = a.N, K = a.K, nk = a.nk, mp = a.mp;
     const int GM = a.gm;
     const int nblk = (a.M + GM - 1) / GM;
-    const int kabs = blockIdx.x / nblk;
-    const int m0 = (blockIdx.x % nblk) * GM;
+    // Consecutive block indices go round-robin to the 8 XCDs; each XCD takes
+    // a contiguous range of tiles instead, so the m-blocks of one |k|, which
+    // share Helmholtz factors, meet in its L2.
+    const int ntiles = (int)gridDim.x;
+    const int tile = ntiles % 8 == 0 ? (blockIdx.x % 8) * (ntiles / 8) + blockIdx.x / 8 : (int)blockIdx.x;
+    const int kabs = tile / nblk;
+    const int m0 = (tile % nblk) * GM;
     const int tid = threadIdx.x, n = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
     const size_t S = (size_t)a.M * nk * N;
