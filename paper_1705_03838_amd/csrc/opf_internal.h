@@ -79,7 +79,6 @@ struct SolveArgs {
     void* w_out;        // vorticity of the output (nonlinear storage type, nullable)
     double* p_out;      // pressure head [M][nk][N] complex128 (nullable)
     double* beta_out;   // flux correction beta (device scalar)
-    double* g_out;      // [M*K] largest |g| after correction, per workgroup (nullable)
     const double* wall; // wall velocity [3][M][nk] complex (r, theta, z) at r = 1, or null (no slip)
     Tables t;
 };
