@@ -133,3 +133,109 @@ def newton(o, x, T, s, tol=1e-8, m=40, max_newton=20, gmres_tol=1e-3):
         x, F = xn, Fn
         hist.append(norm(o, F) / norm(o, x))
     return x, hist
+
+
+# ---- travelling waves with a free phase speed ---------------------------
+# Section 3.2: a travelling wave is an equilibrium in a frame moving with its
+# phase speed c_w, which is not known in advance.  The unknowns become
+# X = (x, c_w) with the residual F(x, c_w) = shift(Phi_T(x), -c_w T) - x and
+# one more equation, the phase condition <d_z x, dx> = 0 on the update (it
+# removes the axial-shift direction, along which every shifted copy of a
+# travelling wave is another one).  d_z is the spectral axial derivative
+# i alpha k.  Extended vectors are flat complex arrays: the field, then
+# c_w; their inner product is the energy inner product plus the product of
+# the speed entries.  The derivative of F in c_w is T d_z shift(Phi_T(x),
+# -c_w T), which the forward difference reproduces.  Where ||d_z x|| /
+# ||x|| < freeze (laminar flow is a travelling wave of every speed, so the
+# speed direction is null there) the step keeps c_w and solves for x alone.
+
+def ddz(o, u):
+    """Axial derivative d_z of a spectral field: i alpha k A_k."""
+    k = np.arange(-(o.K - 1), o.K)
+    return 1j * o.p.alpha * k[None, None, :, None] * u
+
+
+class TravellingWave:
+    """Residual, inner product and Jacobian product of the free-speed
+    travelling-wave system for a time-T map `phi` (by default T/dt steps
+    of the oracle's predictor-corrector)."""
+
+    def __init__(self, o, T, phi=None, freeze=1e-6, eps_rel=1e-7):
+        self.o, self.T = o, T
+        n = int(round(T / o.p.dt))
+        self.phi = phi if phi is not None else (lambda x: o.run(x, n))
+        self.freeze, self.eps_rel = freeze, eps_rel
+        self.shape = (3, o.M, o.nk, o.N)
+        self.size = int(np.prod(self.shape))
+
+    def pack(self, x, c):
+        return np.concatenate([np.ravel(x), np.array([c], dtype=complex)])
+
+    def unpack(self, X):
+        return X[:self.size].reshape(self.shape), float(X[-1].real)
+
+    def dot(self, A, B):
+        a, ca = self.unpack(A)
+        b, cb = self.unpack(B)
+        return inner(self.o, a, b) + ca * cb
+
+    def residual(self, X):
+        x, c = self.unpack(X)
+        return self.pack(shift(self.o, self.phi(x), -c * self.T) - x, 0.0)
+
+    def speed_active(self, X):
+        """False where the state is (nearly) invariant under axial shifts."""
+        x, _ = self.unpack(X)
+        return norm(self.o, ddz(self.o, x)) > self.freeze * norm(self.o, x)
+
+    def jvp(self, X, F0, V, active):
+        """Forward difference of the residual in (x, c_w) plus the phase
+        row <d_z x, v>; with active False the speed is held fixed."""
+        V = V.copy()
+        if not active:
+            V[-1] = 0.0
+        nv = np.sqrt(max(self.dot(V, V), 0.0))
+        if nv == 0.0:
+            return np.zeros_like(X)
+        eps = self.eps_rel * max(np.sqrt(self.dot(X, X)), 1.0) / nv
+        out = (self.residual(X + eps * V) - F0) / eps
+        x, _ = self.unpack(X)
+        v, _ = self.unpack(V)
+        out[-1] = inner(self.o, ddz(self.o, x), v) if active else 0.0
+        return out
+
+
+def newton_tw(o, x, T, c, tol=1e-8, m=40, max_newton=20, gmres_tol=1e-3, phi=None, freeze=1e-6):
+    """Newton iteration for a travelling wave with a free phase speed:
+    GMRES(m) on the extended system [J_x, dF/dc; <d_z x, .>, 0] (dx, dc)
+    = (-F, 0) and a backtracking line search on ||F||, as newton() does for a
+    fixed shift.  Returns (x, c_w, history of ||F|| / ||x||, info) with
+    info['frozen'] the Newton steps taken at fixed speed."""
+    tw = TravellingWave(o, T, phi, freeze)
+    X = tw.pack(x, c)
+    F = tw.residual(X)
+
+    def fnorm(Fv):
+        return np.sqrt(max(tw.dot(Fv, Fv), 0.0))
+
+    hist = [fnorm(F) / norm(o, tw.unpack(X)[0])]
+    info = {"frozen": 0, "steps": []}
+    for _ in range(max_newton):
+        if hist[-1] <= tol:
+            break
+        active = tw.speed_active(X)
+        info["frozen"] += 0 if active else 1
+        F0 = F
+        dX, _, _ = gmres(lambda v: tw.jvp(X, F0, v, active), -F, tw.dot, m=m, tol=gmres_tol)
+        info["steps"].append(dX)
+        lam = 1.0
+        while True:
+            Xn = X + lam * dX
+            Fn = tw.residual(Xn)
+            if fnorm(Fn) < fnorm(F) or lam < 1e-3:
+                break
+            lam *= 0.5
+        X, F = Xn, Fn
+        hist.append(fnorm(F) / norm(o, tw.unpack(X)[0]))
+    xs, cs = tw.unpack(X)
+    return xs, cs, hist, info
