@@ -84,7 +84,9 @@ def traffic_for(kernel, precision):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(w, precision, steps, warmup, profile_steps):
+def run_gpu(w, precision, steps, warmup, profile_steps, repeats=5):
+    """Median over `repeats` timed runs of `steps` graph-launched steps (after
+    `warmup` untimed ones), each bracketed by device synchronisation."""
     import torch
 
     import paper_1705_03838_amd as opf
@@ -95,15 +97,17 @@ def run_gpu(w, precision, steps, warmup, profile_steps):
     u0 = workload_state(w, s.nodes())
     s.set_state(torch.from_numpy(u0))
     s.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) / steps)
     prof = s.profile_steps(profile_steps)
     diag = s.diagnostics(check=False)
     s.close()
-    return (t1 - t0) / steps, prof, diag
+    return float(np.median(times)), prof, diag, times
 
 
 def run_adaptive(w, steps, warmup, courant=0.5, check_every=10, dt_max=0.01):
@@ -310,26 +314,70 @@ def run_ensemble(steps=500, warmup=5):
             "finite_after_run": finite, "autotune": tune}
 
 
-def cpu_baseline(w, nsteps=2):
+def host_cpu():
+    """Host CPU model and counts (the oracle's hardware)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(w, nsteps=10):
     """The oracle as it stands, on this host: one untimed step to build its
-    caches, then nsteps timed steps of the same workload."""
+    caches, then nsteps timed steps of the same workload from the same
+    initial state.  The oracle's states after 0 and nsteps steps also give
+    the accuracy of both GPU forms after nsteps steps, run on the oracle's
+    radial nodes."""
+    import torch
     from threadpoolctl import threadpool_info
 
-    from inputs import workload_state
+    import paper_1705_03838_amd as opf
+    from inputs import laminar_state, workload_state
     from oracle import Oracle, Params
 
     o = Oracle(Params(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"],
                       dt=w["dt"]))
-    u = workload_state(w, o.g.r)
-    u = o.step(u)
+    r = o.g.r
+    u0 = workload_state(w, r)
+    o.step(u0)
     t0 = time.perf_counter()
+    u = u0
     for _ in range(nsteps):
         u = o.step(u)
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": nsteps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nsteps} FP64 predictor-corrector steps of the same workload after one "
-                      f"untimed step; {dt:.1f} s (numpy + LAPACK dense solves)"}
+    base = {"value": nsteps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsteps} FP64 predictor-corrector steps of the same workload from its initial "
+                      f"state after one untimed step; {dt:.1f} s (numpy FFTs + LAPACK dense solves, "
+                      f"{threads} BLAS threads)", **host_cpu()}
+    lam = laminar_state(w["N"], w["M"], w["K"], r)
+    acc = {}
+    for name, prec in (("fp64", opf.OPF_FP64), ("mixed", opf.OPF_MIXED)):
+        s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"],
+                       dt=w["dt"], precision=prec, r_nodes=r)
+        s.set_state(torch.from_numpy(u0))
+        s.step(nsteps)
+        got = s.get_state().cpu().numpy()
+        d = s.diagnostics(check=False)
+        s.close()
+        dref = o.diagnostics(u)
+        e = o.energy_norm(got - u)
+        acc[name] = {"velocity_rel": float(f"{e / o.energy_norm(u):.3e}"),
+                     "velocity_rel_perturbation": float(f"{e / o.energy_norm(u - lam):.3e}"),
+                     "energy_rel": float(f"{abs(d['E'] - dref['E']) / dref['E']:.3e}"),
+                     "wall_shear_rel": float(f"{abs(d['tau_w'] - dref['tau_w']) / dref['tau_w']:.3e}"),
+                     "max_coeff_rel": float(f"{np.max(np.abs(got - u)) / np.max(np.abs(u)):.3e}")}
+    return base, {"steps": nsteps, "against": "FP64 oracle from the same initial state", **acc}
 
 
 def progress(msg):
@@ -375,8 +423,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ms64, prof64, diag64 = run_gpu(w, opf.OPF_FP64, args.steps, args.warmup, args.profile_steps)
-    progress(f"fp64 {args.workload}: {ms64 * 1e3:.4f} ms/step")
+    ms64, prof64, diag64, reps64 = run_gpu(w, opf.OPF_FP64, args.steps, args.warmup, args.profile_steps)
+    progress(f"fp64 {args.workload}: {ms64 * 1e3:.4f} ms/step (median of {len(reps64)})")
 
     def roofline(prof, mixed, prec):
         """Dominant kernel by device time per step.  The predictor and
@@ -408,6 +456,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms64 * 1e3, 4),
+        "repeats_ms_per_step": [round(t * 1e3, 4) for t in reps64],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -423,9 +472,10 @@ def main():
         "diagnostics_after_run": {k: diag64[k] for k in ("E", "D", "tau_w", "beta", "g_norm", "div_max", "cfl")},
     }
     if not args.fp64_only:
-        ms32, prof32, _ = run_gpu(w, opf.OPF_MIXED, args.steps, args.warmup, args.profile_steps)
+        ms32, prof32, _, reps32 = run_gpu(w, opf.OPF_MIXED, args.steps, args.warmup, args.profile_steps)
         progress(f"mixed {args.workload}: {ms32 * 1e3:.4f} ms/step")
         out["mixed"] = {"steps_per_s": round(1.0 / ms32, 2), "ms_per_step": round(ms32 * 1e3, 4),
+                        "repeats_ms_per_step": [round(t * 1e3, 4) for t in reps32],
                         "speedup_vs_fp64": round(ms64 / ms32, 3),
                         "alg_GBps_per_step": round(step_bytes_compulsory(N, M, K, True) / ms32 / 1e9, 1),
                         "kernel_GBps_per_step": round(step_bytes(N, M, K, True) / ms32 / 1e9, 1),
@@ -446,8 +496,10 @@ def main():
                                             "dt=0.01, T=20, near-laminar seed 5000",
                                 **run_nk(WORKLOADS["nk"])}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
-        progress("cpu baseline done")
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(w)
+        progress(f"cpu baseline done; accuracy after {out['accuracy']['steps']} steps: "
+                 f"fp64 {out['accuracy']['fp64']['velocity_rel']:.2e}, "
+                 f"mixed {out['accuracy']['mixed']['velocity_rel']:.2e}")
     print(json.dumps(out), flush=True)
 
 

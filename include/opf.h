@@ -186,35 +186,57 @@ opf_status opf_vec_axpby(opf_ctx* ctx, double a, const void* x_dev, double b, vo
 /* Learned preconditioner network (declared below). */
 typedef struct opf_mlp opf_mlp;
 
-/* Newton-Krylov search for a travelling wave of a fixed phase shift
- * (Section 2: Newton solver for invariant solutions; Section 3.2: a
- * travelling wave is an equilibrium in a frame moving with its phase
- * speed): solves F(x) = shift(Phi_T(x), -shift) - x = 0 by Newton steps,
- * each with restarted GMRES(gmres_m) on J dx = -F (J v by the forward
- * difference (F(x + eps v) - F(x)) / eps, eps = fd_eps max(||x||,1)/||v||),
- * and a backtracking line search.  x_dev (in/out, external layout) holds the
- * guess and receives the solution; krylov_dev is caller device memory of at
- * least opf_nk_workspace_size bytes.  The context's state is overwritten.
+/* Newton-Krylov search for a travelling wave (Section 2: Newton solver for
+ * invariant solutions; Section 3.2: a travelling wave is an equilibrium in a
+ * frame moving with its phase speed c_w): solves
+ *   F(x, c_w) = shift(Phi_T(x), -c_w T) - x = 0
+ * by Newton steps, each with restarted GMRES(gmres_m) on the linearised
+ * system (J v by the forward difference (F(X + eps V) - F(X)) / eps,
+ * eps = fd_eps max(||X||, 1) / ||V||), and a backtracking line search on
+ * ||F||.  x_dev (in/out, external layout) holds the guess and receives the
+ * solution; *cw_inout (host) is the phase speed, in and out.  krylov_dev is
+ * caller device memory of at least opf_nk_workspace_size bytes.  The
+ * context's state is overwritten.  Synchronises.
+ *
+ * free_speed = 0: c_w stays as given (shift s = c_w T fixed).
+ * free_speed != 0: c_w is an unknown too.  The unknowns are X = (x, c_w)
+ * with the phase condition <d_z x, dx> = 0 on the update as the extra
+ * equation (d_z = i alpha k; it removes the axial-shift direction, along
+ * which shifted copies of a travelling wave are travelling waves too); the
+ * inner product of extended vectors is the energy inner product plus the
+ * product of the speed entries, and ||X|| includes c_w.  Where
+ * ||d_z x|| <= speed_freeze ||x|| (default 1e-6; laminar flow is a
+ * travelling wave of every speed, so the speed direction is null there) a
+ * Newton step keeps c_w and solves for x alone (report.frozen_steps).
+ *
  * precond: NULL for plain GMRES; otherwise flexible GMRES with right
  * preconditioning (Saad 1993), z_j = P(v_j) with P = opf_precondition of
- * that network, which must have been created for this context's grid.
+ * that network (created for this context's grid; a speed entry passes
+ * unchanged), one cycle of at most gmres_m products per Newton step.  Plain
+ * GMRES is the fallback (unless no_fallback): a step whose preconditioned
+ * cycle misses gmres_tol, or whose line search does not lower ||F||, is
+ * solved again by restarted plain GMRES (report.fallbacks).
  * record_dev: NULL, or device memory for record_capacity pairs of
- * external-layout vectors; each product J z the solver forms is stored as
- * pair i = (z at vector 2i, J z at vector 2i+1) until the capacity is
- * reached (training data for the network).
+ * external-layout vectors; each product J z with a zero speed entry is
+ * stored as pair i = (z at vector 2i, J z at vector 2i+1) until the
+ * capacity is reached (training data for the network).
+ * max_jvps caps the products of one Newton step.
  *
  * hookstep != 0 replaces restarts and the line search by the Krylov
  * trust-region step of the paper's Newton solver (Section 2, after
  * Viswanath 2007): one Arnoldi cycle from v_1 = -F/||F|| (up to gmres_m
  * products, stopping at the gmres_tol least-squares residual) gives
- * J V_k = V_{k+1} Hb; dx = V_k y with y from opf_hookstep_solve for the
- * current radius Delta.  rho = (||F||^2 - ||F(x+dx)||^2) / (||F||^2 - r^2)
+ * J V_k = V_{k+1} Hb; dX = V_k y with y from opf_hookstep_solve for the
+ * current radius Delta.  rho = (||F||^2 - ||F(X+dX)||^2) / (||F||^2 - r^2)
  * (r the model residual): rho < 0.1 rejects the step and retries with
- * Delta = ||dx||/2 on the same basis (at most max_hook tries, then the
+ * Delta = ||dX||/2 on the same basis (at most max_hook tries, then the
  * search stops unconverged); an accepted step doubles Delta (up to
- * tr_delta_max) if rho > 0.75 and ||dx|| >= 0.99 Delta, and sets
- * Delta = ||dx||/2 if rho < 0.25.  Not combined with precond (returns
- * OPF_E_UNSUPPORTED). */
+ * tr_delta_max) if rho > 0.75 and ||dX|| >= 0.99 Delta, and sets
+ * Delta = ||dX||/2 if rho < 0.25.  Not combined with precond (returns
+ * OPF_E_UNSUPPORTED).
+ * Errors: OPF_E_INVALID for null pointers, gmres_m or max_jvps < 1, a
+ * non-finite *cw_inout or a negative record capacity; OPF_E_NOMEM for a
+ * short krylov_dev; OPF_E_NUMERIC for a non-finite preconditioned vector. */
 typedef struct {
     int32_t gmres_m;     /* Krylov dimension per restart, e.g. 40             */
     int32_t max_newton;  /* Newton iterations                                  */
@@ -230,6 +252,9 @@ typedef struct {
                               length of the first unconstrained step        */
     double tr_delta_max;   /* largest radius; <= 0: unbounded                */
     int32_t max_hook;      /* tries per Newton step; <= 0: 12                */
+    int32_t free_speed;    /* 0: c_w fixed; 1: c_w solved for (phase condition) */
+    int32_t no_fallback;   /* 1: no plain-GMRES fallback for precond           */
+    double speed_freeze;   /* ||d_z x|| / ||x|| below which c_w is held; <= 0: 1e-6 */
 } opf_nk_opts;
 
 typedef struct {
@@ -242,6 +267,9 @@ typedef struct {
     int32_t hook_trials;           /* hookstep candidates evaluated          */
     int32_t stalled;               /* hookstep: max_hook tries all rejected  */
     double tr_delta;               /* hookstep: trust radius on return       */
+    double speed;                  /* c_w on return (= *cw_inout)            */
+    int32_t frozen_steps;          /* free_speed: steps taken at fixed c_w   */
+    int32_t fallbacks;             /* precond: steps solved again plainly    */
 } opf_nk_report;
 
 /* The hookstep subproblem (host only, no device): y minimising
@@ -254,11 +282,11 @@ typedef struct {
 opf_status opf_hookstep_solve(const double* hb_host, int32_t k, double beta, double delta,
                               double* y_host, double* mu_host, double* resid_host);
 
-/* Device bytes for opf_nk_solve: (gmres_m + 5) vectors, plus gmres_m more
+/* Device bytes for opf_nk_solve: (gmres_m + 6) vectors, plus gmres_m more
  * (the preconditioned directions) when preconditioned != 0. */
 opf_status opf_nk_workspace_size(const opf_ctx* ctx, int32_t gmres_m, int32_t preconditioned,
                                  size_t* bytes);
-opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double shift, const opf_nk_opts* opts,
+opf_status opf_nk_solve(opf_ctx* ctx, void* x_dev, double T, double* cw_inout, const opf_nk_opts* opts,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* report);
 
 /* ---- Relative periodic orbits by multiple shooting -------------------------

@@ -86,7 +86,8 @@ class opf_nk_opts(ctypes.Structure):
                 ("precond", ctypes.c_void_p), ("record_dev", ctypes.c_void_p),
                 ("record_capacity", ctypes.c_int32), ("hookstep", ctypes.c_int32),
                 ("tr_delta0", ctypes.c_double), ("tr_delta_max", ctypes.c_double),
-                ("max_hook", ctypes.c_int32)]
+                ("max_hook", ctypes.c_int32), ("free_speed", ctypes.c_int32),
+                ("no_fallback", ctypes.c_int32), ("speed_freeze", ctypes.c_double)]
 
 
 class opf_nk_report(ctypes.Structure):
@@ -95,7 +96,9 @@ class opf_nk_report(ctypes.Structure):
                 ("residual", ctypes.c_double), ("residual_history", ctypes.c_double * 32),
                 ("recorded", ctypes.c_int32), ("precond_applies", ctypes.c_int32),
                 ("residual_evals", ctypes.c_int32), ("hook_trials", ctypes.c_int32),
-                ("stalled", ctypes.c_int32), ("tr_delta", ctypes.c_double)]
+                ("stalled", ctypes.c_int32), ("tr_delta", ctypes.c_double),
+                ("speed", ctypes.c_double), ("frozen_steps", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int32)]
 
 
 class opf_mlp_config(ctypes.Structure):
@@ -141,7 +144,7 @@ def load_library(path=LIB_PATH):
         "opf_vec_dot": ([vp, vp, vp, P(ctypes.c_double)], i32),
         "opf_vec_axpby": ([vp, dbl, vp, dbl, vp], i32),
         "opf_nk_workspace_size": ([vp, i32, i32, P(ctypes.c_size_t)], i32),
-        "opf_nk_solve": ([vp, vp, dbl, dbl, P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
+        "opf_nk_solve": ([vp, vp, dbl, P(dbl), P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
         "opf_probe_pairs": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp, vp], i32),
         "opf_mlp_default_config": ([P(opf_mlp_config)], i32),
@@ -419,11 +422,13 @@ class Solver:
                                          ctypes.c_void_p(b.data_ptr()), ctypes.byref(out)))
         return out.value
 
-    def nk_solve(self, x, T, shift, gmres_m=40, max_newton=20, max_jvps=400, tol=1e-8,
+    def nk_solve(self, x, T, speed=0.0, free_speed=False, gmres_m=40, max_newton=20, max_jvps=400, tol=1e-8,
                  gmres_tol=1e-3, fd_eps=1e-7, precond=None, record=None, hookstep=False, tr_delta0=0.0,
-                 tr_delta_max=0.0, max_hook=12):
+                 tr_delta_max=0.0, max_hook=12, fallback=True, speed_freeze=0.0):
         """Newton-Krylov travelling-wave search; returns (solution, report dict).
-        precond: an Mlp (flexible GMRES with it as right preconditioner) or None.
+        speed: the phase speed c_w (shift c_w T), solved for when free_speed.
+        precond: an Mlp (flexible GMRES with it as right preconditioner) or None;
+        plain GMRES is its fallback unless fallback=False.
         record: None, or a complex128 device tensor [n, 2, 3, M, 2K-1, N] that
         receives the pairs (z, J z) of the products the solver forms.
         hookstep: the Krylov trust-region step instead of restarted GMRES and
@@ -441,9 +446,11 @@ class Solver:
         o = opf_nk_opts(int(gmres_m), int(max_newton), int(max_jvps), float(tol), float(gmres_tol),
                         float(fd_eps), precond.handle if precond is not None else None,
                         record.data_ptr() if record is not None else None, int(cap), int(bool(hookstep)),
-                        float(tr_delta0), float(tr_delta_max), int(max_hook))
+                        float(tr_delta0), float(tr_delta_max), int(max_hook), int(bool(free_speed)),
+                        int(not fallback), float(speed_freeze))
         rep = opf_nk_report()
-        self._check(self.lib.opf_nk_solve(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), float(shift),
+        cw = ctypes.c_double(float(speed))
+        self._check(self.lib.opf_nk_solve(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T), ctypes.byref(cw),
                                           ctypes.byref(o), ctypes.c_void_p(kry.data_ptr()),
                                           ctypes.c_size_t(nbytes.value), ctypes.byref(rep)))
         n = rep.newton_iterations
@@ -452,7 +459,8 @@ class Solver:
                    "history": [rep.residual_history[i] for i in range(min(n + 1, 32))],
                    "recorded": rep.recorded, "precond_applies": rep.precond_applies,
                    "residual_evals": rep.residual_evals, "hook_trials": rep.hook_trials,
-                   "stalled": bool(rep.stalled), "tr_delta": rep.tr_delta}
+                   "stalled": bool(rep.stalled), "tr_delta": rep.tr_delta, "speed": cw.value,
+                   "frozen_steps": rep.frozen_steps, "fallbacks": rep.fallbacks}
 
     def shoot_solve(self, xs, T, shift, steps, free_T=True, free_s=True, gmres_m=40, max_newton=20, tol=1e-8,
                     gmres_tol=1e-3, fd_eps=1e-7, tr_delta0=0.0, tr_delta_max=0.0, max_hook=12):
@@ -515,7 +523,7 @@ class Solver:
         if batch > 1:
             kw = dict(self.kw)
             if self._nodes is not None:
-                raise OpfError(OPF_E_UNSUPPORTED, "batched probes use the default radial nodes")
+                kw["r_nodes"] = self._nodes
             ens = Ensemble([kw] * int(batch), stream=self.stream)
             try:
                 ens._check(self.lib.opf_probe_pairs_ensemble(ens.ens, *args))
@@ -565,8 +573,20 @@ class Ensemble:
         import torch
         self.torch = torch
         self.lib = load_library()
+        import numpy as np
         n = len(members)
-        self.params = (opf_params * n)(*[make_params(**m) for m in members])
+        self._nodes = []  # explicit radial nodes of members that give them (kept alive)
+        plist = []
+        for m in members:
+            m = dict(m)
+            r = m.pop("r_nodes", None)
+            p = make_params(**m)
+            if r is not None:
+                r = np.ascontiguousarray(r, dtype=np.float64)
+                self._nodes.append(r)
+                p.r_nodes = r.ctypes.data
+            plist.append(p)
+        self.params = (opf_params * n)(*plist)
         nbytes = ctypes.c_size_t()
         self.ens = None
         self._check(self.lib.opf_ensemble_workspace_size(self.params, n, ctypes.byref(nbytes)))

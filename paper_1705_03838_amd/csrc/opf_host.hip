@@ -1783,13 +1783,18 @@ opf_status opf_arnoldi(opf_ctx* c, const void* x_dev, double T, double shift, co
 
 opf_status opf_nk_workspace_size(const opf_ctx* c, int32_t m, int32_t preconditioned, size_t* bytes) {
     if (!c || !bytes || m < 1) return OPF_E_INVALID;
-    *bytes = (size_t)(m + 5 + (preconditioned ? m : 0)) * 3 * field_entries(c) * 16;
+    *bytes = (size_t)(m + 6 + (preconditioned ? m : 0)) * 3 * field_entries(c) * 16;
     return OPF_OK;
 }
 
-opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const opf_nk_opts* o,
+// Newton-Krylov travelling-wave search.  Vectors of the (possibly extended)
+// system are a device field plus a host scalar, the speed part (zero when
+// the speed is fixed); their inner product is the energy inner product plus
+// the product of the speed parts.
+opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double* cw_io, const opf_nk_opts* o,
                         void* krylov_dev, size_t krylov_bytes, opf_nk_report* rep) {
-    if (!c || !x_dev || !o || !krylov_dev || !rep) return OPF_E_INVALID;
+    if (!c || !x_dev || !cw_io || !o || !krylov_dev || !rep) return OPF_E_INVALID;
+    if (!std::isfinite(*cw_io) || o->max_jvps < 1 || o->gmres_m < 1) return OPF_E_INVALID;
     const int m = o->gmres_m;
     const bool pre = o->precond != nullptr;
     size_t need = 0;
@@ -1801,24 +1806,36 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
         c->err = "the hookstep is not combined with a preconditioner";
         return OPF_E_UNSUPPORTED;
     }
+    const bool free_c = o->free_speed != 0;
+    const double freeze = o->speed_freeze > 0 ? o->speed_freeze : 1e-6;
+    const bool fallback = pre && !o->no_fallback;
     const int max_hook = o->max_hook > 0 ? o->max_hook : 12;
     const double delta_max = o->tr_delta_max > 0 ? o->tr_delta_max : INFINITY;
     double delta = o->tr_delta0;
-    const size_t vb = 3 * field_entries(c) * 16;  // bytes per vector
+    const size_t total = 3 * field_entries(c);
+    const size_t vb = total * 16;  // bytes per field
     unsigned char* base = static_cast<unsigned char*>(krylov_dev);
     auto vec = [&](int i) { return static_cast<void*>(base + (size_t)i * vb); };
     // flexible GMRES keeps the preconditioned directions z_j = P(v_j)
-    auto zvec = [&](int j) { return static_cast<void*>(base + (size_t)(m + 5 + j) * vb); };
+    auto zvec = [&](int j) { return static_cast<void*>(base + (size_t)(m + 6 + j) * vb); };
     unsigned char* rec = static_cast<unsigned char*>(o->record_dev);
-    void* F0 = vec(m + 1);   // F(x)
+    void* F0 = vec(m + 1);   // F(x, c_w)
     void* tmp = vec(m + 2);  // x + eps v, then F(x + eps v)
     void* w = vec(m + 3);    // Arnoldi vector / J v
     void* dx = vec(m + 4);   // Newton update
+    void* dzx = vec(m + 5);  // d_z x, the phase-condition vector
+    std::vector<double> sv(m + 1, 0.0), sz(m, 0.0);  // speed parts of v_j, z_j
+    double sw = 0.0, sdx = 0.0;
     double* x = static_cast<double*>(x_dev);
-    auto dot = [&](const void* a, const void* b, double* out) { return opf_vec_dot(c, a, b, out); };
-    auto nrm = [&](const void* a, double* out) {
+    double cw = *cw_io;
+    auto dot = [&](const void* a, double sa, const void* b, double sb, double* out) {
+        const opf_status st = opf_vec_dot(c, a, b, out);
+        *out += sa * sb;
+        return st;
+    };
+    auto nrm = [&](const void* a, double sa, double* out) {
         double s2 = 0.0;
-        const opf_status st = dot(a, a, &s2);
+        const opf_status st = dot(a, sa, a, sa, &s2);
         *out = std::sqrt(std::max(s2, 0.0));
         return st;
     };
@@ -1828,24 +1845,43 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
         if (st_ != OPF_OK) return st_;   \
     } while (0)
     double fn = 0.0, xn = 0.0;
-    NKCHK(opf_newton_residual(c, x, T, shift, F0, &fn));
+    NKCHK(opf_newton_residual(c, x, T, cw * T, F0, &fn));
     rep->residual_evals = 1;
-    NKCHK(nrm(x, &xn));
+    NKCHK(opf_vec_dot(c, x, x, &xn));
+    xn = std::sqrt(std::max(xn, 0.0));
     rep->residual_history[0] = fn / xn;
     rep->residual = fn / xn;
     int it = 0;
     for (; it < o->max_newton && rep->residual > o->tol; ++it) {
-        // J v = (F(x + eps v) - F(x)) / eps, written into w
-        auto jv = [&](const void* v, double vnorm) -> opf_status {
-            const double eps = o->fd_eps * std::max(xn, 1.0) / vnorm;
+        const int jv0 = rep->jvps;  // products at the start of this Newton step
+        // the speed is solved for only where x has axial structure
+        bool active = false;
+        if (free_c) {
+            hipLaunchKernelGGL(k_ddz, dim3((total + 255) / 256), dim3(256), 0, c->stream, x,
+                               static_cast<double*>(dzx), c->p.N, c->nk, c->p.K, total, c->p.alpha);
+            HIPCHK(c, hipGetLastError());
+            double dn = 0.0;
+            NKCHK(nrm(dzx, 0.0, &dn));
+            active = dn > freeze * xn;
+            if (!active) rep->frozen_steps += 1;
+        }
+        const double Xn = free_c ? std::sqrt(xn * xn + cw * cw) : xn;
+        // J (v, s) = (F(x + eps v, c_w + eps s) - F(x, c_w)) / eps, plus the
+        // phase row <d_z x, v> as its speed part; into (w, sw)
+        auto jv = [&](const void* v, double& s, double vnorm) -> opf_status {
+            if (!active) s = 0.0;
+            const double eps = o->fd_eps * std::max(Xn, 1.0) / vnorm;
             NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, tmp));
             NKCHK(opf_vec_axpby(c, eps, v, 1.0, tmp));
             HIPCHK(c, hipMemcpyAsync(w, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
-            NKCHK(opf_newton_residual(c, w, T, shift, tmp, nullptr));
+            NKCHK(opf_newton_residual(c, w, T, (cw + eps * s) * T, tmp, nullptr));
             NKCHK(opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, tmp));
             HIPCHK(c, hipMemcpyAsync(w, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
+            sw = 0.0;
+            if (active) NKCHK(opf_vec_dot(c, dzx, v, &sw));
             rep->jvps += 1;
-            if (rec && rep->recorded < o->record_capacity) {
+            // (z, J_x z) training pairs: products that move the state only
+            if (rec && s == 0.0 && rep->recorded < o->record_capacity) {
                 unsigned char* slot = rec + (size_t)rep->recorded * 2 * vb;
                 HIPCHK(c, hipMemcpyAsync(slot, v, vb, hipMemcpyDeviceToDevice, c->stream));
                 HIPCHK(c, hipMemcpyAsync(slot + vb, w, vb, hipMemcpyDeviceToDevice, c->stream));
@@ -1853,22 +1889,29 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
             }
             return OPF_OK;
         };
+        // (w, sw) = a (v, s) + b (w, sw)
+        auto axpby_w = [&](double a, const void* v, double s) -> opf_status {
+            NKCHK(opf_vec_axpby(c, a, v, 1.0, w));
+            sw += a * s;
+            return OPF_OK;
+        };
         if (hook) {
             // one Arnoldi cycle from v_1 = -F / ||F||; Hr keeps the raw
             // Hessenberg matrix, Hw its Givens-rotated copy for the estimate
             NKCHK(opf_vec_axpby(c, -1.0 / fn, F0, 0.0, vec(0)));
+            sv[0] = 0.0;
             std::vector<double> Hr((size_t)(m + 1) * m, 0.0), Hw((size_t)(m + 1) * m, 0.0);
             std::vector<double> cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
             g[0] = fn;
             int k = 0;
             for (int j = 0; j < m; ++j) {
-                NKCHK(jv(vec(j), 1.0));
+                NKCHK(jv(vec(j), sv[j], 1.0));
                 for (int i = 0; i <= j; ++i) {
-                    NKCHK(dot(w, vec(i), &Hr[(size_t)i * m + j]));
-                    NKCHK(opf_vec_axpby(c, -Hr[(size_t)i * m + j], vec(i), 1.0, w));
+                    NKCHK(dot(w, sw, vec(i), sv[i], &Hr[(size_t)i * m + j]));
+                    NKCHK(axpby_w(-Hr[(size_t)i * m + j], vec(i), sv[i]));
                 }
                 double hn = 0.0;
-                NKCHK(nrm(w, &hn));
+                NKCHK(nrm(w, sw, &hn));
                 Hr[(size_t)(j + 1) * m + j] = hn;
                 for (int i = 0; i <= j + 1; ++i) Hw[(size_t)i * m + j] = Hr[(size_t)i * m + j];
                 for (int i = 0; i < j; ++i) {
@@ -1883,8 +1926,9 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
                 g[j] = cs[j] * g[j];
                 k = j + 1;
                 rep->gmres_iterations += 1;
-                if (std::fabs(g[k]) <= o->gmres_tol * fn || hn == 0.0 || rep->jvps >= o->max_jvps) break;
+                if (std::fabs(g[k]) <= o->gmres_tol * fn || hn == 0.0 || rep->jvps - jv0 >= o->max_jvps) break;
                 NKCHK(opf_vec_axpby(c, 1.0 / hn, w, 0.0, vec(j + 1)));
+                sv[j + 1] = sw / hn;
             }
             std::vector<double> hb((size_t)(k + 1) * k), y(k);
             for (int i = 0; i <= k; ++i)
@@ -1897,15 +1941,19 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
                 delta = std::sqrt(l2);
             }
             bool accepted = false;
-            double fnew = 0.0;
+            double fnew = 0.0, cnew = cw;
             for (int trial = 0; trial < max_hook; ++trial) {
                 NKCHK(opf_hookstep_solve(hb.data(), k, fn, delta, y.data(), &mu, &r));
                 double dn2 = 0.0;
                 for (double v : y) dn2 += v * v;
                 const double dn = std::sqrt(dn2);
                 NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
-                for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, w));
-                NKCHK(opf_newton_residual(c, w, T, shift, tmp, &fnew));
+                cnew = cw;
+                for (int i = 0; i < k; ++i) {
+                    NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, w));
+                    cnew += y[i] * sv[i];
+                }
+                NKCHK(opf_newton_residual(c, w, T, cnew * T, tmp, &fnew));
                 rep->residual_evals += 1;
                 rep->hook_trials += 1;
                 const double den = fn * fn - r * r;
@@ -1924,101 +1972,154 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double shift, const o
                 break;
             }
             NKCHK(opf_vec_axpby(c, 1.0, w, 0.0, x));
+            cw = cnew;
             HIPCHK(c, hipMemcpyAsync(F0, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
             fn = fnew;
-            NKCHK(nrm(x, &xn));
+            NKCHK(opf_vec_dot(c, x, x, &xn));
+            xn = std::sqrt(std::max(xn, 0.0));
             rep->residual = fn / xn;
             if (it + 1 < 32) rep->residual_history[it + 1] = rep->residual;
             continue;
         }
-        // GMRES(m) for J dx = -F0, x0 = 0, one cycle per restart
-        NKCHK(opf_vec_axpby(c, 0.0, F0, 0.0, dx));
-        double bn = fn;
-        int restarts = 0;
-        while (true) {
-            // r = -F0 - J dx
-            double beta = 0.0;
-            if (restarts == 0) {
-                NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
-            } else {
-                double dxn = 0.0;
-                NKCHK(nrm(dx, &dxn));
-                NKCHK(jv(dx, dxn));
-                NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
-                NKCHK(opf_vec_axpby(c, -1.0, w, 1.0, vec(0)));
-            }
-            NKCHK(nrm(vec(0), &beta));
-            if (beta <= o->gmres_tol * bn || rep->jvps >= o->max_jvps) break;
-            NKCHK(opf_vec_axpby(c, 0.0, vec(0), 1.0 / beta, vec(0)));
-            std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
-            auto Hh = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
-            g[0] = beta;
-            int k = 0;
-            for (int j = 0; j < m; ++j) {
-                if (pre) {
-                    double zn = 0.0;
-                    NKCHK(opf_precondition(c, o->precond, vec(j), zvec(j)));
-                    rep->precond_applies += 1;
-                    NKCHK(nrm(zvec(j), &zn));
-                    if (!(zn > 0.0)) return OPF_E_NUMERIC;
-                    NKCHK(jv(zvec(j), zn));
+        // GMRES(m) for J (dx, sdx) = (-F0, 0) from zero, restarted; with the
+        // preconditioner, one flexible cycle of at most m products.  Returns
+        // whether the relative tolerance was reached.
+        auto gmres = [&](bool use_pre, bool& reached) -> opf_status {
+            NKCHK(opf_vec_axpby(c, 0.0, F0, 0.0, dx));
+            sdx = 0.0;
+            reached = false;
+            const double bn = fn;
+            const int start = rep->jvps;
+            const int left = o->max_jvps - (start - jv0);  // this Newton step's remaining products
+            const int cap = use_pre ? std::min(left, m) : left;
+            int restarts = 0;
+            while (true) {
+                // r = -F0 - J dx
+                double beta = 0.0;
+                sv[0] = 0.0;
+                if (restarts == 0) {
+                    NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
                 } else {
-                    NKCHK(jv(vec(j), 1.0));
+                    double dxn = 0.0;
+                    NKCHK(nrm(dx, sdx, &dxn));
+                    NKCHK(jv(dx, sdx, dxn));
+                    NKCHK(opf_vec_axpby(c, -1.0, F0, 0.0, vec(0)));
+                    NKCHK(opf_vec_axpby(c, -1.0, w, 1.0, vec(0)));
+                    sv[0] = -sw;
                 }
-                for (int i = 0; i <= j; ++i) {
-                    NKCHK(dot(w, vec(i), &Hh(i, j)));
-                    NKCHK(opf_vec_axpby(c, -Hh(i, j), vec(i), 1.0, w));
+                NKCHK(nrm(vec(0), sv[0], &beta));
+                if (beta <= o->gmres_tol * bn) {
+                    reached = true;
+                    break;
                 }
-                double hn = 0.0;
-                NKCHK(nrm(w, &hn));
-                Hh(j + 1, j) = hn;
-                for (int i = 0; i < j; ++i) {
-                    const double t = cs[i] * Hh(i, j) + sn[i] * Hh(i + 1, j);
-                    Hh(i + 1, j) = -sn[i] * Hh(i, j) + cs[i] * Hh(i + 1, j);
-                    Hh(i, j) = t;
+                if (rep->jvps - start >= cap) break;
+                NKCHK(opf_vec_axpby(c, 0.0, vec(0), 1.0 / beta, vec(0)));
+                sv[0] /= beta;
+                std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+                auto Hh = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+                g[0] = beta;
+                int k = 0;
+                for (int j = 0; j < m; ++j) {
+                    if (use_pre) {
+                        double zn = 0.0;
+                        NKCHK(opf_precondition(c, o->precond, vec(j), zvec(j)));
+                        sz[j] = sv[j];  // the speed part passes unchanged
+                        rep->precond_applies += 1;
+                        NKCHK(nrm(zvec(j), sz[j], &zn));
+                        if (!(zn > 0.0) || !std::isfinite(zn)) return OPF_E_NUMERIC;
+                        NKCHK(jv(zvec(j), sz[j], zn));
+                    } else {
+                        NKCHK(jv(vec(j), sv[j], 1.0));
+                    }
+                    for (int i = 0; i <= j; ++i) {
+                        NKCHK(dot(w, sw, vec(i), sv[i], &Hh(i, j)));
+                        NKCHK(axpby_w(-Hh(i, j), vec(i), sv[i]));
+                    }
+                    double hn = 0.0;
+                    NKCHK(nrm(w, sw, &hn));
+                    Hh(j + 1, j) = hn;
+                    for (int i = 0; i < j; ++i) {
+                        const double t = cs[i] * Hh(i, j) + sn[i] * Hh(i + 1, j);
+                        Hh(i + 1, j) = -sn[i] * Hh(i, j) + cs[i] * Hh(i + 1, j);
+                        Hh(i, j) = t;
+                    }
+                    const double d = std::hypot(Hh(j, j), Hh(j + 1, j));
+                    cs[j] = d == 0.0 ? 1.0 : Hh(j, j) / d;
+                    sn[j] = d == 0.0 ? 0.0 : Hh(j + 1, j) / d;
+                    Hh(j, j) = d;
+                    Hh(j + 1, j) = 0.0;
+                    g[j + 1] = -sn[j] * g[j];
+                    g[j] = cs[j] * g[j];
+                    k = j + 1;
+                    rep->gmres_iterations += 1;
+                    if (std::fabs(g[k]) <= o->gmres_tol * bn || hn == 0.0 || rep->jvps - start >= cap) break;
+                    NKCHK(opf_vec_axpby(c, 1.0 / hn, w, 0.0, vec(j + 1)));
+                    sv[j + 1] = sw / hn;
                 }
-                const double d = std::hypot(Hh(j, j), Hh(j + 1, j));
-                cs[j] = d == 0.0 ? 1.0 : Hh(j, j) / d;
-                sn[j] = d == 0.0 ? 0.0 : Hh(j + 1, j) / d;
-                Hh(j, j) = d;
-                Hh(j + 1, j) = 0.0;
-                g[j + 1] = -sn[j] * g[j];
-                g[j] = cs[j] * g[j];
-                k = j + 1;
-                rep->gmres_iterations += 1;
-                if (std::fabs(g[k]) <= o->gmres_tol * bn || hn == 0.0 || rep->jvps >= o->max_jvps) break;
-                NKCHK(opf_vec_axpby(c, 1.0 / hn, w, 0.0, vec(j + 1)));
+                std::vector<double> y(k, 0.0);
+                for (int i = k - 1; i >= 0; --i) {
+                    double acc = g[i];
+                    for (int j2 = i + 1; j2 < k; ++j2) acc -= Hh(i, j2) * y[j2];
+                    y[i] = acc / Hh(i, i);
+                }
+                for (int i = 0; i < k; ++i) {
+                    NKCHK(opf_vec_axpby(c, y[i], use_pre ? zvec(i) : vec(i), 1.0, dx));
+                    sdx += y[i] * (use_pre ? sz[i] : sv[i]);
+                }
+                ++restarts;
+                if (std::fabs(g[k]) <= o->gmres_tol * bn) {
+                    reached = true;
+                    break;
+                }
+                if (rep->jvps - start >= cap || use_pre) break;
             }
-            std::vector<double> y(k, 0.0);
-            for (int i = k - 1; i >= 0; --i) {
-                double acc = g[i];
-                for (int j2 = i + 1; j2 < k; ++j2) acc -= Hh(i, j2) * y[j2];
-                y[i] = acc / Hh(i, i);
+            return OPF_OK;
+        };
+        // backtracking line search on ||F|| along (dx, sdx); the candidate
+        // stays in (w, tmp); returns whether ||F|| decreased
+        double fnew = 0.0, cnew = cw;
+        auto line_search = [&](bool& lowered) -> opf_status {
+            double lam = 1.0;
+            while (true) {
+                NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
+                NKCHK(opf_vec_axpby(c, lam, dx, 1.0, w));
+                cnew = cw + lam * sdx;
+                NKCHK(opf_newton_residual(c, w, T, cnew * T, tmp, &fnew));
+                rep->residual_evals += 1;
+                if (fnew < fn || lam < 1e-3) break;
+                lam *= 0.5;
             }
-            for (int i = 0; i < k; ++i) NKCHK(opf_vec_axpby(c, y[i], pre ? zvec(i) : vec(i), 1.0, dx));
-            ++restarts;
-            if (std::fabs(g[k]) <= o->gmres_tol * bn || rep->jvps >= o->max_jvps) break;
-        }
-        // backtracking line search on ||F||
-        double lam = 1.0, fnew = 0.0;
-        while (true) {
-            NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
-            NKCHK(opf_vec_axpby(c, lam, dx, 1.0, w));
-            NKCHK(opf_newton_residual(c, w, T, shift, tmp, &fnew));
-            rep->residual_evals += 1;
-            if (fnew < fn || lam < 1e-3) break;
-            lam *= 0.5;
+            lowered = fnew < fn;
+            return OPF_OK;
+        };
+        bool reached = false, lowered = false;
+        NKCHK(gmres(pre, reached));
+        if (pre && fallback && !reached) {  // the network's directions did not solve the step
+            rep->fallbacks += 1;
+            NKCHK(gmres(false, reached));
+            NKCHK(line_search(lowered));
+        } else {
+            NKCHK(line_search(lowered));
+            if (pre && fallback && !lowered) {  // nor lowered ||F||: redo the step without it
+                rep->fallbacks += 1;
+                NKCHK(gmres(false, reached));
+                NKCHK(line_search(lowered));
+            }
         }
         NKCHK(opf_vec_axpby(c, 1.0, w, 0.0, x));
+        cw = cnew;
         HIPCHK(c, hipMemcpyAsync(F0, tmp, vb, hipMemcpyDeviceToDevice, c->stream));
         fn = fnew;
-        NKCHK(nrm(x, &xn));
+        NKCHK(opf_vec_dot(c, x, x, &xn));
+        xn = std::sqrt(std::max(xn, 0.0));
         rep->residual = fn / xn;
         if (it + 1 < 32) rep->residual_history[it + 1] = rep->residual;
     }
 #undef NKCHK
     rep->newton_iterations = it;
     rep->converged = rep->residual <= o->tol ? 1 : 0;
+    rep->speed = cw;
+    *cw_io = cw;
     return OPF_OK;
 }
 

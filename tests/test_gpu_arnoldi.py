@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from inputs import laminar_state, make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stokes_modes.txt")
@@ -47,7 +48,7 @@ def test_stokes_multipliers(torch_cuda):
     Re, dt, T, alpha = 50.0, 0.01, 2.0, 1.25
     kw = dict(N=24, M=3, K=2, alpha=alpha, Re=Re, dt=dt, nonlinear=0)
     say("arnoldi stokes", kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     x = laminar_state(24, 3, 2, s.nodes())
     v0 = make_state(24, 3, 2, 1, alpha, s.nodes(), 1e-2, 3.0, 3.0, 21, laminar=False)
     ev, rep = s.arnoldi(torch_cuda.from_numpy(x), T, 0.0, torch_cuda.from_numpy(v0), m=40, nev=3, tol=1e-8)
@@ -62,7 +63,7 @@ def test_stokes_multipliers(torch_cuda):
     swirl, j11 = golden("swirl", 0, 0.0)
     assert rep["converged"]
     assert np.allclose(ev.real, [mult(gen), mult(swirl), mult(j11 ** 2 + alpha ** 2)], rtol=1e-8, atol=0)
-    o = Oracle(Params(r=s.nodes(), N=24, M=3, K=2, alpha=alpha, Re=Re, dt=dt, nonlinear=False))
+    o = Oracle(Params(N=24, M=3, K=2, alpha=alpha, Re=Re, dt=dt, nonlinear=False))
     evo, k, conv = arnoldi(o, x, T, 0.0, v0, 40, 3, tol=1e-8, check_every=5)
     assert k == rep["products"]
     assert np.allclose(ev, evo, rtol=1e-9, atol=0)
@@ -75,12 +76,12 @@ def test_nonlinear_multipliers_match_oracle(torch_cuda):
     kw = dict(N=16, M=4, K=4, alpha=1.25, Re=1000.0, dt=0.02)
     T, shift = 1.0, 0.3
     say("arnoldi nonlinear", kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     x = laminar_state(16, 4, 4, s.nodes())
     v0 = make_state(16, 4, 4, 1, 1.25, s.nodes(), 1e-2, 3.0, 3.0, 22, laminar=False)
     ev, rep = s.arnoldi(torch_cuda.from_numpy(x), T, shift, torch_cuda.from_numpy(v0), m=30, nev=4, tol=1e-6,
                         check_every=5)
-    o = Oracle(Params(r=s.nodes(), **kw))
+    o = Oracle(Params(**kw))
     evo, k, conv = arnoldi(o, x, T, shift, v0, 30, 4, tol=1e-6, check_every=5)
     say("  gpu", ev, rep["products"], "oracle", evo, k)
     Hg = rep["hessenberg"]

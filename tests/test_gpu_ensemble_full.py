@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from inputs import ensemble_members, make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +24,8 @@ def test_bench_ensemble_sampled_members_match_oracle():
     mem = ensemble_members()
     kws = [dict(N=m["N"], M=m["M"], K=m["K"], mp=m["mp"], alpha=m["alpha"], Re=m["Re"], dt=m["dt"],
                 precision=opf.OPF_MIXED) for m in mem]
-    e = opf.Ensemble(kws)
-    states = [make_state(m["N"], m["M"], m["K"], m["mp"], m["alpha"], e.members[i].nodes(), m["energy_frac"],
+    e = make_ensemble(kws)
+    states = [make_state(m["N"], m["M"], m["K"], m["mp"], m["alpha"], oracle_nodes(m["N"]), m["energy_frac"],
                          m["decay_m"], m["decay_k"], m["seed"], axis_power=1) for i, m in enumerate(mem)]
     for i, st in enumerate(states):
         e.members[i].set_state(torch.from_numpy(st))
@@ -35,8 +36,7 @@ def test_bench_ensemble_sampled_members_match_oracle():
     for i in (5, 40, 95):  # one member of each class
         m = mem[i]
         print("member", i, m["N"], m["M"], m["K"], flush=True)
-        o = Oracle(Params(N=m["N"], M=m["M"], K=m["K"], mp=m["mp"], alpha=m["alpha"], Re=m["Re"], dt=m["dt"],
-                          r=e.members[i].nodes()))
+        o = Oracle(Params(N=m["N"], M=m["M"], K=m["K"], mp=m["mp"], alpha=m["alpha"], Re=m["Re"], dt=m["dt"]))
         ref = o.run(states[i], 3)
         got = e.members[i].get_state().cpu().numpy()
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))

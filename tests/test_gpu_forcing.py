@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from inputs import WORKLOADS, laminar_state, make_state, workload_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -36,9 +37,9 @@ def rel(a, b):
 def setup(kw, rot, **extra):
     import paper_1705_03838_amd as opf
     from oracle import Oracle, Params
-    s = opf.Solver(**kw, **extra)
+    s = make_solver(**kw, **extra)
     s.set_rotation(*rot)
-    o = Oracle(Params(r=s.nodes(), rotation=tuple(rot), **kw))
+    o = Oracle(Params(rotation=tuple(rot), **kw))
     return s, o
 
 
@@ -95,19 +96,19 @@ def test_pipe64_nonlinear_with_rotation(torch_cuda):
     kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
     rot = (0.02, 0.01, 0.005)
     say("pipe64 coriolis nonlinear", rot)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     s.set_rotation(*rot)
-    o = Oracle(Params(r=s.nodes(), rotation=rot, **kw))
+    o = Oracle(Params(rotation=rot, **kw))
     u = workload_state(w, s.nodes())
     assert rel(s.nonlinear(torch_cuda.from_numpy(u)).cpu().numpy(), o.nonlinear(u)) < 1e-13
 
 
 def test_rotation_refused_where_unsupported(torch_cuda):
     import paper_1705_03838_amd as opf
-    s = opf.Solver(**CASES["ragged_axial"][0])
+    s = make_solver(**CASES["ragged_axial"][0])
     with pytest.raises(opf.OpfError):
         s.set_rotation(0.1, 0.0, 0.0)   # transverse axis with mp = 2
     s.set_rotation(0.0, 0.0, 0.1)       # axial is fine
-    t = opf.Solver(**CASES["tiny"][0], nonlinear=False)
+    t = make_solver(**CASES["tiny"][0], nonlinear=False)
     with pytest.raises(opf.OpfError):
         t.set_rotation(0.0, 0.0, 0.1)

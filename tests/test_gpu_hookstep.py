@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from inputs import laminar_state, make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +30,8 @@ def setup():
     import paper_1705_03838_amd as opf
     from oracle import Oracle, Params
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
-    s = opf.Solver(**KW)
-    o = Oracle(Params(r=s.nodes(), **KW))
+    s = make_solver(**KW)
+    o = Oracle(Params(**KW))
     x = make_state(12, 3, 3, 1, 1.25, s.nodes(), 1e-3, 3.0, 3.0, 7)
     return torch, opf, s, o, x
 
@@ -39,7 +40,7 @@ def test_first_hookstep_matches_oracle(setup):
     from oracle.hookstep import newton_hook_pipe
     torch, opf, s, o, x = setup
     say("first hookstep", KW)
-    xg, rep = s.nk_solve(torch.from_numpy(x), T, SHIFT, gmres_m=12, max_newton=1, tol=1e-12, gmres_tol=1e-3,
+    xg, rep = s.nk_solve(torch.from_numpy(x), T, SHIFT / T, gmres_m=12, max_newton=1, tol=1e-12, gmres_tol=1e-3,
                          hookstep=True, tr_delta0=0.01)
     xo, hist, info = newton_hook_pipe(o, x, T, SHIFT, tol=1e-12, m=12, max_newton=1, gmres_tol=1e-3,
                                       delta0=0.01)
@@ -56,7 +57,7 @@ def test_hookstep_reaches_laminar_flow(setup):
     from oracle.hookstep import newton_hook_pipe
     torch, opf, s, o, x = setup
     say("hookstep to laminar", KW)
-    xg, rep = s.nk_solve(torch.from_numpy(x), T, SHIFT, gmres_m=12, tol=1e-8, gmres_tol=1e-3, hookstep=True,
+    xg, rep = s.nk_solve(torch.from_numpy(x), T, SHIFT / T, gmres_m=12, tol=1e-8, gmres_tol=1e-3, hookstep=True,
                          tr_delta0=0.01)
     say("  ", rep)
     _, hist, info = newton_hook_pipe(o, x, T, SHIFT, tol=1e-8, m=12, gmres_tol=1e-3, delta0=0.01)
@@ -71,5 +72,5 @@ def test_hookstep_not_combined_with_preconditioner(setup):
     torch, opf, s, o, x = setup
     net = opf.Mlp(s, width=32, layers=1, rank=1, seed=1)
     with pytest.raises(opf.OpfError):
-        s.nk_solve(torch.from_numpy(x), T, SHIFT, gmres_m=4, max_newton=1, precond=net, hookstep=True)
+        s.nk_solve(torch.from_numpy(x), T, SHIFT / T, gmres_m=4, max_newton=1, precond=net, hookstep=True)
     net.close()

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from inputs import make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -49,13 +50,13 @@ def test_nonlinear_every_length(torch_cuda, M, K):
     from oracle import Oracle, Params
     kw = dict(N=13, M=M, K=K, mp=1, alpha=1.3, Re=2000.0, dt=0.01)
     say("nonlinear at lengths", 3 * M, 3 * K, kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     r = s.nodes()
     u = make_state(13, M, K, 1, 1.3, r, 5e-2, 4.0, 4.0, 7 + M + K)
     ud = torch_cuda.from_numpy(u)
     ref = Oracle(Params(r=r, **kw)).nonlinear(u)
     assert rel(s.nonlinear(ud).cpu().numpy(), ref) < 1e-13
-    m = opf.Solver(precision=opf.OPF_MIXED, **kw)
+    m = make_solver(precision=opf.OPF_MIXED, **kw)
     assert rel(m.nonlinear(ud).cpu().numpy(), ref) < 1e-5
     s.set_rotation(*ROT)
     ref_rot = Oracle(Params(r=r, rotation=ROT, **kw)).nonlinear(u)

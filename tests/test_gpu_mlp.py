@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from inputs import make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +39,7 @@ def torch_cuda():
 def make_net(torch_cuda, width=64, layers=3, max_rows=0, seed=7, **kw):
     import paper_1705_03838_amd as opf
     from oracle.mlp import flatten, init_params, unflatten
-    s = opf.Solver(**GRID)
+    s = make_solver(**GRID)
     net = opf.Mlp(s, width=width, layers=layers, rank=RANK, max_rows=max_rows, **kw)
     p = init_params(net.din, width, layers, net.dout, seed=seed)
     rng = np.random.default_rng(seed)
@@ -187,7 +188,7 @@ def test_probe_pairs_are_jacobian_products(torch_cuda):
     from inputs import laminar_state
     kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
     say("probe pairs", kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     x = torch_cuda.from_numpy(make_state(12, 2, 2, 2, 1.25, s.nodes(), 1e-4, 4.0, 4.0, 6)).cuda()
     pairs = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
     again = s.probe_pairs(x, 1.0, 0.0, 3, seed=5)
@@ -222,7 +223,7 @@ def test_flexible_gmres_with_minus_identity_matches_plain(torch_cuda):
     import paper_1705_03838_amd as opf
     kw = dict(N=12, M=2, K=2, mp=2, alpha=1.25, Re=100.0, dt=0.05)
     say("fgmres -I", kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     net = opf.Mlp(s, width=32, layers=1, rank=2)
     q = net.get_params()
     q[-(net.dout * 32 + net.dout):] = 0.0
@@ -260,7 +261,7 @@ def test_trained_preconditioner_cuts_krylov_work(torch_cuda):
     kw = dict(N=12, M=4, K=4, mp=2, alpha=1.25, Re=200.0, dt=0.05)
     T = 2.0
     say("learned preconditioner gain", kw, "T", T)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     lam = torch_cuda.from_numpy(laminar_state(12, 4, 4, s.nodes())).cuda()
     pairs = s.probe_pairs(lam, T, 0.0, 96, seed=3)  # 3N = 36 complex unknowns per mode
     net = opf.Mlp(s, width=128, layers=4, rank=4, seed=2)
@@ -290,7 +291,7 @@ def test_full_size_network_matches_oracle(torch_cuda):
     from oracle.mlp import (backprop, flatten, feature_rows, forward, head, init_params, precondition,
                             unflatten)
     w = WORKLOADS["nk"]
-    s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
+    s = make_solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
     net = opf.Mlp(s, width=256, layers=4, rank=16)
     say("full-size network", net.din, net.dout, net.n_params)
     p = init_params(net.din, 256, 4, net.dout, seed=12)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from inputs import WORKLOADS, workload_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +21,8 @@ def test_nk_grid_residual_matches_oracle():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     w = WORKLOADS["nk"]
     kw = {k: w[k] for k in ("N", "M", "K", "mp", "alpha", "Re", "dt")}
-    s = opf.Solver(**kw)
-    o = Oracle(Params(r=s.nodes(), **kw))
+    s = make_solver(**kw)
+    o = Oracle(Params(**kw))
     x = workload_state(w, s.nodes())
     x2 = workload_state(dict(w, seed=w["seed"] + 7, energy_frac=1e-2), s.nodes())
     d = s.vec_dot(torch.from_numpy(x), torch.from_numpy(x2))

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from inputs import laminar_state, make_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +30,8 @@ def setup():
     from oracle import Oracle, Params
     from oracle.shooting import Shooting
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
-    s = opf.Solver(**KW)
-    p = Params(r=s.nodes(), **KW)
+    s = make_solver(**KW)
+    p = Params(**KW)
     x = make_state(12, 2, 2, 1, 1.25, s.nodes(), 1e-3, 3.0, 3.0, 7)
     x2 = Shooting(p, 2, N_SEC).oracle(T).run(x, N_SEC)
     return torch, s, p, np.stack([x, x2])
@@ -73,6 +74,6 @@ def test_fixed_period_single_section_is_the_travelling_wave_search(setup):
     g, Tg, sg, rep = s.shoot_solve(torch.from_numpy(xs[:1]), T, SHIFT, 50, free_T=False, free_s=False, gmres_m=20,
                                    tol=1e-8, gmres_tol=1e-3)
     assert Tg == T and sg == SHIFT and rep["converged"]
-    xn, nrep = s.nk_solve(torch.from_numpy(xs[0]), T, SHIFT, gmres_m=20, tol=1e-8, gmres_tol=1e-3, hookstep=True)
+    xn, nrep = s.nk_solve(torch.from_numpy(xs[0]), T, SHIFT / T, gmres_m=20, tol=1e-8, gmres_tol=1e-3, hookstep=True)
     assert nrep["converged"]
     assert np.max(np.abs(g.cpu().numpy()[0] - xn.cpu().numpy())) <= 1e-7

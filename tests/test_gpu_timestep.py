@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from inputs import WORKLOADS, laminar_state, make_state, workload_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -33,12 +34,12 @@ def torch_cuda():
 
 def solver(**kw):
     import paper_1705_03838_amd as opf
-    return opf.Solver(**kw)
+    return make_solver(**kw)
 
 
 def oracle_for(s, **kw):
     from oracle import Oracle, Params
-    return Oracle(Params(r=s.nodes(), **kw))
+    return Oracle(Params(**kw))
 
 
 def state_for(kw, r, energy=1e-2, seed=11):
@@ -144,7 +145,7 @@ def test_adaptive_run_matches_oracle(torch_cuda, case):
     s.set_state(torch_cuda.from_numpy(u))
     rep = s.step_adaptive(12, courant=ctl.courant, pc_tol=ctl.pc_tol, dt_min=ctl.dt_min, dt_max=ctl.dt_max,
                           grow=ctl.grow, check_every=ctl.check_every, trace=True)
-    ref_u, dts, info = run_adaptive(Params(r=s.nodes(), **kw), u, 12, ctl)
+    ref_u, dts, info = run_adaptive(Params(**kw), u, 12, ctl)
     say(f"  dts {rep['dts']}")
     assert rep["changes"] == info["changes"] >= 1
     assert np.allclose(rep["dts"], dts, rtol=1e-10, atol=0)

@@ -10,6 +10,7 @@ import pytest
 from scipy.special import j1, jn_zeros
 
 from inputs import WORKLOADS, laminar_state, make_state, workload_state
+from gpu_support import make_ensemble, make_solver, oracle_nodes  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,7 @@ def test_rotating_pipe_steady_and_spin_up(torch_cuda):
     N, M, K, V = 32, 2, 2, 0.5
     kw = dict(N=N, M=M, K=K, alpha=1.25, Re=100.0, dt=0.01)
     say("rotating pipe", kw)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     s.set_wall_velocity(rotation_wall(M, K, V))
     r = s.nodes()
     u = laminar_state(N, M, K, r)
@@ -81,9 +82,9 @@ def test_general_wall_motion_matches_oracle(torch_cuda, case):
           "ragged": dict(N=21, M=6, K=4, mp=2, alpha=0.9, Re=1500.0, dt=0.007)}[case]
     say("wall motion", case, kw)
     b = random_wall(kw["M"], kw["K"], 9)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     s.set_wall_velocity(b)
-    o = Oracle(Params(r=s.nodes(), wall=b, **kw))
+    o = Oracle(Params(wall=b, **kw))
     u = make_state(kw["N"], kw["M"], kw["K"], kw["mp"], kw["alpha"], s.nodes(), 1e-2, 4.0, 4.0, 43)
     s.set_state(torch_cuda.from_numpy(u))
     s.step(5)
@@ -96,7 +97,7 @@ def test_general_wall_motion_matches_oracle(torch_cuda, case):
     g, dm = o.boundary_and_divergence(ref)
     assert d["g_norm"] <= 1e-13 and g <= 1e-13
     assert abs(d["div_max"] - dm) <= 1e-9 * max(dm, 1e-12)
-    m = opf.Solver(precision=opf.OPF_MIXED, **kw)
+    m = make_solver(precision=opf.OPF_MIXED, **kw)
     m.set_wall_velocity(b)
     m.set_state(torch_cuda.from_numpy(u))
     m.step(5)
@@ -112,9 +113,9 @@ def test_pipe64_step_with_moving_wall(torch_cuda):
     b = random_wall(w["M"], w["K"], 10, scale=1e-3)
     b[1, 0, w["K"] - 1] = 0.05
     say("pipe64 wall step")
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     s.set_wall_velocity(b)
-    o = Oracle(Params(r=s.nodes(), wall=b, **kw))
+    o = Oracle(Params(wall=b, **kw))
     u = workload_state(w, s.nodes())
     s.set_state(torch_cuda.from_numpy(u))
     s.step(1)
@@ -124,7 +125,7 @@ def test_pipe64_step_with_moving_wall(torch_cuda):
 def test_wall_arguments(torch_cuda):
     import paper_1705_03838_amd as opf
     kw = dict(N=16, M=3, K=3, alpha=1.25, Re=500.0, dt=0.01)
-    s = opf.Solver(**kw)
+    s = make_solver(**kw)
     b = np.zeros((3, 3, 5), dtype=complex)
     b[0, 0, 2] = 0.1  # net radial flux through the wall
     with pytest.raises(opf.OpfError):
