@@ -35,11 +35,18 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     const int mu = helm ? q / a.K : a.mp * ((q - a.MU * a.K) / a.K);
     const int ka = helm ? q % a.K : (q - a.MU * a.K) % a.K;
     double* F = a.fac + (size_t)q * N * FACW;
+    // substitution image of this operator: [|k|][mu] (Helmholtz), [|k|][m] (pressure)
+    const int FW = solve_image_doubles(a.NB, a.NW), FWD = solve_image_fwd(a.NB, a.NW);
+    const size_t iq = helm ? (size_t)ka * a.MU + mu : (size_t)a.MU * a.K + (size_t)ka * a.M + (q - a.MU * a.K) / a.K;
+    double* G = a.img + iq * FW;
+    double* Dv = a.dinv + iq * a.NB;
     if (!helm && mu == 0 && ka == 0) {
         if (n < N) {
             for (int d = 0; d < FMAIN; ++d) F[(size_t)n * FMAIN + d] = d == 8 ? 1.0 : 0.0;
             for (int d = 0; d < FTAIL; ++d) F[(size_t)N * FMAIN + (size_t)n * FTAIL + d] = 0.0;
         }
+        for (int e = n; e < FW; e += 64) G[e] = 0.0;
+        if (n < a.NB) Dv[n] = 0.0;
         if (n == 0) a.flags[q] = 0;
         return;
     }
@@ -108,6 +115,19 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
         for (int d = 0; d < 4; ++d) f[4 + d] = n - 1 - d >= 0 ? B[(n - 1 - d) * BW + (9 + d)] : 0.0;
         f[8] = 1.0 / B[n * BW + 8];
         f[9] = 0.0;
+    }
+    // image: Lh[n+d][n] = L[n+d][n] U_nn / U_{n+d,n+d}, W[n-d][n] = U[n-d][n] / U_{n-d,n-d}
+    if (n < a.NB) {
+        const int nd = n < a.NW ? 4 : 8;
+        double* g = G + (n < a.NW ? 4 * n : 4 * a.NW + 8 * (n - a.NW));
+        for (int d = 1; d <= nd; ++d)
+            g[d - 1] = n < N && n + d < N ? B[(n + d) * BW + (8 - d)] * B[n * BW + 8] / B[(n + d) * BW + 8] : 0.0;
+        if (n >= 1) {
+            double* gb = G + FWD + 4 * (n - 1);
+            for (int d = 1; d <= 4; ++d)
+                gb[d - 1] = n < N && n - d >= 0 ? B[(n - d) * BW + (8 + d)] / B[(n - d) * BW + 8] : 0.0;
+        }
+        Dv[n] = n < N ? 1.0 / B[n * BW + 8] : 0.0;
     }
     // the band check is per row: any lane's flag marks the system
     for (int o = 32; o > 0; o >>= 1) bad = max(bad, __shfl_xor(bad, o));

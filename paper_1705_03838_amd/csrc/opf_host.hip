@@ -217,7 +217,7 @@ void build_grid(opf_ctx* c, const double* r_nodes) {
 }
 
 struct Layout {
-    size_t r, rinv, quad, d1, d2, s0, fac, hom, ainv, green, flags, qg, wall, twz, twt;
+    size_t r, rinv, quad, d1, d2, wl, s0, fac, img, dinv, hom, ainv, green, flags, qg, wall, twz, twt;
     size_t u, up, w64, w, Nn, Np, H, G, u32, up32, beta, partial, dpart, cflw, cpart, total;
 };
 
@@ -235,8 +235,12 @@ Layout layout(const opf_params& p) {
     L.quad = take(N * 8);
     L.d1 = take(2 * N * W9 * 8);
     L.d2 = take(2 * N * W9 * 8);
+    L.wl = take(2 * N * W9 * 8);
     L.s0 = take(N * 4);
     L.fac = take(nfac * N * FACW * 8);
+    // substitution images at the largest size (no narrow rows)
+    L.img = take(nfac * solve_image_doubles(solve_nb((int)N), 0) * 8);
+    L.dinv = take(nfac * solve_nb((int)N) * 8);
     L.hom = take(M * K * NHOM * N * 8);
     L.ainv = take(M * nk * 16 * 16);
     L.green = take(N * 8);
@@ -487,6 +491,10 @@ opf_status device_tables(opf_ctx* c, bool pressure) {
     a.d2 = c->t.d2;
     a.s0 = c->t.s0;
     a.fac = reinterpret_cast<double*>(c->ws + Lo.fac);
+    a.img = reinterpret_cast<double*>(c->ws + Lo.img);
+    a.dinv = reinterpret_cast<double*>(c->ws + Lo.dinv);
+    a.NB = solve_nb(p.N);
+    a.NW = solve_nw(p.N, c->narrow);
     a.hom = reinterpret_cast<double*>(c->ws + Lo.hom);
     a.ainv = reinterpret_cast<double*>(c->ws + Lo.ainv);
     a.green = reinterpret_cast<double*>(c->ws + Lo.green);
@@ -729,6 +737,15 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     if (he == hipSuccess) he = up(Lo.d1, c->d1.data(), c->d1.size() * 8);
     if (he == hipSuccess) he = up(Lo.d2, c->d2.data(), c->d2.size() * 8);
     if (he == hipSuccess) he = up(Lo.s0, c->s0.data(), N * 4);
+    // folded weights of d2/dr2 + (1/r) d/dr (the radial part of L), per parity
+    std::vector<double> wl(2 * N * W9);
+    for (int par = 0; par < 2; ++par)
+        for (int n = 0; n < N; ++n)
+            for (int j = 0; j < W9; ++j) {
+                const size_t i = ((size_t)par * N + n) * W9 + j;
+                wl[i] = c->d2[i] + c->rinv[n] * c->d1[i];
+            }
+    if (he == hipSuccess) he = up(Lo.wl, wl.data(), wl.size() * 8);
     // CFL weights: 1/dr_n (nearer neighbour; the axis mirror -r_0 for n = 0) and 1/(r_n dtheta)
     std::vector<double> cflw(2 * N);
     for (int n = 0; n < N; ++n) {
@@ -753,6 +770,9 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->t.d2 = reinterpret_cast<const double*>(ws + Lo.d2);
     c->t.s0 = reinterpret_cast<const int*>(ws + Lo.s0);
     c->t.fac = reinterpret_cast<const double*>(ws + Lo.fac);
+    c->t.img = reinterpret_cast<const double*>(ws + Lo.img);
+    c->t.dinv = reinterpret_cast<const double*>(ws + Lo.dinv);
+    c->t.wl = reinterpret_cast<const double*>(ws + Lo.wl);
     c->t.hom = reinterpret_cast<const double*>(ws + Lo.hom);
     c->t.ainv = reinterpret_cast<const double*>(ws + Lo.ainv);
     c->t.green = reinterpret_cast<const double*>(ws + Lo.green);

@@ -22,6 +22,23 @@ constexpr int FACW = 14;  // doubles per LU factor row: 8 of L, 4 of U, 1/U_ii, 
 constexpr int FMAIN = 10;
 constexpr int FTAIL = 4;
 constexpr int NHOM = 7;   // real radial lines of influence data per (m,|k|)
+// Substitution images of the LU factors (see solve_image_doubles): with
+// A = L U = L D W (D = diag U, W unit upper), A x = b is solved as
+// (D^-1 L D) y = D^-1 b, then W x = y.  Per operator, padded to NB rows:
+// the forward part, row i holding Lh[i+1..i+4][i] for i < NW and
+// Lh[i+1..i+8][i] from NW on (Lh = D^-1 L D), then the backward part, row
+// i >= 1 holding W[i-1..i-4][i] at solve_image_fwd + 4 (i - 1) (row 0 has no
+// entries above the diagonal); rows N..NB-1 are zero.  dinv = 1/U_ii per row.
+__host__ __device__ constexpr int solve_image_fwd(int NB, int NW) { return 4 * NW + 8 * (NB - NW); }
+__host__ __device__ constexpr int solve_image_doubles(int NB, int NW) { return solve_image_fwd(NB, NW) + 4 * (NB - 1); }
+// Padded row count and narrow-row count of the substitution for N radial
+// points whose LU columns j < narrow have at most four entries below the
+// diagonal: NB = 32, 48 or 64, NW = NB - 9, NB - 25 or 0 (the largest the
+// bound allows).
+__host__ __device__ constexpr int solve_nb(int N) { return N <= 32 ? 32 : (N <= 48 ? 48 : 64); }
+__host__ __device__ constexpr int solve_nw(int N, int narrow) {
+    return narrow >= solve_nb(N) - 9 ? solve_nb(N) - 9 : (narrow >= solve_nb(N) - 25 ? solve_nb(N) - 25 : 0);
+}
 constexpr int NMAX = 64;  // radial points handled by one solve workgroup
 constexpr int TILE = 8;   // radial lines per z-transform workgroup
 
@@ -43,6 +60,9 @@ struct Tables {
     const double* d2;     // [2][N][9] folded second-derivative weights
     const int* s0;        // [N] first column of row n's 9-point window
     const double* fac;    // [nfac] banded LU factors of N FACW doubles (main then tail records)
+    const double* img;    // substitution images: [K][MU] Helmholtz, then [K][M] pressure
+    const double* dinv;   // [K][MU] then [K][M] rows of NB values: 1/U_ii (0 past N)
+    const double* wl;     // [2][N][9] folded weights of d2/dr2 + (1/r) d/dr, parity 0 even / 1 odd
     const double* hom;    // [M][K][NHOM][N] influence data (h1+, h1-, q, h2, h3, h4, P1)
     const double* ainv;   // [M][2K-1][16][2] inverse influence matrices (complex)
     const double* green;  // [N] flux Green's function: H_0 u_G = 1, u_G(1) = 0
@@ -108,6 +128,9 @@ struct FactorArgs {
     const double* d2;
     const int* s0;
     double* fac;        // [MU K + M K] factors of N FACW doubles: H_{|mu|,|k|} then L_{m,|k|}
+    double* img;        // substitution images (Tables::img), NB rows, NW narrow rows
+    double* dinv;       // Tables::dinv
+    int NB, NW;
     double* hom;        // [M][K][NHOM][N]
     double* ainv;       // [M][2K-1][16][2]
     double* green;      // [N]

@@ -14,10 +14,14 @@
 // on |k|, and neighbouring m share Helmholtz operators).  Lanes are radial
 // nodes for the stencil work, wave w holding modes 2w and 2w+1; for the
 // substitutions each lane of wave 0 owns one real right-hand side (a real or
-// imaginary part of one component of one mode) and walks the rows with the
-// factor staged in LDS.  m = 0 solves k >= 0 only and writes the conjugate
-// into -k (Hermitian symmetry of a real field); mode (0,0) has u_r = 0, no
-// pressure and the fixed-flux correction.
+// imaginary part of one component of one mode) and walks the rows of the
+// operator's substitution image (unit triangles of the diagonally scaled LU
+// factors, see solve_image_doubles), brought into LDS by DMA.  About 52 KB
+// of LDS and at most 168 VGPRs let three workgroups share a compute unit, so
+// the 768 tiles of the 64 x 48 x 127-mode grid run in one round.  m = 0
+// solves k >= 0 only and writes the conjugate into -k (Hermitian symmetry
+// of a real field); mode (0,0) has u_r = 0, no pressure and the fixed-flux
+// correction.
 #include "opf_internal.h"
 
 namespace opf {
@@ -91,26 +95,28 @@ __device__ __forceinline__ void vort_row(const Tables& t, int N, int n, int m, d
     wz = 0.5 * ix(am - ap);
 }
 
-// Substitution for one real right-hand side living in LDS (`col`, element i
-// at col[2 i]) with a factor in LDS whose row record i holds column i of L
-// below the diagonal (8 values), column i of U above it (4 values) and
-// 1/U_ii.  Right-looking: once y_i is known it updates the next 8 entries,
-// kept in registers, so only one FMA per row lies on the dependency chain;
-// factor records and right-hand-side entries are fetched PF rows ahead.
-// Rows N..NB-1 of the factor and of `col` are zero (the padded tail stays
-// zero; no branches).  Columns j < NW have no nonzero L entry more than four
-// rows below the diagonal (SolveArgs::narrow >= NW): their rows read and
-// apply only the first four, with the same result.  With all but the last
-// nine rows narrow, records are fetched 5 rows ahead instead of 3; with
-// fewer narrow rows a deeper prefetch would exceed 256 VGPRs.
+// Substitution on one real right-hand side held in LDS (element i at
+// col[2 i]: the real or imaginary part of a complex radial line; rows past
+// N are zero), with a factor image F in LDS (see solve_image_doubles); one
+// lane per right-hand side.  Forward sweep with the unit lower Lh, right-
+// looking: once y_i is known it updates the next four (eight from row NW on)
+// entries, kept in registers, so one multiply-add per row lies on the
+// dependency chain; backward sweep with the unit upper W likewise.  Factor
+// rows and right-hand-side entries are fetched PF rows ahead.  Each row's
+// instructions stay in place (a scheduling barrier per row): free scheduling
+// would hoist the LDS reads of many rows at once, far past the register
+// budget of three workgroups per compute unit.
 template <int NB, int NW>
 __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* col) {
-    constexpr int PF = NW >= NB - 9 ? 5 : 3;  // narrow rows leave registers for a deeper prefetch
+    constexpr int PF = 4;
+    constexpr int FWD = solve_image_fwd(NB, NW);
+    auto frow = [](int i) { return i < NW ? 4 * i : 4 * NW + 8 * (i - NW); };
+    auto brow = [](int i) { return FWD + 4 * (i - 1); };
     double2 L[PF][4];
     double nb[PF];  // col[i + 8] for the coming rows
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-        const double2* f = reinterpret_cast<const double2*>(F + p * FACW);
+        const double2* f = reinterpret_cast<const double2*>(F + frow(p));
 #pragma unroll
         for (int j = 0; j < (p < NW ? 2 : 4); ++j) L[p][j] = f[j];
         nb[p] = 8 + p < NB ? col[2 * (8 + p)] : 0.0;
@@ -123,11 +129,12 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
         const double2 l01 = L[p][0], l23 = L[p][1], l45 = L[p][2], l67 = L[p][3];
         const double next = nb[p];
         if (i + PF < NB) {
-            const double2* f = reinterpret_cast<const double2*>(F + (i + PF) * FACW);
+            const double2* f = reinterpret_cast<const double2*>(F + frow(i + PF));
 #pragma unroll
             for (int j = 0; j < (i + PF < NW ? 2 : 4); ++j) L[p][j] = f[j];
             nb[p] = i + PF + 8 < NB ? col[2 * (i + PF + 8)] : 0.0;
         }
+        __builtin_amdgcn_sched_barrier(0);
         const double y = b0;
         col[2 * i] = y;
         b0 = b1 - l01.x * y;
@@ -146,88 +153,68 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
             b7 = next - l67.y * y;
         }
     }
-    double2 U[PF][3];  // (u1, u2), (u3, u4), (1/U_ii, pad)
-    double nc[PF];     // col[i - 4] for the coming rows
+    double2 U[PF][2];
+    double nc[PF];  // col[i - 4] for the coming rows
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
         const int i = NB - 1 - p;
-        const double2* f = reinterpret_cast<const double2*>(F + i * FACW + 8);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) U[p][j] = f[j];
+        const double2* f = reinterpret_cast<const double2*>(F + brow(i));
+        U[p][0] = f[0];
+        U[p][1] = f[1];
         nc[p] = i - 4 >= 0 ? col[2 * (i - 4)] : 0.0;
     }
     double c0 = col[2 * (NB - 1)], c1 = col[2 * (NB - 2)], c2 = col[2 * (NB - 3)], c3 = col[2 * (NB - 4)];
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
         const int i = NB - 1 - t, p = t % PF;
-        const double2 u12 = U[p][0], u34 = U[p][1], dv = U[p][2];
+        const double2 u12 = U[p][0], u34 = U[p][1];
         const double next = nc[p];
-        if (t + PF < NB) {
-            const double2* f = reinterpret_cast<const double2*>(F + (i - PF) * FACW + 8);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) U[p][j] = f[j];
+        if (t + PF < NB - 1) {  // row 0 has nothing above the diagonal: no record
+            const double2* f = reinterpret_cast<const double2*>(F + brow(i - PF));
+            U[p][0] = f[0];
+            U[p][1] = f[1];
             nc[p] = i - PF - 4 >= 0 ? col[2 * (i - PF - 4)] : 0.0;
         }
-        const double x = c0 * dv.x;
+        __builtin_amdgcn_sched_barrier(0);
+        const double x = c0;
         col[2 * i] = x;
-        c0 = c1 - u12.x * x;
-        c1 = c2 - u12.y * x;
-        c2 = c3 - u34.x * x;
-        c3 = next - u34.y * x;
+        if (i > 0) {
+            c0 = c1 - u12.x * x;
+            c1 = c2 - u12.y * x;
+            c2 = c3 - u34.x * x;
+            c3 = next - u34.y * x;
+        }
     }
 }
 
-// Factors moving from global memory to LDS in two halves: load() issues all
-// 16-byte loads of this thread into registers (branch-free, clamped
-// indices), store() writes them into FACW-double row records at stride FS
-// doubles and zeroes rows N..NB-1.  Factor f has global index base + f *
-// stride.  A factor's main records (5 double2 per row) are copied whole, its
-// tail records (2 double2 per row) from row NW on: the narrow rows before NW
-// never read their tail, whose LDS slots are left as they are.
-template <int NB, int NFMAX, int NTHR, int NW>
-struct FactorStage {
-    static constexpr int M2 = FMAIN / 2, T2 = FTAIL / 2, R2 = FACW / 2;
-    static constexpr int MAXIT = (NFMAX * (NB * M2 + (NB - NW) * T2) + NTHR - 1) / NTHR;
-    double2 tmp[MAXIT];
-    // double2 r of a factor's copied part: offset in its HBM block, offset in LDS
-    __device__ __forceinline__ static int src(int r, int N) { return r < N * M2 ? r : r + NW * T2; }
-    __device__ __forceinline__ static int dst(int r, int N) {
-        if (r < N * M2) {
-            const int i = r / M2, s = r % M2;
-            return i * R2 + (s < 2 ? s : s + T2);  // L[1..4] -> slots 0, 1; U, 1/U -> 4, 5, 6
-        }
-        const int t = r - N * M2;
-        return (NW + t / T2) * R2 + 2 + t % T2;  // L[5..8] -> slots 2, 3
+// LDS DMA (global_load_lds_dwordx4): each active lane loads 16 bytes from
+// its own global address into LDS at dst + 16 * lane, without registers.
+// dst must be the same for the whole wave.  Completion is tracked by the
+// vector-memory counter, so a wave waits with lds_dma_wait() before the data
+// is read (and a workgroup barrier publishes it to the other waves).
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+__device__ __forceinline__ void lds_dma16(const void* src, void* dst_wave) {
+    __builtin_amdgcn_global_load_lds((glb_void_t*)src, (lds_void_t*)dst_wave, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Copy nbytes (a multiple of 16; both ends 16-byte aligned) from global
+// memory to LDS by DMA, 1 KB per wave instruction, the four waves taking
+// alternate kilobytes.
+__device__ __forceinline__ void dma_copy(const void* src, void* dst, int nbytes, int w, int lane) {
+    const int nch = (nbytes + 1023) >> 10;
+    for (int ch = w; ch < nch; ch += 4) {
+        const int off = (ch << 10) + 16 * lane;
+        if (off < nbytes)
+            lds_dma16(static_cast<const char*>(src) + off, static_cast<char*>(dst) + (ch << 10));
     }
-    __device__ __forceinline__ void load(const double* fac, size_t base, size_t stride, int nf, int N, int t) {
-        const int per = N * M2 + (N - NW) * T2, total = nf * per;
-        const size_t FSZ = (size_t)N * FACW;
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            const int e = min(t + it * NTHR, total - 1);
-            tmp[it] = reinterpret_cast<const double2*>(fac + (base + (e / per) * stride) * FSZ)[src(e % per, N)];
-        }
-    }
-    __device__ __forceinline__ void store(double* sF, int FS, int nf, int N, int t) const {
-        const int per = N * M2 + (N - NW) * T2, total = nf * per;
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            const int e = t + it * NTHR;
-            if (e < total) reinterpret_cast<double2*>(sF + (e / per) * FS)[dst(e % per, N)] = tmp[it];
-        }
-        const int zper = (NB - N) * FACW;
-        for (int e = t; e < nf * zper; e += NTHR) sF[(e / zper) * FS + N * FACW + e % zper] = 0.0;
-    }
-};
+}
 
 constexpr int NSLOT = 8;     // modes per workgroup: up to 4 values of m, both signs of k
 
-// One workgroup = 4 waves handles |k| = kabs and GM consecutive m
-// (GM = 4, 2, 1 for mp = 1, 2, >= 3 so that the Helmholtz wavenumbers
-// mp*m-1 .. mp*m+1 of the block form one contiguous range of <= 6 values,
-// shared between neighbouring m).  Slot q = 2 j + s is mode (m0 + j, s ? -k : +k).
-// Wave w does the radial-line work of slots 2w, 2w+1; wave 0 does the
-// substitutions with one lane per real right-hand side.
+// Vorticity at row n from (+,-,z) lines in LDS with the first-derivative
+// weights of both parities in registers.
 __device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, int n, int m, double kap,
                                            const dcplx* up, const dcplx* um, const dcplx* uz,
                                            dcplx& wp, dcplx& wm, dcplx& wz) {
@@ -243,16 +230,47 @@ __device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, 
     wz = 0.5 * ix(am - ap);
 }
 
+// 9 weights of one parity for row n, in registers.
+struct Row9 {
+    double e[W9];
+    __device__ __forceinline__ void load(const double* tab, int N, int par, int n) {
+#pragma unroll
+        for (int j = 0; j < W9; ++j) e[j] = tab[(par * N + n) * W9 + j];
+    }
+    __device__ __forceinline__ dcplx apply(const dcplx* line, int s0) const {
+        dcplx acc = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < W9; ++j) acc = acc + e[j] * line[s0 + j];
+        return acc;
+    }
+};
+
+// One workgroup = 4 waves handles |k| = kabs and GM consecutive m
+// (GM = 4, 2, 1 for mp = 1, 2, >= 3 so that the Helmholtz wavenumbers
+// mp*m-1 .. mp*m+1 of the block form one contiguous range of <= 6 values,
+// shared between neighbouring m).  Slot q = 2 j + s is mode (m0 + j, s ? -k : +k).
+// Wave w does the radial-line work of slots 2w, 2w+1 (one lane per radial
+// node); wave 0 does the substitutions, one lane per complex right-hand side.
+// LDS: the factor area (the pressure images and columns, then the Helmholtz
+// images), the radial lines (u^n as loaded, then the right-hand sides and
+// the solution) and the slots' inverse influence matrices: about 53 KB at
+// NB = 64, so three workgroups share a compute unit.  Every input is
+// requested at the start (u^n lines, pressure images and A^-1 by LDS DMA,
+// the nonlinear terms into registers); the Helmholtz images follow as soon as
+// the pressure images are consumed.
 template <typename TNL, int NB, int NW>
 __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
-    constexpr int FS = NB * FACW + 4;  // factor stride (doubles): spreads LDS banks
+    constexpr int FW = solve_image_doubles(NB, NW);
     constexpr int XS = NB + 1;         // radial line stride (complex)
-    __shared__ __align__(16) double sF[NFH * FS];
+    constexpr int FA = NFH * FW;       // factor area (doubles)
+    static_assert(4 * FW + NSLOT * XS * 2 <= FA, "pressure images and columns fit the factor area");
+    __shared__ __align__(16) double sF[FA];
     __shared__ __align__(16) dcplx sX[NSLOT][3][XS];
-    __shared__ dcplx sY[NSLOT][XS];
-    __shared__ dcplx sA[NSLOT][4];
-    __shared__ double sGam;
-    dcplx(*sU)[3][XS] = reinterpret_cast<dcplx(*)[3][XS]>(sF);  // u^n staging (aliases factors)
+    // slot q's A^-1 (32 doubles), overwritten by its correction a (8 doubles)
+    // once read; the flux correction of (0,0) in slot 0's last entry
+    __shared__ __align__(16) double sAi[NSLOT][32];
+    double& sGam = sAi[0][31];
+    dcplx(*sY)[XS] = reinterpret_cast<dcplx(*)[XS]>(sF + 4 * FW);  // pressure columns
 
     const Tables& t = a.t;
     const int N = a.N, K = a.K, nk = a.nk, mp = a.mp;
@@ -270,14 +288,14 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const size_t S = (size_t)a.M * nk * N;
     const int mu_lo = max(mp * m0 - 1, 0);
     const int nr = n < N ? n : N - 1;  // lanes past the last row read a valid row
-    RowW W1;  // first-derivative weights of this lane's row, both parities
-    W1.load(t.d1, N, nr);
     const int s0r = t.s0[nr];
     const double rinvr = t.rinv[nr];
-
     const int nfp = min(GM, a.M - m0);
     const int mu_hi = min(mp * (m0 + GM - 1) + 1, a.MU - 1);
     const int nfh = mu_hi - mu_lo + 1;
+    const int mw = mp * min(m0 + w, a.M - 1);  // azimuthal wavenumber of this wave's slots
+    const size_t ihelm = (size_t)kabs * a.MU + mu_lo;                   // first Helmholtz image
+    const size_t ippe = (size_t)a.MU * K + (size_t)kabs * a.M + m0;     // first pressure image
 
     auto slot_ok = [&](int q) {
         const int j = q >> 1, s = q & 1, mi = m0 + j;
@@ -288,162 +306,210 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         return ((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * N;
     };
 
-    // rows N..NB-1 of the line buffers stay zero (branch-free substitution)
-    for (int i = tid; i < NSLOT * (NB + 1 - N); i += 256) {
-        const int q = i / (NB + 1 - N), r = N + i % (NB + 1 - N);
-        sY[q][r] = dcplx{0.0, 0.0};
-        sX[q][0][r] = sX[q][1][r] = sX[q][2][r] = dcplx{0.0, 0.0};
-    }
-    // ---- load u^n (or R) of this wave's slots ---------------------------
-    for (int q = 2 * w; q < 2 * w + 2; ++q) {
-        if (!slot_ok(q) || n >= N) continue;
-        const size_t off = slot_off(q) + n;
-        if (a.kind == OPF_SOLVE_RAW) {
-            const dcplx rr = load_c<double>(a.n0, off), rt = load_c<double>(a.n0, S + off);
-            sX[q][0][n] = rr + ix(rt);
-            sX[q][1][n] = rr - ix(rt);
-            sX[q][2][n] = load_c<double>(a.n0, 2 * S + off);
-        } else {
-            const dcplx ur = load_c<double>(a.u0, off), ut = load_c<double>(a.u0, S + off);
-            sU[q][0][n] = ur + ix(ut);
-            sU[q][1][n] = ur - ix(ut);
-            sU[q][2][n] = load_c<double>(a.u0, 2 * S + off);
-        }
-    }
-    __syncthreads();
-
-    // ---- R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) --------------------
-    if (a.kind != OPF_SOLVE_RAW && n < N) {
-        const int s0 = s0r;
-        const double rinv = rinvr;
-        RowW W2;  // second-derivative weights, needed here only
-        W2.load(t.d2, N, n);
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
-            if (!slot_ok(q)) continue;
-            const int m = mp * (m0 + (q >> 1)), k = slot_k(q);
-            const double kap2 = a.alpha * k * a.alpha * k;
-            const size_t off = slot_off(q) + n;
-            dcplx nr, nt, nz;
-            if (a.kind == OPF_SOLVE_PRED) {
-                nr = load_c<TNL>(a.n0, off);
-                nt = load_c<TNL>(a.n0, S + off);
-                nz = load_c<TNL>(a.n0, 2 * S + off);
-            } else {
-                const double cc = a.c, c1 = 1.0 - a.c;
-                nr = c1 * load_c<TNL>(a.n0, off) + cc * load_c<TNL>(a.n1, off);
-                nt = c1 * load_c<TNL>(a.n0, S + off) + cc * load_c<TNL>(a.n1, S + off);
-                nz = c1 * load_c<TNL>(a.n0, 2 * S + off) + cc * load_c<TNL>(a.n1, 2 * S + off);
-            }
-            const dcplx nl[3] = {nr + ix(nt), nr - ix(nt), nz};
-            const int mus[3] = {m + 1, m - 1, m};
+    // ---- requests: u^n (or R) lines of this wave's slots and the pressure
+    //      images by DMA, the slots' A^-1 (wave 0), the nonlinear terms
+    {
+        const double* src = a.kind == OPF_SOLVE_RAW ? static_cast<const double*>(a.n0) : a.u0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int mu = mus[c], p = abs(mu) & 1;
-                const dcplx* line = sU[q][c];
-                const dcplx d2 = W2.apply(p, line, s0);
-                const dcplx d1 = W1.apply(p, line, s0);
-                const double diag = double(mu) * double(mu) * rinv * rinv + kap2;
-                const dcplx Lu = d2 + rinv * d1 - diag * line[n];
-                sX[q][c][n] = a.inv_dt * line[n] + a.aexp * Lu + nl[c];
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
+            if (!slot_ok(q)) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (n < N) lds_dma16(src + 2 * (c * S + slot_off(q) + n), &sX[q][c][0]);
+        }
+        dma_copy(t.img + ippe * FW, sF, nfp * FW * 8, w, n);
+        if (w == 0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {  // four slots (16 lanes of 16 bytes each) per instruction
+                const int q = 4 * i + (n >> 4);
+                if (slot_ok(q))
+                    lds_dma16(t.ainv + (((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * 16) * 2 + 2 * (n & 15),
+                              &sAi[4 * i][0]);
             }
-            if (m == 0 && k == 0) sX[q][2][n].x += a.force;
         }
     }
-    __syncthreads();
-
-    // ---- pressure-Poisson right-hand side div R (P(1) = 0); stage L factors
-    {  // pressure factors L_{m,|k|}, m0 <= m < m0 + GM (the u^n staging area is free now)
-        FactorStage<NB, 4, 256, NW> ppe;
-        ppe.load(t.fac, (size_t)a.MU * K + (size_t)m0 * K + kabs, K, nfp, N, tid);
-        ppe.store(sF, FS, nfp, N, tid);
+    dcplx na[2][3];  // nonlinear terms (PRED: N^n, CORR: (1-c) N^n + c N^p) of this lane's row
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int q = 2 * w + j;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) na[j][c] = dcplx{0.0, 0.0};
+        if (a.kind == OPF_SOLVE_RAW || !slot_ok(q) || n >= N) continue;
+        const size_t off = slot_off(q) + n;
+        if (a.kind == OPF_SOLVE_PRED) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) na[j][c] = load_c<TNL>(a.n0, c * S + off);
+        } else {
+            const double cc = a.c, c1 = 1.0 - a.c;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                na[j][c] = c1 * load_c<TNL>(a.n0, c * S + off) + cc * load_c<TNL>(a.n1, c * S + off);
+        }
     }
-    if (n < N) {
-        const int s0 = s0r;
-        const double rinv = rinvr;
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
-            if (!slot_ok(q)) continue;
+    Row9 Lo, Le;  // weights of d2/dr2 + (1/r) d/dr, parity of this wave's m +- 1 and of m
+    Lo.load(t.wl, N, (mw + 1) & 1, nr);
+    Le.load(t.wl, N, mw & 1, nr);
+    // rows N..NB of this wave's lines stay zero (branch-free substitution)
+    for (int i = n; i < 2 * 3 * (XS - N); i += 64) {
+        const int j = i / (3 * (XS - N)), rem = i % (3 * (XS - N));
+        sX[2 * w + j][rem / (XS - N)][N + rem % (XS - N)] = dcplx{0.0, 0.0};
+    }
+    lds_dma_wait();
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) in the (+,-,z) form,
+    //      from this wave's own lines (no workgroup barrier needed)
+    {
+        dcplx rr[2][3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
+            const dcplx ur = sX[q][0][nr], ut = sX[q][1][nr], uz = sX[q][2][nr];
+            if (a.kind == OPF_SOLVE_RAW) {
+                rr[j][0] = ur + ix(ut);
+                rr[j][1] = ur - ix(ut);
+                rr[j][2] = uz;
+            } else {
+                const int m = mp * (m0 + (q >> 1)), k = slot_k(q);
+                const double kap2 = a.alpha * k * a.alpha * k;
+                const dcplx dr = Lo.apply(sX[q][0], s0r), dt = Lo.apply(sX[q][1], s0r), dz = Le.apply(sX[q][2], s0r);
+                const dcplx up = ur + ix(ut), um = ur - ix(ut);
+                const double r2 = rinvr * rinvr;
+                const dcplx Lp = (dr + ix(dt)) - (double(m + 1) * double(m + 1) * r2 + kap2) * up;
+                const dcplx Lm = (dr - ix(dt)) - (double(m - 1) * double(m - 1) * r2 + kap2) * um;
+                const dcplx Lz = dz - (double(m) * double(m) * r2 + kap2) * uz;
+                rr[j][0] = a.inv_dt * up + a.aexp * Lp + (na[j][0] + ix(na[j][1]));
+                rr[j][1] = a.inv_dt * um + a.aexp * Lm + (na[j][0] - ix(na[j][1]));
+                rr[j][2] = a.inv_dt * uz + a.aexp * Lz + na[j][2];
+                if (m == 0 && k == 0) rr[j][2].x += a.force;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // every lane of the wave has read the u^n lines
+        if (n < N) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int q = 2 * w + j;
+                if (!slot_ok(q)) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sX[q][c][n] = rr[j][c];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- pressure-Poisson right-hand side div R (P(1) = 0), scaled by 1/U_ii
+    {
+        Row9 W1o;
+        W1o.load(t.d1, N, (mw + 1) & 1, nr);
+        const double* dvp = t.dinv + ((size_t)a.MU * K + (size_t)kabs * a.M + min(m0 + w, a.M - 1)) * NB;
+        const double dv = n < N ? dvp[n] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
             const int m = mp * (m0 + (q >> 1));
             const double kap = a.alpha * slot_k(q);
-            const int po = (m + 1) & 1;
             dcplx d = {0.0, 0.0};
-            if (n < N - 1 && !(m == 0 && kap == 0.0)) {
-                const dcplx ap = W1.apply(po, sX[q][0], s0) + (double(1 + m) * rinv) * sX[q][0][n];
-                const dcplx am = W1.apply(po, sX[q][1], s0) + (double(1 - m) * rinv) * sX[q][1][n];
+            if (slot_ok(q) && n < N - 1 && !(m == 0 && kap == 0.0)) {
+                const dcplx ap = W1o.apply(sX[q][0], s0r) + (double(1 + m) * rinvr) * sX[q][0][n];
+                const dcplx am = W1o.apply(sX[q][1], s0r) + (double(1 - m) * rinvr) * sX[q][1][n];
                 d = 0.5 * (ap + am) + kap * ix(sX[q][2][n]);
             }
-            sY[q][n] = d;
+            if (n < XS) sY[q][n] = dv * d;  // rows N..XS-1 zero (dv = 0 there)
+            if (n < XS - 64) sY[q][64 + n] = dcplx{0.0, 0.0};
         }
     }
     __syncthreads();
-    if (w == 0 && n < 2 * NSLOT) {
-        const int q = n >> 1;
-        if (slot_ok(q)) lds_solve<NB, NW>(sF + (q >> 1) * FS, &sY[q][0].x + (n & 1));
-    }
+    if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1))
+        lds_solve<NB, NW>(sF + (n >> 2) * FW, &sY[n >> 1][0].x + (n & 1));
     __syncthreads();
 
-    // ---- R -= grad P; (0,0): u_r = 0, real R_theta and R_z; stage H factors
-    {  // Helmholtz factors H_{mu,|k|}, mu_lo <= mu <= mu_hi
-        FactorStage<NB, NFH, 256, NW> helm;
-        helm.load(t.fac, (size_t)mu_lo * K + kabs, K, nfh, N, tid);
-        helm.store(sF, FS, nfh, N, tid);
-    }
-    if (n < N) {
-        const int s0 = s0r;
-        const double rinv = rinvr;
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
-            if (!slot_ok(q)) continue;
-            const int m = mp * (m0 + (q >> 1));
-            const double kap = a.alpha * slot_k(q);
-            if (n == N - 1) {
-                sX[q][0][n] = sX[q][1][n] = sX[q][2][n] = dcplx{0.0, 0.0};
-                if (m == 0 && kap == 0.0 && a.wall) {  // (0,0): Dirichlet values u_theta(1), u_z(1)
-                    const size_t w0 = (size_t)(K - 1) * 2, ws = (size_t)a.M * nk * 2;
-                    sX[q][0][n] = dcplx{a.wall[ws + w0], 0.0};
-                    sX[q][2][n] = dcplx{a.wall[2 * ws + w0], 0.0};
+    // ---- R -= grad P, scaled by 1/U_ii of each Helmholtz operator; (0,0):
+    //      u_r = 0, real R_theta and R_z.  The Helmholtz images that do not
+    //      cover the pressure columns are requested first.
+    const int nfh1 = min(nfh, 4);
+    dma_copy(t.img + ihelm * FW, sF, nfh1 * FW * 8, w, n);
+    {
+        Row9 W1e;
+        W1e.load(t.d1, N, mw & 1, nr);
+        // 1/U_ii of H_{m+1}, H_{|m-1|}, H_m at this row
+        const double* dvh = t.dinv + (size_t)kabs * a.MU * NB;
+        const double dvp = n < N ? dvh[(size_t)(mw + 1) * NB + n] : 0.0;
+        const double dvm = n < N ? dvh[(size_t)abs(mw - 1) * NB + n] : 0.0;
+        const double dvz = n < N ? dvh[(size_t)mw * NB + n] : 0.0;
+        if (n < N) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int q = 2 * w + j;
+                if (!slot_ok(q)) continue;
+                const int m = mp * (m0 + (q >> 1));
+                const double kap = a.alpha * slot_k(q);
+                dcplx r0 = sX[q][0][n], r1 = sX[q][1][n], r2 = sX[q][2][n];
+                const dcplx P = sY[q][n];
+                if (a.p_out && !(m == 0 && kap == 0.0))  // the pressure head before the influence correction
+                    store_c<double>(a.p_out, slot_off(q) + n, P);
+                if (n == N - 1) {
+                    r0 = r1 = r2 = dcplx{0.0, 0.0};
+                    if (m == 0 && kap == 0.0 && a.wall) {  // (0,0): Dirichlet values u_theta(1), u_z(1)
+                        const size_t w0 = (size_t)(K - 1) * 2, ws = (size_t)a.M * nk * 2;
+                        r0 = dcplx{a.wall[ws + w0], 0.0};
+                        r2 = dcplx{a.wall[2 * ws + w0], 0.0};
+                    }
+                } else if (m == 0 && kap == 0.0) {
+                    const dcplx d = r0 - r1;  // 2 i R_theta
+                    r0 = dcplx{0.5 * d.y, 0.0};
+                    r1 = dcplx{0.0, 0.0};
+                    r2 = dcplx{r2.x, 0.0};
+                } else {
+                    const dcplx dP = W1e.apply(sY[q], s0r);
+                    const dcplx mP = (double(m) * rinvr) * P;
+                    r0 = r0 - (dP - mP);
+                    r1 = r1 - (dP + mP);
+                    r2 = r2 - kap * ix(P);
                 }
-            } else if (m == 0 && kap == 0.0) {
-                const dcplx d = sX[q][0][n] - sX[q][1][n];  // 2 i R_theta
-                sX[q][0][n] = dcplx{0.5 * d.y, 0.0};
-                sX[q][1][n] = dcplx{0.0, 0.0};
-                sX[q][2][n] = dcplx{sX[q][2][n].x, 0.0};
-            } else {
-                const dcplx dP = W1.apply(m & 1, sY[q], s0);
-                const dcplx mP = (double(m) * rinv) * sY[q][n];
-                sX[q][0][n] = sX[q][0][n] - (dP - mP);
-                sX[q][1][n] = sX[q][1][n] - (dP + mP);
-                sX[q][2][n] = sX[q][2][n] - kap * ix(sY[q][n]);
+                // (0,0) solves u_theta with H_1 in the + slot and u_z with H_0
+                sX[q][0][n] = dvp * r0;
+                sX[q][1][n] = dvm * r1;
+                sX[q][2][n] = dvz * r2;
             }
         }
     }
+    __syncthreads();  // the pressure columns are read: the rest of the Helmholtz images may land there
+    if (nfh > nfh1)
+        dma_copy(t.img + (ihelm + nfh1) * FW, sF + nfh1 * FW, (nfh - nfh1) * FW * 8, w, n);
+    lds_dma_wait();
     __syncthreads();
     if (w == 0 && n < 6 * NSLOT) {
         const int q = n / 6, c = (n >> 1) % 3;
         if (slot_ok(q)) {
             const int m = mp * (m0 + (q >> 1));
             const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
-            lds_solve<NB, NW>(sF + (mu - mu_lo) * FS, &sX[q][c][0].x + (n & 1));
+            lds_solve<NB, NW>(sF + (mu - mu_lo) * FW, &sX[q][c][0].x + (n & 1));
         }
     }
     __syncthreads();
-
-    // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
-    // The influence data of this wave's m (one radial row per lane) is loaded
-    // now, so its latency overlaps the influence step of the first lanes.
+    // influence data of this wave's m (one radial row per lane)
     double hv[NHOM];
     {
         const double* h = t.hom + ((size_t)min(m0 + w, a.M - 1) * K + kabs) * NHOM * N;
 #pragma unroll
         for (int j = 0; j < NHOM; ++j) hv[j] = h[j * N + nr];
     }
+    // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
+    if (w == 1 && m0 == 0 && kabs == 0) {  // (0,0): flux of u_z,b over the radial quadrature
+        double qs = n < N ? t.quad[n] * sX[0][2][n].x : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) qs += __shfl_xor(qs, o, 64);
+        if (n == 0) {
+            const double gamma = a.fixed_flux ? (0.25 - qs) * t.qG_inv : 0.0;
+            sGam = gamma;
+            if (a.beta_out) *a.beta_out = gamma * a.Re * 0.25;
+        }
+    }
     if (tid < NSLOT && slot_ok(tid)) {
         const int q = tid;
         const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
         if (m == 0 && k == 0) {
-            double qs = 0.0;
-            for (int i = 0; i < N; ++i) qs += t.quad[i] * sX[q][2][i].x;
-            const double gamma = a.fixed_flux ? (0.25 - qs) * t.qG_inv : 0.0;
-            sGam = gamma;
-            if (a.beta_out) *a.beta_out = gamma * a.Re * 0.25;
         } else {
             const double kap = a.alpha * k;
             const int e = N - 1, s0 = t.s0[e];
@@ -459,55 +525,55 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
                 g[1] = g[1] - (br - ix(bt));
                 g[2] = g[2] - dcplx{a.wall[2 * ws + wi], a.wall[2 * ws + wi + 1]};
             }
-            const double* A = t.ainv + (((size_t)mi * nk + (k + K - 1)) * 16) * 2;
+            const double* A = sAi[q];
+            dcplx av[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 dcplx acc = {0.0, 0.0};
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc = acc + cm(dcplx{A[2 * (4 * i + j)], A[2 * (4 * i + j) + 1]}, g[j]);
-                sA[q][i] = dcplx{-acc.x, -acc.y};
+                av[i] = dcplx{-acc.x, -acc.y};
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) reinterpret_cast<dcplx*>(sAi[q])[i] = av[i];
         }
     }
     __syncthreads();
+    RowW W1;  // first-derivative weights of this lane's row, both parities (vorticity)
+    W1.load(t.d1, N, nr);
     if (n < N) {
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
             if (!slot_ok(q)) continue;
             const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
+            const size_t off = slot_off(q) + n;
+            const bool mirror = (mi == 0 && kabs > 0);  // m = 0: -k is the conjugate of +k
+            const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
+            dcplx up = sX[q][0][n], um = sX[q][1][n], uz = sX[q][2][n];
             if (m == 0 && k == 0) {
-                const double ut = sX[q][0][n].x;
-                const double uz = sX[q][2][n].x + sGam * t.green[n];
-                sX[q][0][n] = dcplx{0.0, ut};
-                sX[q][1][n] = dcplx{0.0, -ut};
-                sX[q][2][n] = dcplx{uz, 0.0};
-                sY[q][n] = dcplx{0.0, 0.0};
+                const double ut = up.x;
+                uz = dcplx{uz.x + sGam * t.green[n], 0.0};
+                up = dcplx{0.0, ut};
+                um = dcplx{0.0, -ut};
             } else {
                 const double kap = a.alpha * k;
                 const double h1p = hv[0], h1m = hv[1], qv = hv[2], h2 = hv[3], h3 = hv[4], h4 = hv[5], P1 = hv[6];
-                const dcplx a1 = sA[q][0], a2 = sA[q][1], a3 = sA[q][2], a4 = sA[q][3];
-                sX[q][0][n] = sX[q][0][n] + h1p * a1 + h2 * a2;
-                sX[q][1][n] = sX[q][1][n] + h1m * a1 + h3 * a3;
-                sX[q][2][n] = sX[q][2][n] - (kap * qv) * ix(a1) + h4 * a4;  // h1: u_z = -i kappa q
-                sY[q][n] = sY[q][n] + P1 * a1;
+                const dcplx* sa = reinterpret_cast<const dcplx*>(sAi[q]);
+                const dcplx a1 = sa[0], a2 = sa[1], a3 = sa[2], a4 = sa[3];
+                up = up + h1p * a1 + h2 * a2;
+                um = um + h1m * a1 + h3 * a3;
+                uz = uz - (kap * qv) * ix(a1) + h4 * a4;  // h1: u_z = -i kappa q
+                if (a.p_out) {
+                    const dcplx pp = load_c<double>(a.p_out, off) + P1 * a1;
+                    store_c<double>(a.p_out, off, pp);
+                    if (mirror) store_c<double>(a.p_out, offc, dcplx{pp.x, -pp.y});
+                }
             }
-        }
-    }
-    __syncthreads();
-
-    // ---- output u (r, theta, z); omega from the stored components --------
-    // omega is computed from (u_r, u_theta, u_z) as stored, so it equals what
-    // the standalone vorticity kernel gives for the same state.
-    if (n < N) {
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
-            if (!slot_ok(q)) continue;
-            const int mi = m0 + (q >> 1);
-            const bool mirror = (mi == 0 && kabs > 0);  // m = 0: -k is the conjugate of +k
-            const dcplx up = sX[q][0][n], um = sX[q][1][n], uz = sX[q][2][n];
+            // ---- output u (r, theta, z); omega from the stored components
             const dcplx ur = 0.5 * (up + um), ut = 0.5 * dcplx{(up - um).y, -(up - um).x};
             const dcplx uo[3] = {ur, ut, uz};
-            const size_t off = slot_off(q) + n;
-            const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const dcplx uc = {uo[c].x, -uo[c].y};
@@ -520,18 +586,21 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
                     if (mirror) store_c<float>(a.u_out32, c * S + offc, uc);
                 }
             }
-            if (a.p_out) {
-                const dcplx pp = sY[q][n];
-                store_c<double>(a.p_out, off, pp);
-                if (mirror) store_c<double>(a.p_out, offc, dcplx{pp.x, -pp.y});
-            }
+            if (a.p_out && m == 0 && k == 0) store_c<double>(a.p_out, off, dcplx{0.0, 0.0});
+            // omega is computed from (u_r, u_theta, u_z) as stored, so it
+            // equals what the standalone vorticity kernel gives for the same state
             sX[q][0][n] = ur + ix(ut);
             sX[q][1][n] = ur - ix(ut);
+            sX[q][2][n] = uz;
         }
     }
-    __syncthreads();
+    // the vorticity stencils read only this wave's own lines: a wave-level
+    // ordering suffices (no wait for the stores above)
+    __builtin_amdgcn_wave_barrier();
     if (a.w_out && n < N) {
-        for (int q = 2 * w; q < 2 * w + 2; ++q) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
             if (!slot_ok(q)) continue;
             const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
             const bool mirror = (mi == 0 && kabs > 0);
@@ -549,10 +618,18 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     }
 }
 
+// Three workgroups (12 waves) per compute unit where the LDS allows it (all
+// but the last nine rows narrow: about 53 KB at NB = 64), so at most 168
+// VGPRs; otherwise two.
+constexpr int solve_waves(int NB, int NW) { return NW == NB - 9 ? 3 : 2; }
 template <typename TNL, int NB, int NW>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a) { k_solve_body<TNL, NB, NW>(a); }
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(solve_waves(NB, NW), solve_waves(NB, NW))))
+void k_solve(SolveArgs a) {
+    k_solve_body<TNL, NB, NW>(a);
+}
 template <typename TNL, int NB, int NW>
-__global__ __launch_bounds__(256) void k_solve_b(const SolveArgs* __restrict__ aa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(solve_waves(NB, NW), solve_waves(NB, NW))))
+void k_solve_b(const SolveArgs* __restrict__ aa) {
     // the member's record is read in place (a private copy would live in scratch)
     k_solve_body<TNL, NB, NW>(aa[blockIdx.y]);
 }
@@ -633,20 +710,19 @@ hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int me
                               hipStream_t s) {
     const bool b = batch != nullptr;
     const dim3 grid(a.K * ((a.M + a.gm - 1) / a.gm), b ? members : 1), block(256);
-    // narrow-window rows: the largest compiled count that a.narrow allows
-    // (NB - 9 when N = NB, NB - 25 when N >= NB - 16, else none); the members
-    // of a batch share N and with it narrow
+    // NB rows and NW narrow rows as the factor images were written
+    // (solve_nb, solve_nw); the members of a batch share N and with it both
 #define OPF_SOLVE_LAUNCH(TNL, NB, NW)                                                   \
     if (b) hipLaunchKernelGGL((k_solve_b<TNL, NB, NW>), grid, block, 0, s, batch); \
     else hipLaunchKernelGGL((k_solve<TNL, NB, NW>), grid, block, 0, s, a);
 #define OPF_SOLVE_NW(TNL, NB)                                                       \
-    if (a.narrow >= NB - 9) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 9) }                 \
-    else if (a.narrow >= NB - 25) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 25) }          \
+    if (solve_nw(a.N, a.narrow) == NB - 9) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 9) }   \
+    else if (solve_nw(a.N, a.narrow) == NB - 25) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 25) } \
     else { OPF_SOLVE_LAUNCH(TNL, NB, 0) }
-    if (a.N <= 32) {
+    if (solve_nb(a.N) == 32) {
         if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 32) }
         else { OPF_SOLVE_NW(double, 32) }
-    } else if (a.N <= 48) {
+    } else if (solve_nb(a.N) == 48) {
         if (precision == OPF_MIXED) { OPF_SOLVE_NW(float, 48) }
         else { OPF_SOLVE_NW(double, 48) }
     } else {
