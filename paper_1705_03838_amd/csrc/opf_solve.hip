@@ -45,24 +45,6 @@ __device__ __forceinline__ dcplx stencil(const double* w, const dcplx* line, int
     return acc;
 }
 
-// Row weights of both axis parities held in registers (one lane = one row).
-struct RowW {
-    double e[W9], o[W9];
-    __device__ __forceinline__ void load(const double* tab, int N, int n) {
-#pragma unroll
-        for (int j = 0; j < W9; ++j) {
-            e[j] = tab[n * W9 + j];
-            o[j] = tab[(N + n) * W9 + j];
-        }
-    }
-    __device__ __forceinline__ dcplx apply(int par, const dcplx* line, int s0) const {
-        dcplx acc = {0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < W9; ++j) acc = acc + (par ? o[j] : e[j]) * line[s0 + j];
-        return acc;
-    }
-};
-
 template <typename T>
 __device__ __forceinline__ dcplx load_c(const void* base, size_t idx) {
     const T* p = reinterpret_cast<const T*>(base) + 2 * idx;
@@ -75,24 +57,17 @@ __device__ __forceinline__ void store_c(void* base, size_t idx, dcplx v) {
     p[1] = T(v.y);
 }
 
-// Vorticity at row n from (+,-,z) lines (Section 2.2, rotational form):
-//   w+ = (i m / r) u_z - i u_z' - kappa u+,   w- = (i m / r) u_z + i u_z' + kappa u-,
-//   w_z = -(i/2)[u+' + (1+m) u+ / r] + (i/2)[u-' + (1-m) u- / r].
-__device__ __forceinline__ void vort_row(const Tables& t, int N, int n, int m, double kap,
-                                         const dcplx* up, const dcplx* um, const dcplx* uz,
-                                         dcplx& wp, dcplx& wm, dcplx& wz) {
-    const int pe = m & 1, po = (m + 1) & 1;
-    const int s0 = t.s0[n];
-    const double rinv = t.rinv[n];
-    const dcplx duz = stencil(t.d1 + (pe * N + n) * W9, uz, s0);
-    const dcplx dup = stencil(t.d1 + (po * N + n) * W9, up, s0);
-    const dcplx dum = stencil(t.d1 + (po * N + n) * W9, um, s0);
-    const dcplx imz = (double(m) * rinv) * ix(uz[n]);
-    wp = imz - ix(duz) - kap * up[n];
-    wm = imz + ix(duz) + kap * um[n];
-    const dcplx ap = dup + (double(1 + m) * rinv) * up[n];
-    const dcplx am = dum + (double(1 - m) * rinv) * um[n];
-    wz = 0.5 * ix(am - ap);
+// Vorticity of mode (m, kappa) at one radial node, the cylindrical curl
+// (the rotational form of the nonlinear term, Section 2.2):
+//   w_r = (i m / r) u_z - i kappa u_theta,  w_theta = i kappa u_r - u_z',
+//   w_z = u_theta' + (u_theta - i m u_r) / r,
+// from the node's values and the radial derivatives duz = u_z' (parity of
+// m) and dut = u_theta' (parity of m +- 1).
+__device__ __forceinline__ void curl_row(dcplx duz, dcplx dut, double rinv, int m, double kap, dcplx ur, dcplx ut,
+                                         dcplx uz, dcplx& wr, dcplx& wt, dcplx& wz) {
+    wr = (double(m) * rinv) * ix(uz) - kap * ix(ut);
+    wt = kap * ix(ur) - duz;
+    wz = dut + rinv * (ut - double(m) * ix(ur));
 }
 
 // Substitution on one real right-hand side held in LDS (element i at
@@ -212,23 +187,6 @@ __device__ __forceinline__ void dma_copy(const void* src, void* dst, int nbytes,
 }
 
 constexpr int NSLOT = 8;     // modes per workgroup: up to 4 values of m, both signs of k
-
-// Vorticity at row n from (+,-,z) lines in LDS with the first-derivative
-// weights of both parities in registers.
-__device__ __forceinline__ void vort_row_w(const RowW& w1, double rinv, int s0, int n, int m, double kap,
-                                           const dcplx* up, const dcplx* um, const dcplx* uz,
-                                           dcplx& wp, dcplx& wm, dcplx& wz) {
-    const int pe = m & 1, po = (m + 1) & 1;
-    const dcplx duz = w1.apply(pe, uz, s0);
-    const dcplx dup = w1.apply(po, up, s0);
-    const dcplx dum = w1.apply(po, um, s0);
-    const dcplx imz = (double(m) * rinv) * ix(uz[n]);
-    wp = imz - ix(duz) - kap * up[n];
-    wm = imz + ix(duz) + kap * um[n];
-    const dcplx ap = dup + (double(1 + m) * rinv) * up[n];
-    const dcplx am = dum + (double(1 - m) * rinv) * um[n];
-    wz = 0.5 * ix(am - ap);
-}
 
 // 9 weights of one parity for row n, in registers.
 struct Row9 {
@@ -393,6 +351,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
                 if (!slot_ok(q)) continue;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) sX[q][c][n] = rr[j][c];
+                sY[q][n] = 0.5 * (rr[j][0] + rr[j][1]);  // R_r, for the divergence
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -404,18 +363,24 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         W1o.load(t.d1, N, (mw + 1) & 1, nr);
         const double* dvp = t.dinv + ((size_t)a.MU * K + (size_t)kabs * a.M + min(m0 + w, a.M - 1)) * NB;
         const double dv = n < N ? dvp[n] : 0.0;
+        // div R = d/dr R_r + [(1+m) R+ + (1-m) R-] / (2r) + i kappa R_z, R_r = (R+ + R-)/2
+        dcplx d[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int q = 2 * w + j;
             const int m = mp * (m0 + (q >> 1));
             const double kap = a.alpha * slot_k(q);
-            dcplx d = {0.0, 0.0};
-            if (slot_ok(q) && n < N - 1 && !(m == 0 && kap == 0.0)) {
-                const dcplx ap = W1o.apply(sX[q][0], s0r) + (double(1 + m) * rinvr) * sX[q][0][n];
-                const dcplx am = W1o.apply(sX[q][1], s0r) + (double(1 - m) * rinvr) * sX[q][1][n];
-                d = 0.5 * (ap + am) + kap * ix(sX[q][2][n]);
-            }
-            if (n < XS) sY[q][n] = dv * d;  // rows N..XS-1 zero (dv = 0 there)
+            d[j] = dcplx{0.0, 0.0};
+            if (slot_ok(q) && n < N - 1 && !(m == 0 && kap == 0.0))
+                d[j] = W1o.apply(sY[q], s0r) +
+                       (0.5 * rinvr) * (double(1 + m) * sX[q][0][n] + double(1 - m) * sX[q][1][n]) +
+                       kap * ix(sX[q][2][n]);
+        }
+        __builtin_amdgcn_wave_barrier();  // every lane of the wave has read the R_r lines
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = 2 * w + j;
+            if (n < XS) sY[q][n] = dv * d[j];  // rows N..XS-1 zero (dv = 0 there)
             if (n < XS - 64) sY[q][64 + n] = dcplx{0.0, 0.0};
         }
     }
@@ -540,8 +505,9 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         }
     }
     __syncthreads();
-    RowW W1;  // first-derivative weights of this lane's row, both parities (vorticity)
-    W1.load(t.d1, N, nr);
+    Row9 W1o, W1e;  // first-derivative weights of this lane's row, parities of m +- 1 and m (vorticity)
+    W1o.load(t.d1, N, (mw + 1) & 1, nr);
+    W1e.load(t.d1, N, mw & 1, nr);
     if (n < N) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -589,8 +555,8 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             if (a.p_out && m == 0 && k == 0) store_c<double>(a.p_out, off, dcplx{0.0, 0.0});
             // omega is computed from (u_r, u_theta, u_z) as stored, so it
             // equals what the standalone vorticity kernel gives for the same state
-            sX[q][0][n] = ur + ix(ut);
-            sX[q][1][n] = ur - ix(ut);
+            sX[q][0][n] = ur;
+            sX[q][1][n] = ut;
             sX[q][2][n] = uz;
         }
     }
@@ -604,9 +570,9 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             if (!slot_ok(q)) continue;
             const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
             const bool mirror = (mi == 0 && kabs > 0);
-            dcplx wp, wm, wz;
-            vort_row_w(W1, rinvr, s0r, n, m, a.alpha * k, sX[q][0], sX[q][1], sX[q][2], wp, wm, wz);
-            const dcplx wo[3] = {0.5 * (wp + wm), 0.5 * dcplx{(wp - wm).y, -(wp - wm).x}, wz};
+            dcplx wo[3];
+            curl_row(W1e.apply(sX[q][2], s0r), W1o.apply(sX[q][1], s0r), rinvr, m, a.alpha * k, sX[q][0][n],
+                     sX[q][1][n], sX[q][2][n], wo[0], wo[1], wo[2]);
             const size_t off = slot_off(q) + n;
             const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
 #pragma unroll
@@ -647,16 +613,19 @@ __global__ __launch_bounds__(64) void k_vorticity(AuxArgs a) {
     const size_t S = (size_t)a.M * nk * N;
     const size_t off = ((size_t)mi * nk + kk) * N + n;
     if (n < N) {
-        const dcplx ur = load_c<double>(a.u, off), ut = load_c<double>(a.u, S + off);
-        sL[0][n] = ur + ix(ut);
-        sL[1][n] = ur - ix(ut);
+        sL[0][n] = load_c<double>(a.u, off);
+        sL[1][n] = load_c<double>(a.u, S + off);
         sL[2][n] = load_c<double>(a.u, 2 * S + off);
     }
     __syncthreads();
     if (n < N) {
-        dcplx wp, wm, wz;
-        vort_row(a.t, N, n, m, a.alpha * (kk - (K - 1)), sL[0], sL[1], sL[2], wp, wm, wz);
-        const dcplx wo[3] = {0.5 * (wp + wm), 0.5 * dcplx{(wp - wm).y, -(wp - wm).x}, wz};
+        const int s0 = a.t.s0[n];
+        Row9 de, dod;
+        de.load(a.t.d1, N, m & 1, n);
+        dod.load(a.t.d1, N, (m + 1) & 1, n);
+        dcplx wo[3];
+        curl_row(de.apply(sL[2], s0), dod.apply(sL[1], s0), a.t.rinv[n], m, a.alpha * (kk - (K - 1)), sL[0][n],
+                 sL[1][n], sL[2][n], wo[0], wo[1], wo[2]);
         const bool mirror = a.mirror && mi == 0 && kk > K - 1;
         const size_t offc = ((size_t)mi * nk + (2 * (K - 1) - kk)) * N + n;
         for (int c = 0; c < 3; ++c) {
