@@ -561,20 +561,57 @@ opf_status opf_step_adaptive(opf_ctx* ctx, int32_t nsteps, const opf_dt_control*
  * its own slice. */
 typedef struct opf_ensemble opf_ensemble;
 opf_status opf_ensemble_workspace_size(const opf_params* members, int32_t count, size_t* bytes);
+
+/* Tile shapes of one class of equal (N, M, K, mp, precision): gm consecutive
+ * m per radial-solve workgroup (1, 2 or 4 with mp (gm - 1) + 3 <= 6), tz
+ * axial points per theta-stage workgroup (2, 4 or 8) and ztile radial lines
+ * per z-transform workgroup (4, 8 or 16), each while the longer radix pass
+ * of the transform length fits the workgroup (tz r <= 64, ztile r <= 128,
+ * r = 12 for lengths 144 and 192 ... 3 for 6).  Results never depend on the
+ * tiles, only the speed.  members and us_per_step are informative. */
+typedef struct {
+    int32_t N, M, K, mp, precision;
+    int32_t members;
+    int32_t gm, tz, ztile;
+    double us_per_step;
+} opf_tiles;
+
+/* tune_cache_json: NULL (default tiles), or the path of a tile cache written
+ * by opf_autotune, opf_tile_cache_write or saved from opf_ensemble_tune:
+ * classes found in it take its tiles.  A file that cannot be read or
+ * parsed, or that holds inadmissible tiles, gives OPF_E_INVALID. */
 opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* dev_workspace,
-                               size_t bytes, void* hip_stream, opf_ensemble** out);
+                               size_t bytes, void* hip_stream, const char* tune_cache_json, opf_ensemble** out);
 opf_status opf_ensemble_destroy(opf_ensemble* ens);
 /* The context of member i (set/get state, diagnostics through the single-
  * trajectory calls; do not destroy it). */
 opf_status opf_ensemble_member(opf_ensemble* ens, int32_t i, opf_ctx** out);
 /* nsteps predictor-corrector steps of every member; one graph launch per step. */
 opf_status opf_ensemble_step(opf_ensemble* ens, int32_t nsteps);
-/* Autotuner: for each class, time nsteps batched steps for every admissible
- * radial-solve tile (1, 2 or 4 consecutive m per workgroup), keep the
- * fastest, and write a JSON report into `report` (host, may be NULL).
- * Advances the members' states by the timed steps (cost is data-independent:
- * tune before setting the states to be used).  Synchronises. */
+/* Autotuner (the batched step of an ensemble, one graph launch per step;
+ * not in the paper): for each class, time nsteps batched steps of the class
+ * over the admissible values of each tile dimension in turn (gm, then tz,
+ * then ztile, each from the best so far), keep the fastest, and write the
+ * choice as a tile cache (JSON, the format opf_ensemble_create reads, with
+ * every timed candidate) into `report` (host, may be NULL).  Members that
+ * have a state advance by the timed steps (the cost is data-independent);
+ * members without one run on laminar flow and have no state afterwards.
+ * Synchronises. */
 opf_status opf_ensemble_tune(opf_ensemble* ens, int32_t nsteps, char* report, size_t report_bytes);
+/* The current tiles of each class (in order of first member): *nclasses
+ * classes, the first `capacity` written to out (host). */
+opf_status opf_ensemble_tiles(const opf_ensemble* ens, opf_tiles* out, int32_t capacity, int32_t* nclasses);
+/* Offline tuning: times each of the ncls classes as a batch of 8 equal
+ * members (opf_ensemble_tune, 5 steps per candidate) and writes the tile
+ * cache to the file cache_json_out.  This call allocates: one device
+ * workspace (opf_ensemble_workspace_size of the 8 ncls members) and one
+ * stream on the current device, freed before it returns.  Synchronises. */
+opf_status opf_autotune(const opf_params* cls, int32_t ncls, const char* cache_json_out);
+/* Tile cache files (host only): write n entries (OPF_E_INVALID for
+ * inadmissible tiles or an unwritable path); read one back, *n entries,
+ * the first `capacity` into out. */
+opf_status opf_tile_cache_write(const opf_tiles* tiles, int32_t n, const char* path);
+opf_status opf_tile_cache_read(const char* path, opf_tiles* out, int32_t capacity, int32_t* n);
 const char* opf_ensemble_last_error(const opf_ensemble* ens);
 /* opf_probe_pairs with the probes' trajectories run as ensemble members:
  * every member must have the same parameters (one class, equal nodes); the

@@ -27,6 +27,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_forward", "opf_mlp_gradient", "opf_mlp_train", "opf_mlp_pair_gradient",
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
+           "opf_ensemble_tiles", "opf_autotune", "opf_tile_cache_write", "opf_tile_cache_read",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
            "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
            "opf_hessenberg_eigvals", "opf_set_rotation", "opf_shoot_workspace_size", "opf_shoot_solve", "opf_set_wall_velocity",
@@ -107,6 +108,15 @@ class opf_mlp_config(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float), ("lr_final", ctypes.c_float)]
 
 
+class opf_tiles(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("K", ctypes.c_int32), ("mp", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("members", ctypes.c_int32), ("gm", ctypes.c_int32),
+                ("tz", ctypes.c_int32), ("ztile", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class OpfError(RuntimeError):
     def __init__(self, status, msg=""):
         super().__init__(f"opf status {status}: {msg}")
@@ -163,7 +173,11 @@ def load_library(path=LIB_PATH):
         "opf_precondition": ([vp, vp, vp, vp], i32),
         "opf_mlp_last_error": ([vp], ctypes.c_char_p),
         "opf_ensemble_workspace_size": ([vp, i32, P(ctypes.c_size_t)], i32),
-        "opf_ensemble_create": ([vp, i32, vp, ctypes.c_size_t, vp, P(vp)], i32),
+        "opf_ensemble_create": ([vp, i32, vp, ctypes.c_size_t, vp, ctypes.c_char_p, P(vp)], i32),
+        "opf_ensemble_tiles": ([vp, P(opf_tiles), i32, P(i32)], i32),
+        "opf_autotune": ([vp, i32, ctypes.c_char_p], i32),
+        "opf_tile_cache_write": ([P(opf_tiles), i32, ctypes.c_char_p], i32),
+        "opf_tile_cache_read": ([ctypes.c_char_p, P(opf_tiles), i32, P(i32)], i32),
         "opf_ensemble_destroy": ([vp], i32),
         "opf_ensemble_member": ([vp, i32, P(vp)], i32),
         "opf_ensemble_step": ([vp, i32], i32),
@@ -210,6 +224,44 @@ def hookstep_solve(Hb, beta, delta):
     if st != OPF_OK:
         raise OpfError(st, lib.opf_status_string(st).decode())
     return y, mu.value, r.value
+
+
+def autotune(classes, path):
+    """Offline tile tuning of the given classes (keyword dicts for
+    make_params), written as a tile cache to `path` (opf_autotune)."""
+    lib = load_library()
+    n = len(classes)
+    params = (opf_params * n)(*[make_params(**c) for c in classes])
+    st = lib.opf_autotune(params, n, os.fsencode(path))
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+
+
+def tile_cache_write(entries, path):
+    """Write tile-cache entries (dicts with N, M, K, mp, precision, gm, tz,
+    ztile) to `path` (host only)."""
+    lib = load_library()
+    arr = (opf_tiles * len(entries))()
+    for i, e in enumerate(entries):
+        for k in ("N", "M", "K", "mp", "precision", "gm", "tz", "ztile"):
+            setattr(arr[i], k, int(e[k]))
+    st = lib.opf_tile_cache_write(arr, len(entries), os.fsencode(path))
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+
+
+def tile_cache_read(path):
+    """Entries of a tile cache file, as dicts (host only)."""
+    lib = load_library()
+    n = ctypes.c_int32()
+    st = lib.opf_tile_cache_read(os.fsencode(path), None, 0, ctypes.byref(n))
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+    arr = (opf_tiles * max(n.value, 1))()
+    st = lib.opf_tile_cache_read(os.fsencode(path), arr, n.value, ctypes.byref(n))
+    if st != OPF_OK:
+        raise OpfError(st, lib.opf_status_string(st).decode())
+    return [arr[i].as_dict() for i in range(n.value)]
 
 
 def make_params(N=24, M=8, K=8, mp=1, alpha=1.25, Re=2400.0, dt=0.01, c=0.5, n_corr=1,
@@ -569,7 +621,7 @@ class Ensemble:
     """Independent trajectories stepped together (one graph launch per step).
     `members` is a list of keyword dicts for make_params."""
 
-    def __init__(self, members, stream=None):
+    def __init__(self, members, stream=None, tune_cache=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -597,6 +649,7 @@ class Ensemble:
         ens = ctypes.c_void_p()
         self._check(self.lib.opf_ensemble_create(self.params, n, ctypes.c_void_p(ptr), nbytes.value,
                                                  ctypes.c_void_p(self.stream.cuda_stream),
+                                                 None if tune_cache is None else os.fsencode(tune_cache),
                                                  ctypes.byref(ens)))
         self.ens = ens
         self.members = [_Member(self, i, self.params[i]) for i in range(n)]
@@ -612,10 +665,20 @@ class Ensemble:
         self._check(self.lib.opf_ensemble_step(self.ens, int(n)))
 
     def tune(self, nsteps=5):
+        """Tile autotuning (see opf_ensemble_tune); returns the tile cache as
+        a dict (json.dump it to a file for Ensemble(tune_cache=...))."""
         import json
-        buf = ctypes.create_string_buffer(1 << 16)
+        buf = ctypes.create_string_buffer(1 << 18)
         self._check(self.lib.opf_ensemble_tune(self.ens, int(nsteps), buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    def tiles(self):
+        """Current tile shapes per class, as dicts."""
+        n = ctypes.c_int32()
+        self._check(self.lib.opf_ensemble_tiles(self.ens, None, 0, ctypes.byref(n)))
+        out = (opf_tiles * max(n.value, 1))()
+        self._check(self.lib.opf_ensemble_tiles(self.ens, out, n.value, ctypes.byref(n)))
+        return [out[i].as_dict() for i in range(n.value)]
 
     def close(self):
         if getattr(self, "ens", None):

@@ -22,6 +22,7 @@ struct opf_ctx {
     std::vector<double> r, rinv, quad, d1, d2;  // host copies
     std::vector<int> s0;
     int nk = 0, MU = 0, nfac = 0, gm = 1;
+    int tz = DEFAULT_TZ, ztile = DEFAULT_ZTILE;  // transform tile shapes
     int narrow = 0;  // see SolveArgs::narrow
     double qG_inv = 0.0;
     hipStream_t stream = nullptr;
@@ -300,6 +301,21 @@ __global__ void k_shift_sub(const double* __restrict__ u, const double* __restri
     F[2 * i + 1] = ur * sn + ui * c - x[2 * i + 1];
 }
 
+// Laminar flow u_z(0,0) = 1 - r^2, every other coefficient zero (complex128
+// external layout), in u and its FP32 shadow.
+__global__ void k_laminar(double* __restrict__ u, float* __restrict__ u32, const double* __restrict__ r, int N,
+                          int nk, int K, size_t total) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t S = total / 3, e = i % S;
+    const bool lam = i / S == 2 && e / N == (size_t)(K - 1);  // m = 0, k = 0 of u_z
+    const double v = lam ? 1.0 - r[e % N] * r[e % N] : 0.0;
+    u[2 * i] = v;
+    u[2 * i + 1] = 0.0;
+    u32[2 * i] = float(v);
+    u32[2 * i + 1] = 0.0f;
+}
+
 // Axial derivative d_z x: out_k = i alpha k x_k (complex128 external layout).
 __global__ void k_ddz(const double* __restrict__ x, double* __restrict__ out, int N, int nk, int K, size_t total,
                       double alpha) {
@@ -442,6 +458,8 @@ NLArgs nl_args(const opf_ctx* c, const void* u, const void* w, void* out) {
     a.scale = 1.0 / (9.0 * c->p.K * c->p.M);
     for (int i = 0; i < 3; ++i) a.rot[i] = c->rot[i];
     a.rotating = c->rot[0] != 0.0 || c->rot[1] != 0.0 || c->rot[2] != 0.0;
+    a.tz = c->tz;
+    a.ztile = c->ztile;
     return a;
 }
 
@@ -2202,6 +2220,7 @@ opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift
 // class is one captured graph.
 struct EnsClass {
     int N = 0, M = 0, K = 0, mp = 0, precision = 0, gm = 1;
+    int tz = DEFAULT_TZ, ztile = DEFAULT_ZTILE;  // transform tile shapes
     std::vector<int> idx;                   // member indices
     NLArgs* nl[2] = {nullptr, nullptr};     // device argument records, NL(u^n), NL(u^p)
     SolveArgs* sv[2] = {nullptr, nullptr};  // predictor, corrector
@@ -2218,6 +2237,10 @@ struct opf_ensemble {
 
 namespace {
 
+size_t ens_args_bytes(int count) {
+    return (size_t)count * (2 * sizeof(NLArgs) + 2 * sizeof(SolveArgs) + 2 * 64);
+}
+
 size_t ens_layout(const opf_params* mem, int count, std::vector<size_t>* offs, std::vector<size_t>* sizes) {
     size_t o = 0;
     for (int i = 0; i < count; ++i) {
@@ -2227,8 +2250,9 @@ size_t ens_layout(const opf_params* mem, int count, std::vector<size_t>* offs, s
         if (sizes) sizes->push_back(b);
         o = align_up(o + b);
     }
-    // argument records: at most 2 NL + 2 solve records per member
-    o = align_up(o + (size_t)count * (2 * sizeof(NLArgs) + 2 * sizeof(SolveArgs)) + 1024);
+    // argument records: 2 NL + 2 solve records per member, each class's two
+    // groups padded to 64 bytes (at most count classes)
+    o = align_up(o + ens_args_bytes(count));
     return o;
 }
 
@@ -2239,6 +2263,8 @@ opf_status ens_upload(opf_ensemble* e, EnsClass& k, hipStream_t s) {
     for (int i : k.idx) {
         opf_ctx* c = e->members[i];
         c->gm = k.gm;
+        c->tz = k.tz;
+        c->ztile = k.ztile;
         const bool mixed = c->p.precision == OPF_MIXED;
         const void* uin = mixed ? (const void*)c->u32 : (const void*)c->u;
         const void* upin = mixed ? (const void*)c->up32 : (const void*)c->up;
@@ -2273,6 +2299,188 @@ opf_status ens_upload(opf_ensemble* e, EnsClass& k, hipStream_t s) {
     return OPF_OK;
 }
 
+// ---- tile cache (JSON) --------------------------------------------------
+// {"version": 1, "classes": [{"N": .., "M": .., "K": .., "mp": .., "precision": ..,
+//   "members": .., "gm": .., "tz": .., "ztile": .., "us_per_step": ..,
+//   "candidates": [{"gm": .., "tz": .., "ztile": .., "us_per_step": ..}, ...]}, ...]}
+// A minimal reader: objects, arrays, numbers, strings and literals.
+struct JVal {
+    enum Kind { NUL, NUM, STR, ARR, OBJ, BOOL } kind = NUL;
+    double num = 0.0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::vector<std::pair<std::string, JVal>> obj;
+    const JVal* get(const char* key) const {
+        for (const auto& kv : obj)
+            if (kv.first == key) return &kv.second;
+        return nullptr;
+    }
+};
+
+struct JParser {
+    const char* p;
+    const char* end;
+    bool ok = true;
+    void ws() {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) ++p;
+    }
+    bool lit(const char* w) {
+        const size_t n = std::strlen(w);
+        if ((size_t)(end - p) >= n && std::strncmp(p, w, n) == 0) {
+            p += n;
+            return true;
+        }
+        return false;
+    }
+    JVal value(int depth) {
+        JVal v;
+        ws();
+        if (!ok || p >= end || depth > 32) {
+            ok = false;
+            return v;
+        }
+        if (*p == '{') {
+            v.kind = JVal::OBJ;
+            ++p;
+            ws();
+            if (p < end && *p == '}') {
+                ++p;
+                return v;
+            }
+            while (ok) {
+                ws();
+                JVal k = value(depth + 1);
+                if (k.kind != JVal::STR) { ok = false; break; }
+                ws();
+                if (p >= end || *p != ':') { ok = false; break; }
+                ++p;
+                v.obj.emplace_back(k.str, value(depth + 1));
+                ws();
+                if (p < end && *p == ',') { ++p; continue; }
+                if (p < end && *p == '}') { ++p; break; }
+                ok = false;
+            }
+        } else if (*p == '[') {
+            v.kind = JVal::ARR;
+            ++p;
+            ws();
+            if (p < end && *p == ']') {
+                ++p;
+                return v;
+            }
+            while (ok) {
+                v.arr.push_back(value(depth + 1));
+                ws();
+                if (p < end && *p == ',') { ++p; continue; }
+                if (p < end && *p == ']') { ++p; break; }
+                ok = false;
+            }
+        } else if (*p == '"') {
+            v.kind = JVal::STR;
+            ++p;
+            while (p < end && *p != '"') {
+                if (*p == '\\' && p + 1 < end) ++p;
+                v.str += *p++;
+            }
+            if (p >= end) ok = false;
+            else ++p;
+        } else if (lit("true")) {
+            v.kind = JVal::BOOL;
+            v.num = 1.0;
+        } else if (lit("false")) {
+            v.kind = JVal::BOOL;
+        } else if (lit("null")) {
+        } else {
+            char* q = nullptr;
+            v.num = std::strtod(p, &q);
+            if (q == p) ok = false;
+            else {
+                v.kind = JVal::NUM;
+                p = q;
+            }
+        }
+        return v;
+    }
+};
+
+struct TileChoice {
+    int N, M, K, mp, precision, gm, tz, ztile;
+};
+
+bool tiles_ok(const TileChoice& t) {
+    return gm_ok(t.gm, t.mp) && t.gm <= t.M && tz_ok(t.tz, t.M) && ztile_ok(t.ztile, t.K);
+}
+
+// Parse a tile cache; false (with msg) on a malformed file or an
+// inadmissible entry.
+bool parse_tile_cache(const std::string& text, std::vector<TileChoice>& out, std::string& msg) {
+    JParser ps{text.data(), text.data() + text.size()};
+    const JVal root = ps.value(0);
+    ps.ws();
+    if (!ps.ok || ps.p != ps.end || root.kind != JVal::OBJ) {
+        msg = "tile cache: not a JSON object";
+        return false;
+    }
+    const JVal* cls = root.get("classes");
+    if (!cls || cls->kind != JVal::ARR) {
+        msg = "tile cache: no \"classes\" array";
+        return false;
+    }
+    for (const JVal& c : cls->arr) {
+        TileChoice t{};
+        int* f[] = {&t.N, &t.M, &t.K, &t.mp, &t.precision, &t.gm, &t.tz, &t.ztile};
+        const char* names[] = {"N", "M", "K", "mp", "precision", "gm", "tz", "ztile"};
+        for (int i = 0; i < 8; ++i) {
+            const JVal* v = c.kind == JVal::OBJ ? c.get(names[i]) : nullptr;
+            if (!v || v->kind != JVal::NUM || v->num != (double)(int)v->num) {
+                msg = std::string("tile cache: class entry without integer \"") + names[i] + "\"";
+                return false;
+            }
+            *f[i] = (int)v->num;
+        }
+        if (!tiles_ok(t)) {
+            msg = "tile cache: inadmissible tiles for class N=" + std::to_string(t.N) + " M=" + std::to_string(t.M) +
+                  " K=" + std::to_string(t.K);
+            return false;
+        }
+        out.push_back(t);
+    }
+    return true;
+}
+
+std::string tile_cache_json(const std::vector<opf_tiles>& t, const std::vector<std::string>& candidates) {
+    std::string js = "{\"version\": 1, \"classes\": [";
+    for (size_t i = 0; i < t.size(); ++i) {
+        char buf[320];
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"N\": %d, \"M\": %d, \"K\": %d, \"mp\": %d, \"precision\": %d, \"members\": %d, "
+                      "\"gm\": %d, \"tz\": %d, \"ztile\": %d, \"us_per_step\": %.3f",
+                      i ? ", " : "", t[i].N, t[i].M, t[i].K, t[i].mp, t[i].precision, t[i].members, t[i].gm, t[i].tz,
+                      t[i].ztile, t[i].us_per_step);
+        js += buf;
+        if (i < candidates.size()) js += ", \"candidates\": [" + candidates[i] + "]";
+        js += "}";
+    }
+    return js + "]}";
+}
+
+bool read_file(const char* path, std::string& out) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return false;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) out.append(buf, n);
+    std::fclose(f);
+    return true;
+}
+
+bool write_file(const char* path, const std::string& text) {
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return false;
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    return std::fclose(f) == 0 && ok;
+}
+
 // One predictor-corrector step of class k (all members, batched launches).
 hipError_t ens_enqueue_class(opf_ensemble* e, const EnsClass& k, hipStream_t s) {
     opf_ctx* c0 = e->members[k.idx[0]];
@@ -2305,9 +2513,14 @@ opf_status opf_ensemble_workspace_size(const opf_params* members, int32_t count,
 }
 
 opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* ws, size_t bytes,
-                               void* hip_stream, opf_ensemble** out) {
+                               void* hip_stream, const char* tune_cache_json, opf_ensemble** out) {
     if (!members || count < 1 || !ws || !out) return OPF_E_INVALID;
     *out = nullptr;
+    std::vector<TileChoice> cached;
+    if (tune_cache_json) {
+        std::string text, msg;
+        if (!read_file(tune_cache_json, text) || !parse_tile_cache(text, cached, msg)) return OPF_E_INVALID;
+    }
     std::vector<size_t> offs, sizes;
     const size_t need = ens_layout(members, count, &offs, &sizes);
     if (!need) return OPF_E_INVALID;
@@ -2344,11 +2557,16 @@ opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* w
             k->mp = p.mp;
             k->precision = p.precision;
             k->gm = default_gm(p.mp);
+            for (const TileChoice& t : cached)  // tiles from the cache, where it has the class
+                if (t.N == p.N && t.M == p.M && t.K == p.K && t.mp == p.mp && t.precision == p.precision) {
+                    k->gm = t.gm;
+                    k->tz = t.tz;
+                    k->ztile = t.ztile;
+                }
         }
         k->idx.push_back(i);
     }
-    unsigned char* args = base + ens_layout(members, count, nullptr, nullptr) -
-                          align_up((size_t)count * (2 * sizeof(NLArgs) + 2 * sizeof(SolveArgs)) + 1024);
+    unsigned char* args = base + ens_layout(members, count, nullptr, nullptr) - align_up(ens_args_bytes(count));
     size_t o = 0;
     for (EnsClass& k : e->classes) {
         const size_t n = k.idx.size();
@@ -2489,21 +2707,33 @@ opf_status opf_probe_pairs_ensemble(opf_ensemble* e, const void* x_dev, double T
 
 opf_status opf_ensemble_tune(opf_ensemble* e, int32_t nsteps, char* report, size_t report_bytes) {
     if (!e || nsteps < 1) return OPF_E_INVALID;
-    std::string js = "{\"classes\": [";
+    // members without a state run on laminar flow while the tiles are timed
+    // (finite, representative data) and have no state afterwards
+    std::vector<opf_ctx*> filled;
+    for (opf_ctx* c : e->members)
+        if (!c->have_state) {
+            const size_t total = 3 * field_entries(c);
+            hipLaunchKernelGGL(k_laminar, dim3((total + 255) / 256), dim3(256), 0, e->stream, c->u, c->u32,
+                               c->t.r, c->p.N, c->nk, c->p.K, total);
+            HIPCHK(c, hipGetLastError());
+            opf_status st = refresh_derived(c);
+            if (st != OPF_OK) return st;
+            filled.push_back(c);
+        }
+    std::vector<opf_tiles> chosen;
+    std::vector<std::string> cands;
     for (size_t ci = 0; ci < e->classes.size(); ++ci) {
         EnsClass& k = e->classes[ci];
-        double best = 1e300;
-        int best_gm = k.gm;
+        opf_ctx* c0 = e->members[k.idx[0]];
         std::string cand;
-        for (int gm = 1; gm <= 4; gm *= 2) {
-            if (!gm_ok(gm, k.mp) || gm > k.M) continue;
-            k.gm = gm;
+        // time one setting: nsteps batched steps of the class after a warm-up step
+        auto time_it = [&](double* us) -> opf_status {
             opf_status st = ens_upload(e, k, e->stream);
             if (st != OPF_OK) return st;
             hipEvent_t a, b;
-            HIPCHK(e->members[k.idx[0]], hipEventCreate(&a));
-            HIPCHK(e->members[k.idx[0]], hipEventCreate(&b));
-            hipError_t he = ens_enqueue_class(e, k, e->stream);  // warm-up
+            HIPCHK(c0, hipEventCreate(&a));
+            HIPCHK(c0, hipEventCreate(&b));
+            hipError_t he = ens_enqueue_class(e, k, e->stream);
             if (he == hipSuccess) he = hipEventRecord(a, e->stream);
             for (int t = 0; t < nsteps && he == hipSuccess; ++t) he = ens_enqueue_class(e, k, e->stream);
             if (he == hipSuccess) he = hipEventRecord(b, e->stream);
@@ -2516,36 +2746,112 @@ opf_status opf_ensemble_tune(opf_ensemble* e, int32_t nsteps, char* report, size
                 e->err = std::string("tune: ") + hipGetErrorString(he);
                 return OPF_E_HIP;
             }
-            const double us = 1e3 * ms / nsteps;
-            char buf[64];
-            std::snprintf(buf, sizeof buf, "%s{\"gm\": %d, \"us_per_step\": %.3f}", cand.empty() ? "" : ", ", gm, us);
+            *us = 1e3 * ms / nsteps;
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "%s{\"gm\": %d, \"tz\": %d, \"ztile\": %d, \"us_per_step\": %.3f}",
+                          cand.empty() ? "" : ", ", k.gm, k.tz, k.ztile, *us);
             cand += buf;
-            if (us < best) {
-                best = us;
-                best_gm = gm;
+            return OPF_OK;
+        };
+        // one tile dimension at a time, each from the best of the previous
+        double best = 1e300;
+        const int gms[] = {1, 2, 4}, tzs[] = {2, 4, 8}, zts[] = {4, 8, 16};
+        for (int dim = 0; dim < 3; ++dim) {
+            const int* vals = dim == 0 ? gms : dim == 1 ? tzs : zts;
+            int* knob = dim == 0 ? &k.gm : dim == 1 ? &k.tz : &k.ztile;
+            const int keep = *knob;
+            int pick = keep;
+            for (int i = 0; i < 3; ++i) {
+                *knob = vals[i];
+                const bool ok = dim == 0 ? gm_ok(k.gm, k.mp) && k.gm <= k.M
+                              : dim == 1 ? tz_ok(k.tz, k.M) : ztile_ok(k.ztile, k.K);
+                if (!ok) continue;
+                double us = 0.0;
+                const opf_status st = time_it(&us);
+                if (st != OPF_OK) return st;
+                if (us < best) {
+                    best = us;
+                    pick = vals[i];
+                }
             }
+            *knob = pick;
+            (void)keep;
         }
-        k.gm = best_gm;
         k.tuned_us = best;
         const opf_status st = ens_upload(e, k, e->stream);
         if (st != OPF_OK) return st;
-        char head[256];
-        std::snprintf(head, sizeof head,
-                      "%s{\"N\": %d, \"M\": %d, \"K\": %d, \"mp\": %d, \"precision\": %d, \"members\": %d, "
-                      "\"gm\": %d, \"us_per_step\": %.3f, \"candidates\": [",
-                      ci ? ", " : "", k.N, k.M, k.K, k.mp, k.precision, (int)k.idx.size(), k.gm, best);
-        js += head + cand + "]}";
+        chosen.push_back(opf_tiles{k.N, k.M, k.K, k.mp, k.precision, (int)k.idx.size(), k.gm, k.tz, k.ztile, best});
+        cands.push_back(cand);
     }
-    js += "]}";
+    for (opf_ctx* c : filled) c->have_state = false;
     if (e->graph) {  // recapture with the chosen tiles
         (void)hipGraphExecDestroy(e->graph);
         e->graph = nullptr;
     }
+    const std::string js = tile_cache_json(chosen, cands);
     if (report && report_bytes) {
         std::strncpy(report, js.c_str(), report_bytes - 1);
         report[report_bytes - 1] = 0;
     }
     return OPF_OK;
+}
+
+opf_status opf_ensemble_tiles(const opf_ensemble* e, opf_tiles* out, int32_t capacity, int32_t* nclasses) {
+    if (!e || !nclasses || capacity < 0 || (capacity > 0 && !out)) return OPF_E_INVALID;
+    *nclasses = (int32_t)e->classes.size();
+    for (int i = 0; i < std::min<int>(capacity, (int)e->classes.size()); ++i) {
+        const EnsClass& k = e->classes[i];
+        out[i] = opf_tiles{k.N, k.M, k.K, k.mp, k.precision, (int)k.idx.size(), k.gm, k.tz, k.ztile, k.tuned_us};
+    }
+    return OPF_OK;
+}
+
+opf_status opf_tile_cache_write(const opf_tiles* t, int32_t n, const char* path) {
+    if (!t || n < 0 || !path) return OPF_E_INVALID;
+    std::vector<opf_tiles> v(t, t + n);
+    for (const opf_tiles& x : v)
+        if (!tiles_ok(TileChoice{x.N, x.M, x.K, x.mp, x.precision, x.gm, x.tz, x.ztile})) return OPF_E_INVALID;
+    return write_file(path, tile_cache_json(v, {})) ? OPF_OK : OPF_E_INVALID;
+}
+
+opf_status opf_tile_cache_read(const char* path, opf_tiles* out, int32_t capacity, int32_t* n) {
+    if (!path || !n || capacity < 0 || (capacity > 0 && !out)) return OPF_E_INVALID;
+    std::string text, msg;
+    std::vector<TileChoice> v;
+    if (!read_file(path, text) || !parse_tile_cache(text, v, msg)) return OPF_E_INVALID;
+    *n = (int32_t)v.size();
+    for (int i = 0; i < std::min<int>(capacity, (int)v.size()); ++i)
+        out[i] = opf_tiles{v[i].N, v[i].M, v[i].K, v[i].mp, v[i].precision, 0, v[i].gm, v[i].tz, v[i].ztile, 0.0};
+    return OPF_OK;
+}
+
+opf_status opf_autotune(const opf_params* cls, int32_t ncls, const char* cache_json_out) {
+    if (!cls || ncls < 1 || !cache_json_out) return OPF_E_INVALID;
+    constexpr int B = 8;  // members timed per class
+    std::vector<opf_params> mem;
+    for (int i = 0; i < ncls; ++i)
+        for (int j = 0; j < B; ++j) mem.push_back(cls[i]);
+    size_t bytes = 0;
+    opf_status st = opf_ensemble_workspace_size(mem.data(), (int32_t)mem.size(), &bytes);
+    if (st != OPF_OK) return st;
+    void* ws = nullptr;
+    hipStream_t s = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) return OPF_E_NOMEM;
+    if (hipStreamCreate(&s) != hipSuccess) {
+        (void)hipFree(ws);
+        return OPF_E_HIP;
+    }
+    opf_ensemble* e = nullptr;
+    st = opf_ensemble_create(mem.data(), (int32_t)mem.size(), ws, bytes, s, nullptr, &e);
+    std::string js(1 << 16, '\0');
+    if (st == OPF_OK) st = opf_ensemble_tune(e, 5, &js[0], js.size());
+    if (e) opf_ensemble_destroy(e);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    (void)hipFree(ws);
+    if (st != OPF_OK) return st;
+    js.resize(std::strlen(js.c_str()));
+    return write_file(cache_json_out, js) ? OPF_OK : OPF_E_INVALID;
 }
 
 const char* opf_ensemble_last_error(const opf_ensemble* e) { return e ? e->err.c_str() : "null ensemble"; }

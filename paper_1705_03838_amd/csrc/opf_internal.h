@@ -40,7 +40,6 @@ __host__ __device__ constexpr int solve_nw(int N, int narrow) {
     return narrow >= solve_nb(N) - 9 ? solve_nb(N) - 9 : (narrow >= solve_nb(N) - 25 ? solve_nb(N) - 25 : 0);
 }
 constexpr int NMAX = 64;  // radial points handled by one solve workgroup
-constexpr int TILE = 8;   // radial lines per z-transform workgroup
 
 // Complex number used by the kernels (interleaved re/im, same layout as
 // complex128 / complex64 in memory).  Aligned to its full size so that one
@@ -81,6 +80,8 @@ struct NLArgs {
     double scale;       // 1 / (9 K M)
     double rot[3];      // rotation vector Omega (Cartesian, z the pipe axis) of the Coriolis force
     int rotating;       // nonzero: add -2 Omega x u to u x omega (mp = 1 unless Omega is axial)
+    int tz;             // axial points per theta-stage workgroup (tile shape), see tz_ok
+    int ztile;          // radial lines per z-transform workgroup (tile shape), see ztile_ok
 };
 
 // Arguments of one substep solve (one kernel).
@@ -147,6 +148,12 @@ hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s);
 // One of the three transform kernels: 0 z-inverse, 1 theta + product, 2 z-forward.
 hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s);
 bool nonlinear_supported(int M, int K);
+// Admissible transform tile shapes: tz in {2, 4, 8} axial points per theta
+// workgroup, zt in {4, 8, 16} radial lines per z workgroup, each while the
+// longer radix pass fits the workgroup.
+bool tz_ok(int tz, int M);
+bool ztile_ok(int zt, int K);
+constexpr int DEFAULT_TZ = 4, DEFAULT_ZTILE = 8;
 hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s);
 // Batched forms: one launch for `members` argument records in device memory
 // (grid.y = member); `proto` gives the shared sizes.

@@ -188,36 +188,37 @@ template <> struct ZLayout<108> { static constexpr int LSI = 126, LSF = 122; };
 template <> struct ZLayout<144> { static constexpr int LSI = 158, LSF = 158; };
 template <> struct ZLayout<192> { static constexpr int LSI = 210, LSF = 210; };
 // LDS bytes of one z-transform workgroup
-template <typename T, int L, bool INV>
+template <typename T, int L, bool INV, int ZT>
 constexpr size_t z_lds() {
-    return (size_t)(radix_max<L>() * radix_max<L>() + TILE * (INV ? ZLayout<L>::LSI : ZLayout<L>::LSF)) * sizeof(cpx<T>);
+    return (size_t)(radix_max<L>() * radix_max<L>() + ZT * (INV ? ZLayout<L>::LSI : ZLayout<L>::LSF)) * sizeof(cpx<T>);
 }
 
-constexpr int NT2 = 128;  // threads of a z-transform workgroup (TILE lines)
+constexpr int NT2 = 128;  // threads of a z-transform workgroup (ZT radial lines, ZT max(RA, RB) <= 128)
 
 // ---------------------------------------------------------------------------
 // k_zinv: spectral [M][nk][N] -> H[f][n][m][z], z = 0..3K-1 (inverse, zero
-// padded).  Workgroup: field f, azimuthal index m, TILE radial nodes.
-template <typename TS, typename T, int L>
+// padded).  Workgroup: field f, azimuthal index m, ZT radial nodes.
+template <typename TS, typename T, int L, int ZT>
 __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSI, RM = radix_max<L>();
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
+    static_assert(ZT * RM <= NT2, "a pass must fit the workgroup");
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
-    cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
+    cpx<T>* buf = tw2 + RM * RM;                         // [ZT][LS]
     constexpr int K = L / 3, nk = 2 * K - 1;  // the z line is the 3/2-padded length 3K
     const int N = a.N, M = a.M;
-    const int ntile = (N + TILE - 1) / TILE;
+    const int ntile = (N + ZT - 1) / ZT;
     const int tile = blockIdx.x % ntile;
     const int m = (blockIdx.x / ntile) % M;
     const int f = blockIdx.x / (ntile * M);
-    const int n0 = tile * TILE;
+    const int n0 = tile * ZT;
     const int tid = threadIdx.x;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);  // W_L^t, t < L
     for (int t = tid; t < RM * RM; t += NT2) tw2[t] = twg[((t % RM) * (t / RM)) % L];
     const cpx<TS>* src = reinterpret_cast<const cpx<TS>*>(a.in[f]) + (size_t)m * nk * N;
     // pass A: thread (j, nn), radial node fastest (coalesced rows of the spectral layout)
-    const int ja = tid / TILE, na = tid % TILE;
+    const int ja = tid / ZT, na = tid % ZT;
     cpx<T> v[RA];
     if (ja < RB) {
         const int n = min(n0 + na, N - 1);
@@ -236,7 +237,7 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     __syncthreads();  // pass A results and tw2
     // pass B: thread (nn, j), z fastest (coalesced z lines of H)
     const int nb = tid / RA, jb = tid % RA;
-    if (nb < TILE && n0 + nb < N) {
+    if (nb < ZT && n0 + nb < N) {
         cpx<T> u[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -250,11 +251,11 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     }
 }
 
-template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L>(a); }
-template <typename TS, typename T, int L>
+template <typename TS, typename T, int L, int ZT>
+__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L, ZT>(a); }
+template <typename TS, typename T, int L, int ZT>
 __global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
-    k_zinv_body<TS, T, L>(aa[blockIdx.y]);  // record read in place, not copied to scratch
+    k_zinv_body<TS, T, L, ZT>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
 // Coriolis force -2 Omega x u added to (nr, nt, nz) at theta point t of the
@@ -271,7 +272,8 @@ __device__ __forceinline__ void add_coriolis(const NLArgs& a, cpx<T> w, T ur, T 
 }
 
 // ---------------------------------------------------------------------------
-// k_theta_lp: per (n, TZ = 4 axial points), the three packed lines spread
+// k_theta_lp: per (n, TZ axial points; TZ = 2, 4 or 8 with TZ max(RA, RB)
+// <= 64), the three packed lines spread
 // over the three waves of a 192-thread workgroup (wave p holds line p).  A
 // thread keeps one line's RA or RB values, not all three (an FP64 thread
 // holding all three needs 208 VGPRs), and the product reads the three lines
@@ -290,7 +292,7 @@ __device__ __forceinline__ void add_coriolis(const NLArgs& a, cpx<T> w, T ur, T 
 // consecutive lanes), counted access by access.  The twiddles between the
 // passes come from tw2[r RM + j] = W_L^{j r}, RM = max(RA, RB), read at
 // stride one; the roots inside each radix are compile-time constants.
-constexpr int TZ = 4;
+constexpr int TZC = 4;  // axial points per workgroup of the CFL kernel
 constexpr int NT3 = 192;
 
 template <int L> struct ThetaLayout;
@@ -309,7 +311,7 @@ template <> struct ThetaLayout<144> { static constexpr int LS = 156; };
 template <> struct ThetaLayout<192> { static constexpr int LS = 220; };
 
 // LDS bytes of one k_theta_lp workgroup
-template <typename T, int L>
+template <typename T, int L, int TZ>
 constexpr size_t theta_lp_lds() {
     return (size_t)(radix_max<L>() * radix_max<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
 }
@@ -324,10 +326,10 @@ __device__ __forceinline__ int xcd_group_tile(int b, int total) {
     return g * 8 * G + G * (w % 8) + w / 8;
 }
 
-template <typename T, int L, bool ROT>
+template <typename T, int L, bool ROT, int TZ>
 __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ThetaLayout<L>::LS, RM = radix_max<L>();
-    constexpr int XG = 128 / (TZ * (int)sizeof(cpx<T>));  // tiles per 128-byte line of H and G
+    constexpr int XG = 128 / (TZ * (int)sizeof(cpx<T>)) > 0 ? 128 / (TZ * (int)sizeof(cpx<T>)) : 1;  // tiles per 128-byte line of H and G
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
     extern __shared__ unsigned char smem_raw[];
@@ -454,11 +456,11 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     }
 }
 
-template <typename T, int L, bool ROT>
-__global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L, ROT>(a); }
-template <typename T, int L>
+template <typename T, int L, bool ROT, int TZ>
+__global__ __launch_bounds__(NT3) void k_theta_lp(NLArgs a) { k_theta_lp_body<T, L, ROT, TZ>(a); }
+template <typename T, int L, int TZ>
 __global__ __launch_bounds__(NT3) void k_theta_lp_b(const NLArgs* __restrict__ aa) {
-    k_theta_lp_body<T, L, false>(aa[blockIdx.y]);  // ensemble members carry no forcing
+    k_theta_lp_body<T, L, false, TZ>(aa[blockIdx.y]);  // ensemble members carry no forcing
 }
 
 // ---------------------------------------------------------------------------
@@ -472,12 +474,12 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = L + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // [L]
-    cpx<T>* buf = tw + L;                                // [2][TZ][LS]
+    cpx<T>* buf = tw + L;                                // [2][TZC][LS]
     constexpr int M = L / 3;  // the theta line is the 3/2-padded length 3M
     const int N = a.N, L3K = 3 * a.K;
-    const int nzt = (L3K + TZ - 1) / TZ;
+    const int nzt = (L3K + TZC - 1) / TZC;
     const int n = blockIdx.x / nzt;
-    const int z0 = (blockIdx.x % nzt) * TZ;
+    const int z0 = (blockIdx.x % nzt) * TZC;
     const int tid = threadIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);
@@ -485,8 +487,8 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
     const size_t fstride = (size_t)N * M * L3K;
     const size_t nbase = (size_t)n * M * L3K;
-    cpx<T>* lb = buf + p * TZ * LS;
-    const int ja = lane / TZ, za = lane % TZ;
+    cpx<T>* lb = buf + p * TZC * LS;
+    const int ja = lane / TZC, za = lane % TZC;
     const int zc = min(z0 + za, L3K - 1);
     cpx<T> v[RA];
     if (ja < RB) {
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     }
     __syncthreads();
     const int zb = lane / RA, jb = lane % RA;
-    const bool actB = zb < TZ;
+    const bool actB = zb < TZC;
     cpx<T> u[RB];
     if (actB) {
 #pragma unroll
@@ -538,7 +540,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int pt = jb + r * RA;
-                const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZ + zb) * LS + pt];
+                const cpx<T> l0 = buf[zb * LS + pt], l1 = buf[(TZC + zb) * LS + pt];
                 mx = fmax(mx, fabs((double)l0.x) * a1 + fabs((double)l0.y) * a2 + fabs((double)l1.x) * wz);
             }
         }
@@ -552,8 +554,8 @@ template <typename T>
 static hipError_t launch_cfl_typed(const NLArgs& a, const double* wr, const double* wt, double wz, double* out,
                                    hipStream_t s) {
     const int L3M = 3 * a.M;
-    const dim3 g(a.N * ((3 * a.K + TZ - 1) / TZ));
-    const size_t lds = (size_t)(L3M + 2 * TZ * (L3M + 1)) * sizeof(cpx<T>);
+    const dim3 g(a.N * ((3 * a.K + TZC - 1) / TZC));
+    const size_t lds = (size_t)(L3M + 2 * TZC * (L3M + 1)) * sizeof(cpx<T>);
     switch (L3M) {
 #define OPF_CASE(V)                                                                       \
     case V:                                                                               \
@@ -568,20 +570,21 @@ static hipError_t launch_cfl_typed(const NLArgs& a, const double* wr, const doub
 
 // ---------------------------------------------------------------------------
 // k_zfwd: G[f][n][m][z] -> spectral [M][nk][N] (forward), |k| < K kept.
-template <typename TS, typename T, int L>
+template <typename TS, typename T, int L, int ZT>
 __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSF, RM = radix_max<L>();
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
+    static_assert(ZT * RM <= NT2, "a pass must fit the workgroup");
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
-    cpx<T>* buf = tw2 + RM * RM;                         // [TILE][LS]
+    cpx<T>* buf = tw2 + RM * RM;                         // [ZT][LS]
     constexpr int K = L / 3, nk = 2 * K - 1;  // the z line is the 3/2-padded length 3K
     const int N = a.N, M = a.M;
-    const int ntile = (N + TILE - 1) / TILE;
+    const int ntile = (N + ZT - 1) / ZT;
     const int tile = blockIdx.x % ntile;
     const int m = (blockIdx.x / ntile) % M;
     const int f = blockIdx.x / (ntile * M);
-    const int n0 = tile * TILE;
+    const int n0 = tile * ZT;
     const int tid = threadIdx.x;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twz);  // W_L^t, t < L
     for (int t = tid; t < RM * RM; t += NT2) tw2[t] = twg[((t % RM) * (t / RM)) % L];
@@ -589,7 +592,7 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     // pass A: thread (nn, j), z fastest
     const int na = tid / RB, ja = tid % RB;
     cpx<T> v[RA];
-    if (na < TILE) {
+    if (na < ZT) {
         const int n = min(n0 + na, N - 1);
         const cpx<T>* line = src + ((size_t)n * M + m) * L;
 #pragma unroll
@@ -600,7 +603,7 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     }
     __syncthreads();  // pass A results and tw2
     // pass B: thread (j, nn), radial node fastest (coalesced spectral rows)
-    const int jb = tid / TILE, nb = tid % TILE;
+    const int jb = tid / ZT, nb = tid % ZT;
     if (jb < RA && n0 + nb < N) {
         cpx<T> u[RB];
 #pragma unroll
@@ -621,11 +624,11 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     }
 }
 
-template <typename TS, typename T, int L>
-__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L>(a); }
-template <typename TS, typename T, int L>
+template <typename TS, typename T, int L, int ZT>
+__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L, ZT>(a); }
+template <typename TS, typename T, int L, int ZT>
 __global__ __launch_bounds__(NT2) void k_zfwd_b(const NLArgs* __restrict__ aa) {
-    k_zfwd_body<TS, T, L>(aa[blockIdx.y]);  // record read in place, not copied to scratch
+    k_zfwd_body<TS, T, L, ZT>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
 // ---------------------------------------------------------------------------
@@ -641,43 +644,71 @@ static bool length_ok(int L) {
 
 bool nonlinear_supported(int M, int K) { return length_ok(3 * M) && length_ok(3 * K); }
 
+// Largest radix of the two-pass split of length L (0: unsupported length).
+static int radix_of(int L) {
+    switch (L) {
+#define OPF_CASE(V) case V: return radix_max<V>();
+        OPF_FOR_LENGTHS(OPF_CASE)
+#undef OPF_CASE
+        default: return 0;
+    }
+}
+
+bool ztile_ok(int zt, int K) { return (zt == 4 || zt == 8 || zt == 16) && radix_of(3 * K) * zt <= NT2; }
+bool tz_ok(int tz, int M) { return (tz == 2 || tz == 4 || tz == 8) && radix_of(3 * M) * tz <= 64; }
+
+template <typename TS, typename T, int L, int ZT>
+static void launch_z(const NLArgs& a, const NLArgs* batch, int members, bool inv, hipStream_t s) {
+    const int ntile = (a.N + ZT - 1) / ZT;
+    const bool b = batch != nullptr;
+    if constexpr (ZT * radix_max<L>() <= NT2) {
+        if (inv) {
+            const dim3 g(6 * a.M * ntile, b ? members : 1);
+            if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, batch);
+            else hipLaunchKernelGGL((k_zinv<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, a);
+        } else {
+            const dim3 g(3 * a.M * ntile, b ? members : 1);
+            if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, batch);
+            else hipLaunchKernelGGL((k_zfwd<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, a);
+        }
+    }
+}
+
+template <typename T, int L, int TZ>
+static void launch_theta(const NLArgs& a, const NLArgs* batch, int members, hipStream_t s) {
+    if constexpr (TZ * radix_max<L>() <= 64) {
+        const dim3 g(a.N * ((3 * a.K + TZ - 1) / TZ), batch ? members : 1);
+        if (batch) hipLaunchKernelGGL((k_theta_lp_b<T, L, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, batch);
+        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, L, true, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, a);
+        else hipLaunchKernelGGL((k_theta_lp<T, L, false, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, a);
+    }
+}
+
 template <typename TS, typename T>
 static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
-    const int ntile = (a.N + TILE - 1) / TILE;
-    const bool b = batch != nullptr;
-    if (stage == 0) {
-        const dim3 g(6 * a.M * ntile, b ? members : 1);
-        switch (L3K) {
-#define OPF_CASE(V)                                                                  \
-    case V:                                                                          \
-        if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, V>), g, dim3(NT2), (z_lds<T, V, true>()), s, batch); \
-        else hipLaunchKernelGGL((k_zinv<TS, T, V>), g, dim3(NT2), (z_lds<T, V, true>()), s, a);         \
-        break;
-            OPF_FOR_LENGTHS(OPF_CASE)
-#undef OPF_CASE
-            default: return hipErrorInvalidValue;
-        }
-    } else if (stage == 1) {
-        const dim3 g(a.N * ((L3K + TZ - 1) / TZ), b ? members : 1);
+    if (stage == 1) {
+        if (!tz_ok(a.tz, a.M)) return hipErrorInvalidValue;
         switch (L3M) {
-#define OPF_CASE(V)                                                                                          \
-    case V:                                                                                                  \
-        if (b) hipLaunchKernelGGL((k_theta_lp_b<T, V>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, batch);        \
-        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, V, true>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a); \
-        else hipLaunchKernelGGL((k_theta_lp<T, V, false>), g, dim3(NT3), (theta_lp_lds<T, V>()), s, a);        \
+#define OPF_CASE(V)                                                        \
+    case V:                                                                \
+        if (a.tz == 2) launch_theta<T, V, 2>(a, batch, members, s);        \
+        else if (a.tz == 4) launch_theta<T, V, 4>(a, batch, members, s);   \
+        else launch_theta<T, V, 8>(a, batch, members, s);                  \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
             default: return hipErrorInvalidValue;
         }
     } else {
-        const dim3 g(3 * a.M * ntile, b ? members : 1);
+        if (!ztile_ok(a.ztile, a.K)) return hipErrorInvalidValue;
+        const bool inv = stage == 0;
         switch (L3K) {
-#define OPF_CASE(V)                                                                  \
-    case V:                                                                          \
-        if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, V>), g, dim3(NT2), (z_lds<T, V, false>()), s, batch); \
-        else hipLaunchKernelGGL((k_zfwd<TS, T, V>), g, dim3(NT2), (z_lds<T, V, false>()), s, a);         \
+#define OPF_CASE(V)                                                                \
+    case V:                                                                        \
+        if (a.ztile == 4) launch_z<TS, T, V, 4>(a, batch, members, inv, s);        \
+        else if (a.ztile == 8) launch_z<TS, T, V, 8>(a, batch, members, inv, s);   \
+        else launch_z<TS, T, V, 16>(a, batch, members, inv, s);                    \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
