@@ -180,7 +180,8 @@ opf_status opf_profile_steps(opf_ctx* ctx, int32_t nsteps, double* ms, int32_t* 
  * c_m = 2, w_n the radial quadrature weights of int_0^1 f r dr. */
 opf_status opf_vec_dot(opf_ctx* ctx, const void* a_dev, const void* b_dev, double* out_host);
 
-/* y = a x + b y over a whole external-layout field (complex128, real a, b). */
+/* y = a x + b y over a whole external-layout field (complex128, real a, b);
+ * b = 0 overwrites y without reading it. */
 opf_status opf_vec_axpby(opf_ctx* ctx, double a, const void* x_dev, double b, void* y_dev);
 
 /* Learned preconditioner network (declared below). */

@@ -386,9 +386,11 @@ __global__ __launch_bounds__(256) void k_pcdiff(const double* __restrict__ a, co
 }
 
 // y = a x + b y over n doubles.
+// y = a x + b y; with b = 0, y is overwritten without being read (a fresh
+// buffer may hold NaN, and 0 * NaN is NaN).
 __global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, size_t n) {
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a * x[i] + b * y[i];
+    if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
 // Independent unit normals in every real and imaginary part of a field:
