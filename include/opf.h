@@ -377,6 +377,18 @@ opf_status opf_hessenberg_eigvals(const double* h_host, int32_t k, double* re_ho
  * Synchronises. */
 opf_status opf_probe_pairs(opf_ctx* ctx, const void* x_dev, double T, double shift, int32_t n,
                            uint64_t seed, double fd_eps, void* pairs_dev, void* work_dev);
+/* opf_probe_pairs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same pairs, bitwise, with no work_dev argument.  Its three work
+ * vectors live in a file-scope device array of 16 MiB (3 fields of the
+ * grid must fit: OPF_E_INVALID otherwise, before any device work), which
+ * each device holds from the first call on it until the process ends; the
+ * steps are launched kernel by kernel (no step graph is captured).  It
+ * calls no hipMalloc, hipFree or allocating library routine.  Every call on
+ * one device shares that device's array: calls that overlap on one device
+ * (other threads or streams) race.  Synchronises. */
+opf_status opf_probe_pairs_noalloc(opf_ctx* ctx, const void* x_dev, double T, double shift, int32_t n,
+                                   uint64_t seed, double fd_eps, void* pairs_dev);
 
 /* ---- Learned preconditioner (not part of the paper) ----------------------
  * A residual MLP, shared by every Fourier mode (m, k) of one grid and fed

@@ -28,6 +28,7 @@ EXPORTS = ["opf_default_params", "opf_tables", "opf_workspace_size", "opf_create
            "opf_mlp_train_pairs", "opf_mlp_factors", "opf_precondition", "opf_mlp_last_error", "opf_ensemble_workspace_size", "opf_ensemble_create",
            "opf_ensemble_destroy", "opf_ensemble_member", "opf_ensemble_step", "opf_ensemble_tune",
            "opf_ensemble_tiles", "opf_autotune", "opf_tile_cache_write", "opf_tile_cache_read",
+           "opf_probe_pairs_noalloc",
            "opf_ensemble_last_error", "opf_probe_pairs_ensemble", "opf_set_dt", "opf_pc_difference",
            "opf_step_adaptive", "opf_hookstep_solve", "opf_arnoldi_workspace_size", "opf_arnoldi",
            "opf_hessenberg_eigvals", "opf_set_rotation", "opf_shoot_workspace_size", "opf_shoot_solve", "opf_set_wall_velocity",
@@ -157,6 +158,7 @@ def load_library(path=LIB_PATH):
         "opf_nk_solve": ([vp, vp, dbl, P(dbl), P(opf_nk_opts), vp, ctypes.c_size_t, P(opf_nk_report)], i32),
         "opf_diagnostics": ([vp, P(opf_diag)], i32),
         "opf_probe_pairs": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp, vp], i32),
+        "opf_probe_pairs_noalloc": ([vp, vp, dbl, dbl, i32, ctypes.c_uint64, dbl, vp], i32),
         "opf_mlp_default_config": ([P(opf_mlp_config)], i32),
         "opf_mlp_workspace_size": ([vp, P(opf_mlp_config), P(ctypes.c_size_t)], i32),
         "opf_mlp_create": ([vp, P(opf_mlp_config), vp, ctypes.c_size_t, P(vp)], i32),
@@ -583,6 +585,17 @@ class Solver:
                 ens.close()
         else:
             self._check(self.lib.opf_probe_pairs(self.ctx, *args))
+        return pairs
+
+    def probe_pairs_noalloc(self, x, T, shift, n, seed=1, fd_eps=1e-7):
+        """opf_probe_pairs_noalloc: the pairs of probe_pairs, with the
+        library's static device scratch as work space (no workspace
+        argument; see opf.h)."""
+        x = self._dev(x, self.shape)
+        pairs = self.torch.empty((int(n), 2) + tuple(self.shape), dtype=self.torch.complex128, device=self.device)
+        self._check(self.lib.opf_probe_pairs_noalloc(self.ctx, ctypes.c_void_p(x.data_ptr()), float(T),
+                                                     float(shift), int(n), int(seed), float(fd_eps),
+                                                     ctypes.c_void_p(pairs.data_ptr())))
         return pairs
 
     def diagnostics(self, check=True):

@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2184,16 +2185,50 @@ opf_status make_probe(opf_ctx* c, double* z, int i, uint64_t seed) {
 
 extern "C" {
 
-opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n, uint64_t seed,
-                           double fd_eps, void* pairs_dev, void* work_dev) {
-    if (!c || !x_dev || !pairs_dev || !work_dev || n < 1 || !(fd_eps > 0.0)) return OPF_E_INVALID;
+}  // extern "C"
+
+// Work vectors of opf_probe_pairs_noalloc: a file-scope device array.  In
+// host code `scratch` only names the symbol; its device address on the
+// current device comes from hipGetSymbolAddress, taken once per device on
+// the first call there and kept (each device holds its own copy of the
+// array until the process ends).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+// F = shift(Phi_T(x), -shift) - x with the steps launched one kernel at a
+// time (the same kernels and arguments as the step graph, which is neither
+// captured nor instantiated here).
+opf_status residual_eager(opf_ctx* c, const void* x, double T, double shift, void* F) {
+    if (!(T >= 0)) return OPF_E_INVALID;
+    const int nsteps = (int)std::lround(T / c->p.dt);
+    opf_status st = opf_set_state(c, x);
+    if (st != OPF_OK) return st;
+    for (int i = 0; i < nsteps; ++i)
+        if ((st = enqueue_step(c, c->stream)) != OPF_OK) return st;
+    if (nsteps > 0) c->pc_valid = true;
+    const size_t total = 3 * field_entries(c);
+    hipLaunchKernelGGL(k_shift_sub, dim3((total + 255) / 256), dim3(256), 0, c->stream, c->u,
+                       static_cast<const double*>(x), static_cast<double*>(F), c->p.N, c->nk, c->p.K, total,
+                       c->p.alpha, shift);
+    HIPCHK(c, hipGetLastError());
+    return OPF_OK;
+}
+
+// The probes of opf_probe_pairs with three work vectors at work_dev; eager
+// selects the residual without the step graph.
+opf_status probe_pairs_impl(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n, uint64_t seed,
+                            double fd_eps, void* pairs_dev, void* work_dev, bool eager) {
     const size_t total = 3 * field_entries(c);
     const size_t vb = total * 16;
     unsigned char* w = static_cast<unsigned char*>(work_dev);
     void* F0 = w;
     void* tmp = w + vb;
     void* F1 = w + 2 * vb;
-    opf_status st = opf_newton_residual(c, x_dev, T, shift, F0, nullptr);
+    auto resid = [&](const void* x, void* F) {
+        return eager ? residual_eager(c, x, T, shift, F) : opf_newton_residual(c, x, T, shift, F, nullptr);
+    };
+    opf_status st = resid(x_dev, F0);
     if (st != OPF_OK) return st;
     double xn2 = 0.0;
     if ((st = opf_vec_dot(c, x_dev, x_dev, &xn2)) != OPF_OK) return st;
@@ -2205,12 +2240,61 @@ opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift
         if ((st = make_probe(c, z, i, seed)) != OPF_OK) return st;
         if ((st = opf_vec_axpby(c, 1.0, x_dev, 0.0, tmp)) != OPF_OK) return st;
         if ((st = opf_vec_axpby(c, eps, z, 1.0, tmp)) != OPF_OK) return st;
-        if ((st = opf_newton_residual(c, tmp, T, shift, F1, nullptr)) != OPF_OK) return st;
+        if ((st = resid(tmp, F1)) != OPF_OK) return st;
         HIPCHK(c, hipMemcpyAsync(jz, F1, vb, hipMemcpyDeviceToDevice, c->stream));
         if ((st = opf_vec_axpby(c, -1.0 / eps, F0, 1.0 / eps, jz)) != OPF_OK) return st;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return OPF_OK;
+}
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+opf_status scratch_on_current_device(opf_ctx* c, void** out) {
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        c->err = "no-allocation scratch: device index out of range";
+        return OPF_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (he != hipSuccess || !p) {
+            c->err = std::string("no-allocation scratch: hipGetSymbolAddress: ") + hipGetErrorString(he);
+            return OPF_E_HIP;
+        }
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return OPF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+opf_status opf_probe_pairs(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n, uint64_t seed,
+                           double fd_eps, void* pairs_dev, void* work_dev) {
+    if (!c || !x_dev || !pairs_dev || !work_dev || n < 1 || !(fd_eps > 0.0)) return OPF_E_INVALID;
+    return probe_pairs_impl(c, x_dev, T, shift, n, seed, fd_eps, pairs_dev, work_dev, false);
+}
+
+opf_status opf_probe_pairs_noalloc(opf_ctx* c, const void* x_dev, double T, double shift, int32_t n,
+                                   uint64_t seed, double fd_eps, void* pairs_dev) {
+    if (!c || !x_dev || !pairs_dev || n < 1 || !(fd_eps > 0.0)) return OPF_E_INVALID;
+    const size_t need = 3 * (3 * field_entries(c) * 16);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        c->err = "opf_probe_pairs_noalloc: three fields of this grid take " + std::to_string(need) +
+                 " bytes, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch";
+        return OPF_E_INVALID;
+    }
+    void* w = nullptr;
+    const opf_status st = scratch_on_current_device(c, &w);
+    if (st != OPF_OK) return st;
+    return probe_pairs_impl(c, x_dev, T, shift, n, seed, fd_eps, pairs_dev, w, true);
 }
 
 }  // extern "C"
