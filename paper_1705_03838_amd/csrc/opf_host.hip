@@ -2518,7 +2518,8 @@ bool parse_tile_cache(const std::string& text, std::vector<TileChoice>& out, std
         const char* names[] = {"N", "M", "K", "mp", "precision", "gm", "tz", "ztile"};
         for (int i = 0; i < 8; ++i) {
             const JVal* v = c.kind == JVal::OBJ ? c.get(names[i]) : nullptr;
-            if (!v || v->kind != JVal::NUM || v->num != (double)(int)v->num) {
+            // an integer in int range (casting a number outside it is undefined)
+            if (!v || v->kind != JVal::NUM || !(std::fabs(v->num) < 1e9) || v->num != std::floor(v->num)) {
                 msg = std::string("tile cache: class entry without integer \"") + names[i] + "\"";
                 return false;
             }
