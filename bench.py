@@ -166,16 +166,21 @@ def run_rotation(w, steps, warmup):
             "theta_us": round(prof["theta"][0] / max(prof["theta"][1], 1) * 1e3, 2)}
 
 
-def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
+def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16, train_seeds=(5101, 5102, 5103),
+           nonlaminar_energies=(1e-3,)):
     """Newton-Krylov travelling-wave search on the nk workload (N=48, |m|<24
     with 2-fold symmetry, |k|<32, Re 2400, alpha 1.25, T=20): seeded
-    near-laminar guess, GMRES(40), tolerance 1e-8 on ||F||/||x||; first plain
-    (restarted GMRES and a line search), then with the Krylov trust-region
-    hookstep, then the Arnoldi stability of the solution found, then with the
-    learned preconditioner trained on Jacobian probes at
-    laminar flow, run 32 at a time as ensemble members (probing and training
-    timed separately: they are made once per grid, Re and T and serve every
-    later search)."""
+    near-laminar guess (seed 5000), GMRES(40), tolerance 1e-8 on ||F||/||x||;
+    first plain (restarted GMRES and a line search), then with the Krylov
+    trust-region hookstep, then the Arnoldi stability of the solution found,
+    then with the learned preconditioner trained two ways: on the (z, J z)
+    pairs of the Krylov vectors that plain searches from other seeds
+    (train_seeds) generate, and on Jacobian probes at laminar flow (run 32
+    at a time as ensemble members).  Wall times are given for the search
+    alone and with the training data and training included (both are made
+    once per grid, Re and T and serve every later search).  Last, the same
+    two networks at non-laminar base states: guesses of perturbation energy
+    e (fractions of the laminar energy) for e in nonlaminar_energies."""
     import torch
 
     import paper_1705_03838_amd as opf
@@ -184,11 +189,11 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     s = opf.Solver(N=w["N"], M=w["M"], K=w["K"], mp=w["mp"], alpha=w["alpha"], Re=w["Re"], dt=w["dt"])
     x0 = torch.from_numpy(workload_state(w, s.nodes()))
 
-    def search(precond=None, hookstep=False):
+    def search(x=None, precond=None, hookstep=False, record=None, **kw):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xs, rep = s.nk_solve(x0, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3, precond=precond,
-                             hookstep=hookstep)
+        xs, rep = s.nk_solve(x0 if x is None else x, w["T"], 0.0, gmres_m=gmres_m, tol=1e-8, gmres_tol=1e-3,
+                             precond=precond, hookstep=hookstep, record=record, **kw)
         torch.cuda.synchronize()
         rep["wall_s"] = round(time.perf_counter() - t0, 3)
         rep["history"] = [float(f"{h:.3e}") for h in rep["history"]]
@@ -210,32 +215,82 @@ def run_nk(w, gmres_m=40, probes=160, rank=16, train_steps=12000, batch=16):
     progress(f"nk plain: {plain['jvps']} jvps, {plain['wall_s']} s")
     hook = search(hookstep=True)
     progress(f"nk hookstep: {hook['jvps']} jvps, {hook['residual_evals']} residuals, {hook['wall_s']} s")
+    # training data 1: the Krylov vectors of plain searches from other seeds (every product recorded)
+    t0 = time.perf_counter()
+    recs = []
+    for seed in train_seeds:
+        rec = torch.zeros((2 * gmres_m, 2) + tuple(s.shape), dtype=torch.complex128, device="cuda")
+        r = search(torch.from_numpy(workload_state(dict(w, seed=seed), s.nodes())), record=rec)
+        recs.append(rec[:r["recorded"]])
+    krylov_pairs = torch.cat(recs)
+    del recs
+    krylov_s = time.perf_counter() - t0
+    progress(f"nk krylov pairs: {krylov_pairs.shape[0]} from {len(train_seeds)} searches in {krylov_s:.1f} s")
+    # training data 2: Jacobian probes at laminar flow
     t0 = time.perf_counter()
     lam = torch.from_numpy(laminar_state(w["N"], w["M"], w["K"], s.nodes()))
-    pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11, batch=32)
+    probe_pairs = s.probe_pairs(lam, w["T"], 0.0, probes, seed=11, batch=32)
     probe_s = time.perf_counter() - t0
     progress(f"nk probes: {probes} in {probe_s:.1f} s")
-    net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3, lr=1e-3, lr_final=3e-5)
-    t0 = time.perf_counter()
-    losses = net.train_pairs(pairs, batch=batch, steps=train_steps, seed=5)
-    train_s = time.perf_counter() - t0
-    progress(f"nk training: {train_steps} steps in {train_s:.1f} s")
-    del pairs
-    pre = search(net)
-    flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
-    out = {"plain": plain, "hookstep": hook, "preconditioned": pre, "stability_arnoldi": stability,
-           "wall_speedup": round(plain["wall_s"] / pre["wall_s"], 3),
-           "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
+
+    def trained(pairs, data_s, label):
+        net = opf.Mlp(s, width=256, layers=4, rank=rank, seed=3, lr=1e-3, lr_final=3e-5)
+        t0 = time.perf_counter()
+        losses = net.train_pairs(pairs, batch=batch, steps=train_steps, seed=5)
+        train_s = time.perf_counter() - t0
+        progress(f"nk training ({label}): {train_steps} steps in {train_s:.1f} s")
+        pre = search(precond=net)
+        flops_step = mlp_train_flops(net, s.M * (2 * s.K - 1))
+        out = {"search": pre, "pairs": int(pairs.shape[0]), "data_s": round(data_s, 2),
+               "train_steps": train_steps, "batch_pairs": batch, "lr": "cosine 1e-3 -> 3e-5",
+               "train_s": round(train_s, 2), "train_step_ms": round(train_s / train_steps * 1e3, 4),
+               "train_gemm_TFLOPs_lower_bound": round(flops_step * train_steps / train_s / 1e12, 2),
+               "loss_first_last": [float(f"{losses[0]:.3e}"), float(f"{losses[-100:].mean():.3e}")],
+               "wall_speedup_search": round(plain["wall_s"] / pre["wall_s"], 3),
+               "wall_speedup_with_data_and_training": round(plain["wall_s"] / (pre["wall_s"] + data_s + train_s), 3),
+               "jvp_ratio": round(plain["jvps"] / max(pre["jvps"], 1), 3),
+               "break_even_searches": round((data_s + train_s) / max(plain["wall_s"] - pre["wall_s"], 1e-9), 2)}
+        out["params"] = net.n_params
+        return out, net
+
+    krylov, knet = trained(krylov_pairs, krylov_s, "krylov")
+    del krylov_pairs
+    probed, pnet = trained(probe_pairs, probe_s, "probes")
+    del probe_pairs
+    # the same networks (trained near laminar flow) at non-laminar base states:
+    # a guess of perturbation energy e (seed 5200), first Newton step and the
+    # whole search (e <= 1e-3; larger e: first step only, up to 400 products)
+    lam_norm = float(np.sqrt(s.vec_dot(lam, lam)))
+    nonlaminar = []
+    for e in nonlaminar_energies:
+        xb = torch.from_numpy(workload_state(dict(w, seed=5200, energy_frac=e), s.nodes()))
+        row = {"energy_frac": e, "seed": 5200}
+        for label, net in (("plain", None), ("krylov", knet), ("probes", pnet)):
+            first = search(xb, precond=net, max_newton=1, max_jvps=400)
+            row[label] = {"first_step_products": first["jvps"], "first_step_fallbacks": first["fallbacks"],
+                          "first_step_wall_s": first["wall_s"]}
+            if e <= 1e-3:
+                full = search(xb, precond=net)
+                d = search.last - lam.to(search.last.device)
+                row[label].update({"search": full, "distance_to_laminar": float(np.sqrt(s.vec_dot(d, d))) / lam_norm})
+            progress(f"nk non-laminar E'={e:g} {label}: first step {first['jvps']} products")
+        for label in ("krylov", "probes"):
+            if "search" in row[label]:
+                row[label]["wall_speedup_search"] = round(row["plain"]["search"]["wall_s"] / row[label]["search"]["wall_s"], 3)
+        nonlaminar.append(row)
+    knet.close()
+    pnet.close()
+    out = {"plain": plain, "hookstep": hook, "stability_arnoldi": stability,
            "steps_per_residual": int(round(w["T"] / w["dt"])),
-           "network": {"width": 256, "layers": 4, "rank": rank, "params": net.n_params,
-                       "probes": probes, "probe_batch": 32, "probe_s": round(probe_s, 2),
-                       "train_steps": train_steps, "batch_pairs": batch, "lr": "cosine 1e-3 -> 3e-5",
-                       "train_s": round(train_s, 2),
-                       "train_step_ms": round(train_s / train_steps * 1e3, 4),
-                       "train_gemm_TFLOPs_lower_bound": round(flops_step * train_steps / train_s / 1e12, 2),
-                       "loss_first_last": [float(f"{losses[0]:.3e}"), float(f"{losses[-100:].mean():.3e}")]},
-           "break_even_searches": round((probe_s + train_s) / max(plain["wall_s"] - pre["wall_s"], 1e-9), 2)}
-    net.close()
+           "network": {"width": 256, "layers": 4, "rank": rank, "params": krylov.pop("params")},
+           "learned_krylov_pairs": dict(krylov, training_seeds=list(train_seeds), evaluation_seed=w["seed"]),
+           "learned_laminar_probes": dict(probed, probe_batch=32, evaluation_seed=w["seed"]),
+           "non_laminar_bases": nonlaminar}
+    probed.pop("params", None)
+    # the headline learned-preconditioner figures: Krylov-trained (the solver's own vectors)
+    out["preconditioned"] = krylov["search"]
+    out["wall_speedup"] = krylov["wall_speedup_search"]
+    out["jvp_ratio"] = krylov["jvp_ratio"]
     s.close()
     return out
 
@@ -395,6 +450,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-nk", action="store_true", help="skip the Newton-Krylov search")
+    ap.add_argument("--nk-energies", default="1e-3",
+                    help="comma-separated perturbation energies (fractions of laminar) of the non-laminar "
+                         "base states the learned preconditioner is evaluated at")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 96-member ensemble")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the run under time-step control")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -494,7 +552,8 @@ def main():
     if not args.no_nk:
         out["newton_krylov"] = {"workload": "nk: N=48, |m|<24 (mp=2), |k|<32, alpha=1.25, Re=2400, "
                                             "dt=0.01, T=20, near-laminar seed 5000",
-                                **run_nk(WORKLOADS["nk"])}
+                                **run_nk(WORKLOADS["nk"], nonlaminar_energies=tuple(
+                                    float(v) for v in args.nk_energies.split(",") if v))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(w)
         progress(f"cpu baseline done; accuracy after {out['accuracy']['steps']} steps: "

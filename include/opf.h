@@ -169,10 +169,12 @@ opf_status opf_newton_residual(opf_ctx* ctx, const void* x_dev, double T,
                                double shift, void* F_dev, double* norm_out);
 
 /* Advance nsteps steps like opf_step but with every kernel launched on its
- * own and bracketed by HIP events on the context's stream (for measurement).
- * ms[5] / launches[5] receive the summed device time and launch count of the
- * z-inverse transform, theta transform + product, z-forward transform,
- * predictor solve and corrector solve kernels.  Synchronises. */
+ * own (for measurement), through hipExtLaunchKernel with a start and a stop
+ * event tied to that kernel's dispatch, so the times exclude the gaps
+ * between launches.  ms[5] / launches[5]
+ * receive the summed device time and launch count of the z-inverse
+ * transform, theta transform + product, z-forward transform, predictor solve
+ * and corrector solve kernels.  Synchronises. */
 opf_status opf_profile_steps(opf_ctx* ctx, int32_t nsteps, double* ms, int32_t* launches);
 
 /* Energy inner product of two external-layout fields (host result,
@@ -237,7 +239,11 @@ typedef struct opf_mlp opf_mlp;
  * OPF_E_UNSUPPORTED).
  * Errors: OPF_E_INVALID for null pointers, gmres_m or max_jvps < 1, a
  * non-finite *cw_inout or a negative record capacity; OPF_E_NOMEM for a
- * short krylov_dev; OPF_E_NUMERIC for a non-finite preconditioned vector. */
+ * short krylov_dev; OPF_E_NUMERIC for a non-finite preconditioned vector,
+ * a non-finite residual at x, or a line search whose shortest trial
+ * (step/1024) still has one.  A trial point whose residual is not finite
+ * (its trajectory left the range the explicit terms can follow) counts as
+ * rejected: the line search halves the step, the hookstep halves Delta. */
 typedef struct {
     int32_t gmres_m;     /* Krylov dimension per restart, e.g. 40             */
     int32_t max_newton;  /* Newton iterations                                  */

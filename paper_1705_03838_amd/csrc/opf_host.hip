@@ -892,32 +892,33 @@ opf_status opf_profile_steps(opf_ctx* c, int32_t nsteps, double* ms, int32_t* la
     if (!c->have_state) return OPF_E_STATE;
     const bool mixed = c->p.precision == OPF_MIXED;
     const int nk = 5;  // zinv, theta, zfwd, solve (predictor), solve (corrector)
-    std::vector<hipEvent_t> ev;
+    // one start/stop pair per launch, recorded around the kernel itself
+    std::vector<KernelTiming> ev;
     std::vector<int> kind;
-    auto mark = [&](int k) -> hipError_t {
-        hipEvent_t e;
-        hipError_t he = hipEventCreate(&e);
-        if (he != hipSuccess) return he;
-        ev.push_back(e);
-        kind.push_back(k);
-        return hipEventRecord(e, c->stream);
-    };
     hipError_t he = hipSuccess;
+    auto timing = [&](int k, KernelTiming& kt) -> hipError_t {
+        hipError_t e = hipEventCreate(&kt.start);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&kt.stop);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(kt.start);
+            return e;
+        }
+        ev.push_back(kt);
+        kind.push_back(k);
+        return hipSuccess;
+    };
     const void* uin = mixed ? (const void*)c->u32 : (const void*)c->u;
     const void* upin = mixed ? (const void*)c->up32 : (const void*)c->up;
     for (int st = 0; st < nsteps && he == hipSuccess; ++st) {
         for (int half = 0; half < 2 && he == hipSuccess; ++half) {
             if (c->p.nonlinear) {
                 NLArgs a = nl_args(c, half ? upin : uin, c->w, half ? c->Np : c->Nn);
-                he = mark(-1);
-                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 0, c->stream);
-                if (he == hipSuccess) he = mark(0);
-                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 1, c->stream);
-                if (he == hipSuccess) he = mark(1);
-                if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, 2, c->stream);
-                if (he == hipSuccess) he = mark(2);
-            } else {
-                he = mark(-1);
+                for (int stage = 0; stage < 3 && he == hipSuccess; ++stage) {
+                    KernelTiming kt;
+                    he = timing(stage, kt);
+                    if (he == hipSuccess) he = launch_nonlinear_stage(a, c->p.precision, stage, c->stream, kt);
+                }
             }
             if (he != hipSuccess) break;
             SolveArgs b = solve_args(c, half ? OPF_SOLVE_CORR : OPF_SOLVE_PRED);
@@ -927,20 +928,23 @@ opf_status opf_profile_steps(opf_ctx* c, int32_t nsteps, double* ms, int32_t* la
             b.u_out = half ? c->u : (mixed ? nullptr : c->up);
             b.u_out32 = mixed ? (half ? c->u32 : c->up32) : nullptr;
             b.w_out = c->w;
-            he = launch_solve(b, c->p.precision, c->stream);
-            if (he == hipSuccess) he = mark(3 + half);
+            KernelTiming kt;
+            he = timing(3 + half, kt);
+            if (he == hipSuccess) he = launch_solve(b, c->p.precision, c->stream, kt);
         }
     }
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     for (int k = 0; k < nk; ++k) { ms[k] = 0.0; launches[k] = 0; }
-    for (size_t i = 1; i < ev.size() && he == hipSuccess; ++i) {
-        if (kind[i] < 0) continue;
+    for (size_t i = 0; i < ev.size() && he == hipSuccess; ++i) {
         float t = 0.0f;
-        he = hipEventElapsedTime(&t, ev[i - 1], ev[i]);
+        he = hipEventElapsedTime(&t, ev[i].start, ev[i].stop);
         ms[kind[i]] += t;
         launches[kind[i]] += 1;
     }
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (const KernelTiming& kt : ev) {
+        (void)hipEventDestroy(kt.start);
+        (void)hipEventDestroy(kt.stop);
+    }
     if (he != hipSuccess) {
         c->err = std::string("profile: ") + hipGetErrorString(he);
         return OPF_E_HIP;
@@ -1271,6 +1275,21 @@ opf_status opf_newton_residual(opf_ctx* c, const void* x, double T, double shift
     return OPF_OK;
 }
 
+namespace {
+// ||F|| at a trial point of a Newton step.  A trial state the time step
+// cannot follow (the explicit terms past their stability limit) gives a
+// non-finite norm: that trial counts as +infinity, i.e. rejected, and the
+// caller shortens the step.
+opf_status trial_residual(opf_ctx* c, const void* x, double T, double shift, void* F, double* norm) {
+    const opf_status st = opf_newton_residual(c, x, T, shift, F, norm);
+    if (st == OPF_E_NUMERIC) {
+        *norm = INFINITY;
+        return OPF_OK;
+    }
+    return st;
+}
+}  // namespace
+
 opf_status opf_hookstep_solve(const double* hb, int32_t k, double beta, double delta, double* y, double* mu_out,
                               double* resid) {
     if (!hb || !y || !mu_out || !resid || k < 1 || !(beta >= 0) || !(delta > 0)) return OPF_E_INVALID;
@@ -1585,7 +1604,11 @@ opf_status opf_shoot_solve(opf_ctx* c, void* x_dev, double* T_io, double* s_io, 
             sXe[1] = sW[1];
             for (int i = 0; i < k; ++i) SHCHK(xaxpby(y[i], ev(i), &sc[2 * i], 1.0, ev(iXe), sXe));
             SHCHK(residual(ev(iXe), sXe, ev(iGt), sGt));
-            SHCHK(nrm(ev(iGt), sGt, &fnew));
+            {  // a trial the time step cannot follow (non-finite norm) is rejected
+                const opf_status st = nrm(ev(iGt), sGt, &fnew);
+                if (st == OPF_E_NUMERIC) fnew = INFINITY;
+                else SHCHK(st);
+            }
             rep->hook_trials += 1;
             const double den = fn * fn - r * r;
             const double rho = den > 0 ? (fn * fn - fnew * fnew) / den : -INFINITY;
@@ -1994,7 +2017,7 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double* cw_io, const 
                     NKCHK(opf_vec_axpby(c, y[i], vec(i), 1.0, w));
                     cnew += y[i] * sv[i];
                 }
-                NKCHK(opf_newton_residual(c, w, T, cnew * T, tmp, &fnew));
+                NKCHK(trial_residual(c, w, T, cnew * T, tmp, &fnew));
                 rep->residual_evals += 1;
                 rep->hook_trials += 1;
                 const double den = fn * fn - r * r;
@@ -2125,11 +2148,12 @@ opf_status opf_nk_solve(opf_ctx* c, void* x_dev, double T, double* cw_io, const 
                 NKCHK(opf_vec_axpby(c, 1.0, x, 0.0, w));
                 NKCHK(opf_vec_axpby(c, lam, dx, 1.0, w));
                 cnew = cw + lam * sdx;
-                NKCHK(opf_newton_residual(c, w, T, cnew * T, tmp, &fnew));
+                NKCHK(trial_residual(c, w, T, cnew * T, tmp, &fnew));
                 rep->residual_evals += 1;
                 if (fnew < fn || lam < 1e-3) break;
                 lam *= 0.5;
             }
+            if (!std::isfinite(fnew)) return OPF_E_NUMERIC;  // even the shortest step left the stable range
             lowered = fnew < fn;
             return OPF_OK;
         };

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -143,10 +144,24 @@ struct FactorArgs {
 // inverse influence matrices and Green's function.
 hipError_t launch_operator_tables(const FactorArgs& a, bool pressure, hipStream_t s);
 
+// Kernel-only timing of one launch: when start is set, the launch goes
+// through hipExtLaunchKernelGGL, which records start and stop around the
+// kernel itself (no dispatch gap), for opf_profile_steps.
+struct KernelTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+template <typename... Args, typename F = void (*)(Args...)>
+inline void launch_timed(F kernel, const dim3& grid, const dim3& block, uint32_t lds, hipStream_t s,
+                         const KernelTiming& kt, Args... args) {
+    if (kt.start) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, kt.start, kt.stop, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 // Launchers (return the first HIP error).
 hipError_t launch_nonlinear(const NLArgs& a, int precision, hipStream_t s);
 // One of the three transform kernels: 0 z-inverse, 1 theta + product, 2 z-forward.
-hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s);
+hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s,
+                                  const KernelTiming& kt = KernelTiming{});
 bool nonlinear_supported(int M, int K);
 // Admissible transform tile shapes: tz in {2, 4, 8} axial points per theta
 // workgroup, zt in {4, 8, 16} radial lines per z workgroup, each while the
@@ -154,7 +169,7 @@ bool nonlinear_supported(int M, int K);
 bool tz_ok(int tz, int M);
 bool ztile_ok(int zt, int K);
 constexpr int DEFAULT_TZ = 4, DEFAULT_ZTILE = 8;
-hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s, const KernelTiming& kt = KernelTiming{});
 // Batched forms: one launch for `members` argument records in device memory
 // (grid.y = member); `proto` gives the shared sizes.
 hipError_t launch_nonlinear_batch(const NLArgs& proto, const NLArgs* dev_args, int members, int precision,

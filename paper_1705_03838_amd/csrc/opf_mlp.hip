@@ -135,6 +135,91 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16_t* __restrict__ A, int 
     }
 }
 
+// The same product for large shapes: one 128 x 128 tile of C per workgroup,
+// each wave a 64 x 64 quarter (2 x 2 instruction tiles of 32 x 32, 64
+// accumulators per lane).  K advances 32 at a time through double-buffered
+// LDS tiles of A and B (rows padded to 40 bf16, 80 bytes, so the 16-byte
+// operand reads of 16 consecutive lanes hit distinct banks); the next
+// slice's global loads are issued before the current slice's products.
+// Every wave takes its 64 x 64 quarter through all of K, so a C entry is the
+// same K-ordered sum for every launch shape; with a split (part != null)
+// workgroup z writes its raw partial tile for k_gemm_reduce.
+// Requires rows, cols multiples of 128, K and kc of 32, lda, ldb of 8.
+constexpr int G2 = 128, GK2 = 32, GLS2 = 40;
+__global__ __launch_bounds__(256) void k_gemm128(const bf16_t* __restrict__ A, int lda,
+                                                 const bf16_t* __restrict__ B, int ldb, int K, int kc, Epi e,
+                                                 float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) bf16_t sa[2][G2 * GLS2];
+    __shared__ __attribute__((aligned(16))) bf16_t sb[2][G2 * GLS2];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int m0 = blockIdx.y * G2, n0 = blockIdx.x * G2;
+    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+    const int lr = t >> 2, lk = 8 * (t & 3);  // loader: rows lr and lr + 64, k lk..lk+7
+    const bf16_t* ag = A + (size_t)(m0 + lr) * lda + lk;
+    const bf16_t* bg = B + (size_t)(n0 + lr) * ldb + lk;
+    const size_t a64 = (size_t)64 * lda, b64 = (size_t)64 * ldb;
+    u32x4 ra0, ra1, rb0, rb1;
+    ra0 = *reinterpret_cast<const u32x4*>(ag + kb);
+    ra1 = *reinterpret_cast<const u32x4*>(ag + a64 + kb);
+    rb0 = *reinterpret_cast<const u32x4*>(bg + kb);
+    rb1 = *reinterpret_cast<const u32x4*>(bg + b64 + kb);
+    *reinterpret_cast<u32x4*>(&sa[0][lr * GLS2 + lk]) = ra0;
+    *reinterpret_cast<u32x4*>(&sa[0][(lr + 64) * GLS2 + lk]) = ra1;
+    *reinterpret_cast<u32x4*>(&sb[0][lr * GLS2 + lk]) = rb0;
+    *reinterpret_cast<u32x4*>(&sb[0][(lr + 64) * GLS2 + lk]) = rb1;
+    __syncthreads();
+    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+    const int rr = lane & 31, kq = (lane >> 5) * 8;
+    f32x16 acc[2][2] = {};
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += GK2) {
+        const bool more = k0 + GK2 < ke;
+        if (more) {
+            ra0 = *reinterpret_cast<const u32x4*>(ag + k0 + GK2);
+            ra1 = *reinterpret_cast<const u32x4*>(ag + a64 + k0 + GK2);
+            rb0 = *reinterpret_cast<const u32x4*>(bg + k0 + GK2);
+            rb1 = *reinterpret_cast<const u32x4*>(bg + b64 + k0 + GK2);
+        }
+#pragma unroll
+        for (int ks = 0; ks < GK2; ks += 16) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm + 32 * i + rr) * GLS2 + ks + kq]);
+                bv[i] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn + 32 * i + rr) * GLS2 + ks + kq]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) {
+            *reinterpret_cast<u32x4*>(&sa[buf ^ 1][lr * GLS2 + lk]) = ra0;
+            *reinterpret_cast<u32x4*>(&sa[buf ^ 1][(lr + 64) * GLS2 + lk]) = ra1;
+            *reinterpret_cast<u32x4*>(&sb[buf ^ 1][lr * GLS2 + lk]) = rb0;
+            *reinterpret_cast<u32x4*>(&sb[buf ^ 1][(lr + 64) * GLS2 + lk]) = rb1;
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+    const int cols = gridDim.x * G2, rows = gridDim.y * G2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = n0 + wn + 32 * j + rr;
+                if (part)
+                    part[((size_t)blockIdx.z * rows + row) * cols + col] = acc[i][j][v];
+                else
+                    epilogue(e, row, col, acc[i][j][v]);
+            }
+}
+
 // Sum of the split partial tiles in order, then the epilogue.
 __global__ void k_gemm_reduce(const float* __restrict__ part, int rows, int cols, int nsplit, Epi e) {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -408,131 +493,199 @@ struct HeadArgs {
     int rows, rp;  // M(2K-1) live rows, rows padded to 32
     float* Y;      // in: network output rows; out: dLoss/dY
     bf16_t* dyb;   // [rp][dout]
-    bf16_t* dyt;   // [dout][ldt]
-    int ldt;
-    float* lrow;  // per-row loss
-    float scale;  // 1 / (batch rows)
+    float* lrow;   // per-row loss
+    float scale;   // 1 / (batch rows)
+    int hb;        // pairs per pass (head_pairs)
 };
 
-constexpr int HB = 8;             // pairs staged per pass of the loss head
+constexpr int HB = 8;             // most pairs staged per pass of the loss head
 constexpr int HOUT = 12;          // gradient outputs per thread and factor: 3N R <= 256 HOUT
-constexpr int HMAX3N = 3 * 64;    // profile length bound (N <= 64)
+constexpr int HEAD_LDS = 53248;   // LDS bytes of one loss-head workgroup at most (three per compute unit)
+
+// float2 slots of the loss head's LDS for nb pairs per pass: U and V rows
+// padded to R + 1 entries, the nb staged profiles xhat and that (then r),
+// C and G, and 256 partial sums.
+__host__ __device__ inline int head_slots(int n3, int R, int nb) {
+    return 2 * n3 * (R + 1) + nb * (2 * n3 + 2 * R) + 256;
+}
+// Pairs per pass that fit HEAD_LDS, at least 1.  Every admissible grid
+// (3N R <= 3072, 3N <= 192) needs at most 7200 slots (57.6 KB) for one pair,
+// within the 64 KB a workgroup may take.
+inline int head_pairs(int n3, int R) {
+    int nb = HB;
+    while (nb > 1 && head_slots(n3, R, nb) * 8 > HEAD_LDS) --nb;
+    return nb;
+}
 
 // Loss head of the training pairs: the network's factors U = A, V = B model
 // the Jacobian on each mode, J_q ~ -I + U V^H.  For mode q and pair p:
 // s = RMS of the z_q profile (pairs with s = 0 skip), xhat = z_q / s,
 // that = (J z)_q / s, c = V^H xhat, r = -xhat + U c - that;
 // loss = scale sum |r|^2, dU = 2 scale sum r c^H, dV = 2 scale sum xhat (U^H r)^H.
-// One workgroup of 256 threads per row.  Pairs pass through LDS HB at a time
-// (FP32); per pass the products C = V^H X, R = -X + U C - T, G = U^H R are
-// formed by threads over their outputs, and dU += R C^H, dV += X G^H stay in
-// registers (each thread owns fixed gradient entries) until the row is
-// written once: dY in FP32 and its bfloat16 copies.
+// One workgroup of 256 threads per row.  The row's U and V are staged in LDS
+// once (rows padded to R + 1 entries, so threads over consecutive e spread
+// over the banks); pairs pass through LDS hb at a time (FP32).  Per pass:
+// C = V^H X and G = U^H R with the sum over e split into np ranges whose
+// partial sums are added in a fixed order, R = -X + U C - T by threads over
+// (pair, e), and dU += R C^H, dV += X G^H in registers (each thread owns
+// fixed gradient entries) until the row is written once: dY in FP32 and its
+// row-major bfloat16 copy (k_transpose_bf16 makes the transposed one).
+// HO: gradient entries per thread and factor (3N R <= 256 HO); JFIX: R
+// divides 256, so every entry of a thread has the same j and the thread
+// keeps C and G of its column in registers through the dU, dV update.
+template <int HO, bool JFIX>
 __global__ __launch_bounds__(256) void k_head(HeadArgs a) {
-    __shared__ float xs[HB][HMAX3N][2];  // xhat, then kept for dV
-    __shared__ float rs[HB][HMAX3N][2];  // that, then the residual r
-    __shared__ float cs[HB][RMAX][2];
-    __shared__ float gs[HB][RMAX][2];
+    extern __shared__ float2 hsm[];
     __shared__ float sinv[HB];
     __shared__ float lpart[4];
     const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     float* yrow = a.Y + (long)q * a.dout;
-    const int n3 = 3 * a.N, R = a.rank, nf = n3 * R;  // complex entries of U (and of V)
+    const int n3 = 3 * a.N, R = a.rank, RP = R + 1, nf = n3 * R;  // complex entries of U (and of V)
     if (q >= a.rows) {  // padding rows: zero gradient
         for (int j = t; j < a.dout; j += 256) {
             yrow[j] = 0.0f;
             a.dyb[(long)q * a.dout + j] = 0;
-            a.dyt[(long)j * a.ldt + q] = 0;
         }
         if (t == 0) a.lrow[q] = 0.0f;
         return;
     }
-    const float* U = yrow;
-    const float* V = yrow + 2 * nf;
+    const int hb = a.hb;
+    float2* sU = hsm;               // [n3][RP]
+    float2* sV = sU + n3 * RP;      // [n3][RP]
+    float2* xs = sV + n3 * RP;      // [hb][n3]: xhat, kept for dV
+    float2* rs = xs + hb * n3;      // [hb][n3]: that, then r
+    float2* cs = rs + hb * n3;      // [hb][R]
+    float2* gs = cs + hb * R;       // [hb][R]
+    float2* red = gs + hb * R;      // [256] partial sums
+    {
+        const float2* U2 = reinterpret_cast<const float2*>(yrow);
+        for (int i = t; i < nf; i += 256) {
+            const int e = i / R, j = i - e * R;
+            sU[e * RP + j] = U2[i];
+            sV[e * RP + j] = U2[nf + i];
+        }
+    }
     const long S = (long)a.M * a.nk * a.N;
-    float du[HOUT][2], dv[HOUT][2];
+    float2 du[HO], dv[HO];
 #pragma unroll
-    for (int o = 0; o < HOUT; ++o) du[o][0] = du[o][1] = dv[o][0] = dv[o][1] = 0.0f;
+    for (int o = 0; o < HO; ++o) du[o] = dv[o] = make_float2(0.0f, 0.0f);
     float lsum = 0.0f;
-    for (int b0 = 0; b0 < a.batch; b0 += HB) {
-        const int nb = min(HB, a.batch - b0);
+    for (int b0 = 0; b0 < a.batch; b0 += hb) {
+        const int nb = min(hb, a.batch - b0);
+        const int items = nb * R;
+        const int np = items >= 256 ? 1 : 256 / items;  // e ranges of the V^H X and U^H R sums
+        const int elen = (n3 + np - 1) / np;
         for (int i = t; i < nb * n3; i += 256) {  // stage z and J z profiles of mode q
-            const int b = i / n3, e = i % n3;
+            const int b = i / n3, e = i - b * n3;
             const double* zv = a.pairs + (long)a.idx[b0 + b] * 2 * a.vec;
             const long idx = (e / a.N) * S + (long)q * a.N + e % a.N;
-            xs[b][e][0] = (float)zv[2 * idx];
-            xs[b][e][1] = (float)zv[2 * idx + 1];
-            rs[b][e][0] = (float)zv[a.vec + 2 * idx];
-            rs[b][e][1] = (float)zv[a.vec + 2 * idx + 1];
+            const double2 zz = *reinterpret_cast<const double2*>(zv + 2 * idx);
+            const double2 jz = *reinterpret_cast<const double2*>(zv + a.vec + 2 * idx);
+            xs[i] = make_float2((float)zz.x, (float)zz.y);
+            rs[i] = make_float2((float)jz.x, (float)jz.y);
         }
         __syncthreads();
         for (int b = w; b < nb; b += 4) {  // s of each pair: one wave per pair
             float s2 = 0.0f;
-            for (int e = lane; e < n3; e += 64) s2 += xs[b][e][0] * xs[b][e][0] + xs[b][e][1] * xs[b][e][1];
+            for (int e = lane; e < n3; e += 64) s2 += xs[b * n3 + e].x * xs[b * n3 + e].x + xs[b * n3 + e].y * xs[b * n3 + e].y;
             s2 = wave_sum(s2);
             if (lane == 0) sinv[b] = s2 > 0.0f ? 1.0f / sqrtf(s2 / n3) : 0.0f;
         }
         __syncthreads();
         for (int i = t; i < nb * n3; i += 256) {
-            const int b = i / n3, e = i % n3;
-            const float f = sinv[b];
-            xs[b][e][0] *= f;
-            xs[b][e][1] *= f;
-            rs[b][e][0] *= f;
-            rs[b][e][1] *= f;
+            const float f = sinv[i / n3];
+            xs[i].x *= f;
+            xs[i].y *= f;
+            rs[i].x *= f;
+            rs[i].y *= f;
         }
         __syncthreads();
-        for (int i = t; i < nb * R; i += 256) {  // C = V^H X
-            const int b = i / R, j = i % R;
+        for (int i = t; i < items * np; i += 256) {  // partial C = V^H X over e range p
+            const int p = i / items, bj = i - p * items, b = bj / R, j = bj - b * R;
+            const int e0 = p * elen, e1 = min(n3, e0 + elen);
             float cr = 0.0f, ci = 0.0f;
-            for (int e = 0; e < n3; ++e) {
-                const float vr = V[2 * (e * R + j)], vi = V[2 * (e * R + j) + 1];
-                const float xr = xs[b][e][0], xi = xs[b][e][1];
-                cr += vr * xr + vi * xi;
-                ci += vr * xi - vi * xr;
+            for (int e = e0; e < e1; ++e) {
+                const float2 v = sV[e * RP + j], x = xs[b * n3 + e];
+                cr += v.x * x.x + v.y * x.y;
+                ci += v.x * x.y - v.y * x.x;
             }
-            cs[b][j][0] = cr;
-            cs[b][j][1] = ci;
+            if (np == 1) cs[bj] = make_float2(cr, ci);
+            else red[i] = make_float2(cr, ci);
         }
         __syncthreads();
-        for (int i = t; i < nb * n3; i += 256) {  // r = -x + U c - that
-            const int b = i / n3, e = i % n3;
-            float pr = -xs[b][e][0] - rs[b][e][0], pi = -xs[b][e][1] - rs[b][e][1];
-            for (int j = 0; j < R; ++j) {
-                const float ur = U[2 * (e * R + j)], ui = U[2 * (e * R + j) + 1];
-                pr += ur * cs[b][j][0] - ui * cs[b][j][1];
-                pi += ur * cs[b][j][1] + ui * cs[b][j][0];
+        if (np > 1) {
+            for (int bj = t; bj < items; bj += 256) {
+                float2 c = red[bj];
+                for (int p = 1; p < np; ++p) c.x += red[p * items + bj].x, c.y += red[p * items + bj].y;
+                cs[bj] = c;
             }
-            rs[b][e][0] = pr;
-            rs[b][e][1] = pi;
+            __syncthreads();
+        }
+        for (int i = t; i < nb * n3; i += 256) {  // r = -x + U c - that
+            const int b = i / n3, e = i - b * n3;
+            const float2 x = xs[i], th = rs[i];
+            float pr = -x.x - th.x, pi = -x.y - th.y;
+            for (int j = 0; j < R; ++j) {
+                const float2 u = sU[e * RP + j], c = cs[b * R + j];
+                pr += u.x * c.x - u.y * c.y;
+                pi += u.x * c.y + u.y * c.x;
+            }
+            rs[i] = make_float2(pr, pi);
             lsum += pr * pr + pi * pi;
         }
         __syncthreads();
-        for (int i = t; i < nb * R; i += 256) {  // G = U^H r
-            const int b = i / R, j = i % R;
+        for (int i = t; i < items * np; i += 256) {  // partial G = U^H R over e range p
+            const int p = i / items, bj = i - p * items, b = bj / R, j = bj - b * R;
+            const int e0 = p * elen, e1 = min(n3, e0 + elen);
             float gr = 0.0f, gi = 0.0f;
-            for (int e = 0; e < n3; ++e) {
-                const float ur = U[2 * (e * R + j)], ui = U[2 * (e * R + j) + 1];
-                const float rr = rs[b][e][0], ri = rs[b][e][1];
-                gr += ur * rr + ui * ri;
-                gi += ur * ri - ui * rr;
+            for (int e = e0; e < e1; ++e) {
+                const float2 u = sU[e * RP + j], r = rs[b * n3 + e];
+                gr += u.x * r.x + u.y * r.y;
+                gi += u.x * r.y - u.y * r.x;
             }
-            gs[b][j][0] = gr;
-            gs[b][j][1] = gi;
+            if (np == 1) gs[bj] = make_float2(gr, gi);
+            else red[i] = make_float2(gr, gi);
         }
         __syncthreads();
+        if (np > 1) {
+            for (int bj = t; bj < items; bj += 256) {
+                float2 g = red[bj];
+                for (int p = 1; p < np; ++p) g.x += red[p * items + bj].x, g.y += red[p * items + bj].y;
+                gs[bj] = g;
+            }
+            __syncthreads();
+        }
+        if constexpr (JFIX) {  // dU += r c^H, dV += x g^H on this thread's entries (column j0)
+            const int j0 = t % R, e0 = t / R, es = 256 / R;
+#pragma unroll 2
+            for (int b = 0; b < nb; ++b) {
+                const float2 c = cs[b * R + j0], g = gs[b * R + j0];
 #pragma unroll
-        for (int o = 0; o < HOUT; ++o) {  // dU += r c^H, dV += x g^H on this thread's entries
-            const int i = t + 256 * o;
-            if (i < nf) {
-                const int e = i / R, j = i % R;
-                for (int b = 0; b < nb; ++b) {
-                    const float rr = rs[b][e][0], ri = rs[b][e][1], cr = cs[b][j][0], ci = cs[b][j][1];
-                    du[o][0] += rr * cr + ri * ci;
-                    du[o][1] += ri * cr - rr * ci;
-                    const float xr = xs[b][e][0], xi = xs[b][e][1], gr = gs[b][j][0], gi = gs[b][j][1];
-                    dv[o][0] += xr * gr + xi * gi;
-                    dv[o][1] += xi * gr - xr * gi;
+                for (int o = 0; o < HO; ++o) {
+                    const int e = e0 + es * o;
+                    if (e < n3) {
+                        const float2 r = rs[b * n3 + e], x = xs[b * n3 + e];
+                        du[o].x += r.x * c.x + r.y * c.y;
+                        du[o].y += r.y * c.x - r.x * c.y;
+                        dv[o].x += x.x * g.x + x.y * g.y;
+                        dv[o].y += x.y * g.x - x.x * g.y;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < HO; ++o) {
+                const int i = t + 256 * o;
+                if (i < nf) {
+                    const int e = i / R, j = i - e * R;
+                    for (int b = 0; b < nb; ++b) {
+                        const float2 r = rs[b * n3 + e], c = cs[b * R + j];
+                        du[o].x += r.x * c.x + r.y * c.y;
+                        du[o].y += r.y * c.x - r.x * c.y;
+                        const float2 x = xs[b * n3 + e], g = gs[b * R + j];
+                        dv[o].x += x.x * g.x + x.y * g.y;
+                        dv[o].y += x.y * g.x - x.x * g.y;
+                    }
                 }
             }
         }
@@ -540,28 +693,43 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs a) {
     }
     lsum = wave_sum(lsum);
     if (lane == 0) lpart[w] = lsum;
-    __syncthreads();  // every read of this row's factors is done: the row can take dY
+    __syncthreads();
     if (t == 0) a.lrow[q] = ((lpart[0] + lpart[1]) + lpart[2]) + lpart[3];
     const float g2 = 2.0f * a.scale;
+    float2* y2 = reinterpret_cast<float2*>(yrow);
+    uint32_t* yb = reinterpret_cast<uint32_t*>(a.dyb + (long)q * a.dout);  // bf16 pairs
 #pragma unroll
-    for (int o = 0; o < HOUT; ++o) {
-        const int i = t + 256 * o;
+    for (int o = 0; o < HO; ++o) {
+        const int i = t + 256 * o;  // with JFIX: e = e0 + es o, j = j0, i.e. the same i
         if (i < nf) {
-            const float vals[4] = {g2 * du[o][0], g2 * du[o][1], g2 * dv[o][0], g2 * dv[o][1]};
-            const int cols[4] = {2 * i, 2 * i + 1, 2 * nf + 2 * i, 2 * nf + 2 * i + 1};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                yrow[cols[c]] = vals[c];
-                const bf16_t hb = f2bf(vals[c]);
-                a.dyb[(long)q * a.dout + cols[c]] = hb;
-                a.dyt[(long)cols[c] * a.ldt + q] = hb;
-            }
+            const float2 gu = make_float2(g2 * du[o].x, g2 * du[o].y), gv = make_float2(g2 * dv[o].x, g2 * dv[o].y);
+            y2[i] = gu;
+            y2[nf + i] = gv;
+            yb[i] = (uint32_t)f2bf(gu.x) | ((uint32_t)f2bf(gu.y) << 16);
+            yb[nf + i] = (uint32_t)f2bf(gv.x) | ((uint32_t)f2bf(gv.y) << 16);
         }
     }
     for (int j = 4 * nf + t; j < a.dout; j += 256) {
         yrow[j] = 0.0f;
         a.dyb[(long)q * a.dout + j] = 0;
-        a.dyt[(long)j * a.ldt + q] = 0;
+    }
+}
+
+// dst[c][r] = src[r][c] for r < rows, c < cols (bfloat16), through a 64 x 64
+// LDS tile so that both the reads and the writes are row-contiguous.
+__global__ __launch_bounds__(256) void k_transpose_bf16(const bf16_t* __restrict__ src, int rows, int cols, int lds,
+                                                        bf16_t* __restrict__ dst, int ldd) {
+    __shared__ bf16_t tile[64][66];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int y = ty; y < 64; y += 4) {
+        const int r = r0 + y, c = c0 + tx;
+        tile[y][tx] = (r < rows && c < cols) ? src[(size_t)r * lds + c] : (bf16_t)0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 64; y += 4) {
+        const int c = c0 + y, r = r0 + tx;
+        if (c < cols && r < rows) dst[(size_t)c * ldd + r] = tile[tx][y];
     }
 }
 
@@ -835,6 +1003,30 @@ hipError_t gemm(opf_mlp* m, const bf16_t* A, int lda, const bf16_t* B, int ldb, 
                 const Epi& e) {
     if (rows % GT || cols % GT || K % 16 || lda % 8 || ldb % 8 || rows <= 0 || cols <= 0 || K <= 0)
         return hipErrorInvalidValue;
+    if (rows % G2 == 0 && cols % G2 == 0 && K % GK2 == 0 && (double)rows * cols * K >= (double)(1L << 30)) {
+        // large product: 128 x 128 tiles, K split until about 256 workgroups
+        const long tiles = (long)(rows / G2) * (cols / G2);
+        int nsplit = 1, kc = K;
+        if (tiles < 256) {
+            nsplit = (int)std::min<long>((256 + tiles - 1) / tiles, std::min(K / 256, 2 * GSPLIT));
+            if ((size_t)nsplit * rows * cols > GPART) nsplit = (int)(GPART / ((size_t)rows * cols));
+            nsplit = std::max(nsplit, 1);
+            kc = (K + nsplit - 1) / nsplit;
+            kc = (kc + GK2 - 1) / GK2 * GK2;
+            nsplit = (K + kc - 1) / kc;
+        }
+        if (nsplit == 1) {
+            hipLaunchKernelGGL(k_gemm128, dim3(cols / G2, rows / G2, 1), dim3(256), 0, m->s, A, lda, B, ldb, K, K, e,
+                               nullptr);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL(k_gemm128, dim3(cols / G2, rows / G2, nsplit), dim3(256), 0, m->s, A, lda, B, ldb, K, kc,
+                           e, m->gpart);
+        const size_t n = (size_t)rows * cols;
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, m->s, m->gpart, rows,
+                           cols, nsplit, e);
+        return hipGetLastError();
+    }
     const long tiles = (long)(rows / GT) * (cols / GT);
     int nsplit = 1, kc = K;
     if (tiles < 1024 && K >= 512) {
@@ -988,11 +1180,17 @@ hipError_t backward_pairs(opf_mlp* m, const double* pairs, const int* idx, int b
     a.rp = rp;
     a.Y = m->Y;
     a.dyb = m->dYb;
-    a.dyt = m->dYT;
-    a.ldt = m->R;
     a.lrow = m->lrow;
     a.scale = (float)(1.0 / ((double)batch * m->mode_rows));
-    hipLaunchKernelGGL(k_head, dim3(rp), dim3(256), 0, s, a);
+    a.hb = head_pairs(3 * m->N, m->rank);
+    const size_t hl = (size_t)head_slots(3 * m->N, m->rank, a.hb) * sizeof(float2);
+    const int nf = 3 * m->N * m->rank, ho = nf <= 768 ? 3 : nf <= 1536 ? 6 : nf <= 2304 ? 9 : 12;
+    const bool jfix = 256 % m->rank == 0;
+    auto kh = jfix ? (ho == 3 ? k_head<3, true> : ho == 6 ? k_head<6, true> : ho == 9 ? k_head<9, true> : k_head<12, true>)
+                   : (ho == 3 ? k_head<3, false> : ho == 6 ? k_head<6, false> : ho == 9 ? k_head<9, false> : k_head<12, false>);
+    hipLaunchKernelGGL(kh, dim3(rp), dim3(256), hl, s, a);
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((m->dout + 63) / 64, (rp + 63) / 64), dim3(256), 0, s, m->dYb, rp,
+                       m->dout, m->dout, m->dYT, m->R);
     hipLaunchKernelGGL(k_weight_sum, dim3(1), dim3(256), 0, s, nullptr, batch * m->mode_rows, m->wsum);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, m->lrow, m->mode_rows, m->wsum, loss_slot);
     const hipError_t st = hipGetLastError();

@@ -675,15 +675,15 @@ int default_gm(int mp) { return mp == 1 ? 4 : (mp <= 3 ? 2 : 1); }
 
 bool gm_ok(int gm, int mp) { return gm >= 1 && gm <= 4 && mp * (gm - 1) + 3 <= NFH; }
 
-hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int members, int precision,
-                              hipStream_t s) {
+static hipError_t launch_solve_any(const SolveArgs& a, const SolveArgs* batch, int members, int precision,
+                                   hipStream_t s, const KernelTiming& kt) {
     const bool b = batch != nullptr;
     const dim3 grid(a.K * ((a.M + a.gm - 1) / a.gm), b ? members : 1), block(256);
     // NB rows and NW narrow rows as the factor images were written
     // (solve_nb, solve_nw); the members of a batch share N and with it both
 #define OPF_SOLVE_LAUNCH(TNL, NB, NW)                                                   \
     if (b) hipLaunchKernelGGL((k_solve_b<TNL, NB, NW>), grid, block, 0, s, batch); \
-    else hipLaunchKernelGGL((k_solve<TNL, NB, NW>), grid, block, 0, s, a);
+    else launch_timed((k_solve<TNL, NB, NW>), grid, block, 0, s, kt, a);
 #define OPF_SOLVE_NW(TNL, NB)                                                       \
     if (solve_nw(a.N, a.narrow) == NB - 9) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 9) }   \
     else if (solve_nw(a.N, a.narrow) == NB - 25) { OPF_SOLVE_LAUNCH(TNL, NB, NB - 25) } \
@@ -703,8 +703,13 @@ hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int me
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s) {
-    return launch_solve_batch(a, nullptr, 1, precision, s);
+hipError_t launch_solve_batch(const SolveArgs& a, const SolveArgs* batch, int members, int precision,
+                              hipStream_t s) {
+    return launch_solve_any(a, batch, members, precision, s, KernelTiming{});
+}
+
+hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s, const KernelTiming& kt) {
+    return launch_solve_any(a, nullptr, 1, precision, s, kt);
 }
 
 // Boundary-condition residual and interior divergence of every mode (one

@@ -658,43 +658,44 @@ bool ztile_ok(int zt, int K) { return (zt == 4 || zt == 8 || zt == 16) && radix_
 bool tz_ok(int tz, int M) { return (tz == 2 || tz == 4 || tz == 8) && radix_of(3 * M) * tz <= 64; }
 
 template <typename TS, typename T, int L, int ZT>
-static void launch_z(const NLArgs& a, const NLArgs* batch, int members, bool inv, hipStream_t s) {
+static void launch_z(const NLArgs& a, const NLArgs* batch, int members, bool inv, hipStream_t s, const KernelTiming& kt) {
     const int ntile = (a.N + ZT - 1) / ZT;
     const bool b = batch != nullptr;
     if constexpr (ZT * radix_max<L>() <= NT2) {
         if (inv) {
             const dim3 g(6 * a.M * ntile, b ? members : 1);
             if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, batch);
-            else hipLaunchKernelGGL((k_zinv<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, a);
+            else launch_timed((k_zinv<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, kt, a);
         } else {
             const dim3 g(3 * a.M * ntile, b ? members : 1);
             if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, batch);
-            else hipLaunchKernelGGL((k_zfwd<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, a);
+            else launch_timed((k_zfwd<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, kt, a);
         }
     }
 }
 
 template <typename T, int L, int TZ>
-static void launch_theta(const NLArgs& a, const NLArgs* batch, int members, hipStream_t s) {
+static void launch_theta(const NLArgs& a, const NLArgs* batch, int members, hipStream_t s, const KernelTiming& kt) {
     if constexpr (TZ * radix_max<L>() <= 64) {
         const dim3 g(a.N * ((3 * a.K + TZ - 1) / TZ), batch ? members : 1);
         if (batch) hipLaunchKernelGGL((k_theta_lp_b<T, L, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, batch);
-        else if (a.rotating) hipLaunchKernelGGL((k_theta_lp<T, L, true, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, a);
-        else hipLaunchKernelGGL((k_theta_lp<T, L, false, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, a);
+        else if (a.rotating) launch_timed((k_theta_lp<T, L, true, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, kt, a);
+        else launch_timed((k_theta_lp<T, L, false, TZ>), g, dim3(NT3), (theta_lp_lds<T, L, TZ>()), s, kt, a);
     }
 }
 
 template <typename TS, typename T>
-static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s) {
+static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members, int stage, hipStream_t s,
+                               const KernelTiming& kt = KernelTiming{}) {
     const int L3K = 3 * a.K, L3M = 3 * a.M;
     if (stage == 1) {
         if (!tz_ok(a.tz, a.M)) return hipErrorInvalidValue;
         switch (L3M) {
 #define OPF_CASE(V)                                                        \
     case V:                                                                \
-        if (a.tz == 2) launch_theta<T, V, 2>(a, batch, members, s);        \
-        else if (a.tz == 4) launch_theta<T, V, 4>(a, batch, members, s);   \
-        else launch_theta<T, V, 8>(a, batch, members, s);                  \
+        if (a.tz == 2) launch_theta<T, V, 2>(a, batch, members, s, kt);      \
+        else if (a.tz == 4) launch_theta<T, V, 4>(a, batch, members, s, kt); \
+        else launch_theta<T, V, 8>(a, batch, members, s, kt);                \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -706,9 +707,9 @@ static hipError_t launch_typed(const NLArgs& a, const NLArgs* batch, int members
         switch (L3K) {
 #define OPF_CASE(V)                                                                \
     case V:                                                                        \
-        if (a.ztile == 4) launch_z<TS, T, V, 4>(a, batch, members, inv, s);        \
-        else if (a.ztile == 8) launch_z<TS, T, V, 8>(a, batch, members, inv, s);   \
-        else launch_z<TS, T, V, 16>(a, batch, members, inv, s);                    \
+        if (a.ztile == 4) launch_z<TS, T, V, 4>(a, batch, members, inv, s, kt);      \
+        else if (a.ztile == 8) launch_z<TS, T, V, 8>(a, batch, members, inv, s, kt); \
+        else launch_z<TS, T, V, 16>(a, batch, members, inv, s, kt);                  \
         break;
             OPF_FOR_LENGTHS(OPF_CASE)
 #undef OPF_CASE
@@ -724,9 +725,9 @@ hipError_t launch_nonlinear_batch(const NLArgs& proto, const NLArgs* dev_args, i
     return launch_typed<double, double>(proto, dev_args, members, stage, s);
 }
 
-hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s) {
-    if (precision == OPF_MIXED) return launch_typed<float, float>(a, nullptr, 1, stage, s);
-    return launch_typed<double, double>(a, nullptr, 1, stage, s);
+hipError_t launch_nonlinear_stage(const NLArgs& a, int precision, int stage, hipStream_t s, const KernelTiming& kt) {
+    if (precision == OPF_MIXED) return launch_typed<float, float>(a, nullptr, 1, stage, s, kt);
+    return launch_typed<double, double>(a, nullptr, 1, stage, s, kt);
 }
 
 hipError_t launch_cfl(const NLArgs& a, int precision, const double* wr, const double* wt, double wz, double* out,
