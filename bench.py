@@ -68,10 +68,10 @@ def step_bytes_compulsory(N, M, K, mixed):
         (3 * S64 + 6 * S + 3 * S64 + (6 * S if mixed else 3 * S64))
 
 
-def traffic_for(kernel, precision):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_pipe64_{precision}.json")
+def traffic_for(kernel, precision, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -499,7 +499,7 @@ def main():
         b = bytes_all / launches
         avg_ms = tot[dom] / launches
         ach = b / (avg_ms * 1e-3) / 1e9
-        tr = traffic_for(dom, prec)
+        tr = traffic_for(dom, prec, args.workload)
         return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": tr, "alg_bytes_per_launch": int(b),
@@ -507,7 +507,7 @@ def main():
                 "kernels_us": {k: round(v * 1e3, 2) for k, v in per.items()}}
 
     out = {
-        "metric": "time steps/s (FP64 predictor-corrector step) and HBM GB/s at N=64, |m|<48, |k|<64",
+        "metric": f"time steps/s (FP64 predictor-corrector step) and HBM GB/s at N={N}, |m|<{M}, |k|<{K}",
         "value": round(1.0 / ms64, 2),
         "unit": "steps/s",
         "n_gpus": 1,
@@ -519,7 +519,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic: laminar pipe flow + seeded divergence-free perturbation (10% laminar energy)",
+        "data": f"synthetic: laminar pipe flow + seeded divergence-free perturbation "
+                f"({100 * w['energy_frac']:g}% laminar energy)",
         "config": {"workload": f"{args.workload}: N={N} radial points, |m|<{M}, |k|<{K} "
                                f"(grid {N}x{3 * M}x{3 * K}), alpha={w['alpha']}, Re={w['Re']}, "
                                f"dt={w['dt']}, fixed flux, seed {w['seed']}",

@@ -585,9 +585,11 @@ opf_status opf_ensemble_workspace_size(const opf_params* members, int32_t count,
  * m per radial-solve workgroup (1, 2 or 4 with mp (gm - 1) + 3 <= 6), tz
  * axial points per theta-stage workgroup (2, 4 or 8) and ztile radial lines
  * per z-transform workgroup (4, 8 or 16), each while the longer radix pass
- * of the transform length fits the workgroup (tz r <= 64, ztile r <= 128,
- * r = 12 for lengths 144 and 192 ... 3 for 6).  Results never depend on the
- * tiles, only the speed.  members and us_per_step are informative. */
+ * of the transform length fits the workgroup (tz r <= 64; ztile r <= 256,
+ * with 256-thread z workgroups when ztile r > 128; r the larger radix of the
+ * length's two-pass split: 16 for 192, 12 for 144 ... 3 for 6).  Results
+ * never depend on the tiles, only the speed.  members and us_per_step are
+ * informative. */
 typedef struct {
     int32_t N, M, K, mp, precision;
     int32_t members;

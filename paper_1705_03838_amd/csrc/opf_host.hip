@@ -725,6 +725,7 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     c->MU = p->mp * (M - 1) + 2;
     c->nfac = c->MU * K + M * K;
     c->gm = default_gm(p->mp);
+    c->ztile = default_ztile(p->precision);
 
     build_grid(c, p->r_nodes);
 
@@ -2668,6 +2669,7 @@ opf_status opf_ensemble_create(const opf_params* members, int32_t count, void* w
             k->mp = p.mp;
             k->precision = p.precision;
             k->gm = default_gm(p.mp);
+            k->ztile = default_ztile(p.precision);
             for (const TileChoice& t : cached)  // tiles from the cache, where it has the class
                 if (t.N == p.N && t.M == p.M && t.K == p.K && t.mp == p.mp && t.precision == p.precision) {
                     k->gm = t.gm;

@@ -169,6 +169,10 @@ bool nonlinear_supported(int M, int K);
 bool tz_ok(int tz, int M);
 bool ztile_ok(int zt, int K);
 constexpr int DEFAULT_TZ = 4, DEFAULT_ZTILE = 8;
+// Radial lines per z workgroup before any tuning: 16 with FP32 transforms
+// (half the bytes per line, so the same bytes per workgroup as 8 lines in
+// FP64), else 8.
+inline int default_ztile(int precision) { return precision == OPF_MIXED ? 16 : DEFAULT_ZTILE; }
 hipError_t launch_solve(const SolveArgs& a, int precision, hipStream_t s, const KernelTiming& kt = KernelTiming{});
 // Batched forms: one launch for `members` argument records in device memory
 // (grid.y = member); `proto` gives the shared sizes.

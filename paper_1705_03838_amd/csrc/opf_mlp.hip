@@ -604,6 +604,7 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs a) {
             const int p = i / items, bj = i - p * items, b = bj / R, j = bj - b * R;
             const int e0 = p * elen, e1 = min(n3, e0 + elen);
             float cr = 0.0f, ci = 0.0f;
+#pragma unroll 4
             for (int e = e0; e < e1; ++e) {
                 const float2 v = sV[e * RP + j], x = xs[b * n3 + e];
                 cr += v.x * x.x + v.y * x.y;
@@ -625,6 +626,7 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs a) {
             const int b = i / n3, e = i - b * n3;
             const float2 x = xs[i], th = rs[i];
             float pr = -x.x - th.x, pi = -x.y - th.y;
+#pragma unroll 4
             for (int j = 0; j < R; ++j) {
                 const float2 u = sU[e * RP + j], c = cs[b * R + j];
                 pr += u.x * c.x - u.y * c.y;
@@ -638,6 +640,7 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs a) {
             const int p = i / items, bj = i - p * items, b = bj / R, j = bj - b * R;
             const int e0 = p * elen, e1 = min(n3, e0 + elen);
             float gr = 0.0f, gi = 0.0f;
+#pragma unroll 4
             for (int e = e0; e < e1; ++e) {
                 const float2 u = sU[e * RP + j], r = rs[b * n3 + e];
                 gr += u.x * r.x + u.y * r.y;

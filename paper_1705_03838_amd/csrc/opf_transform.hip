@@ -193,7 +193,10 @@ constexpr size_t z_lds() {
     return (size_t)(radix_max<L>() * radix_max<L>() + ZT * (INV ? ZLayout<L>::LSI : ZLayout<L>::LSF)) * sizeof(cpx<T>);
 }
 
-constexpr int NT2 = 128;  // threads of a z-transform workgroup (ZT radial lines, ZT max(RA, RB) <= 128)
+// Threads of a z-transform workgroup: 128, or 256 when ZT radial lines of
+// the longer radix pass need more (ZT max(RA, RB) <= 256).
+template <int L, int ZT>
+constexpr int z_threads() { return ZT * radix_max<L>() <= 128 ? 128 : 256; }
 
 // ---------------------------------------------------------------------------
 // k_zinv: spectral [M][nk][N] -> H[f][n][m][z], z = 0..3K-1 (inverse, zero
@@ -202,6 +205,7 @@ template <typename TS, typename T, int L, int ZT>
 __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSI, RM = radix_max<L>();
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
+    constexpr int NT2 = z_threads<L, ZT>();
     static_assert(ZT * RM <= NT2, "a pass must fit the workgroup");
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
@@ -252,9 +256,9 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
 }
 
 template <typename TS, typename T, int L, int ZT>
-__global__ __launch_bounds__(NT2) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L, ZT>(a); }
+__global__ __launch_bounds__((z_threads<L, ZT>())) void k_zinv(NLArgs a) { k_zinv_body<TS, T, L, ZT>(a); }
 template <typename TS, typename T, int L, int ZT>
-__global__ __launch_bounds__(NT2) void k_zinv_b(const NLArgs* __restrict__ aa) {
+__global__ __launch_bounds__((z_threads<L, ZT>())) void k_zinv_b(const NLArgs* __restrict__ aa) {
     k_zinv_body<TS, T, L, ZT>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
@@ -574,6 +578,7 @@ template <typename TS, typename T, int L, int ZT>
 __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
     constexpr int RA = TwoPass<L>::RA, RB = TwoPass<L>::RB, LS = ZLayout<L>::LSF, RM = radix_max<L>();
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
+    constexpr int NT2 = z_threads<L, ZT>();
     static_assert(ZT * RM <= NT2, "a pass must fit the workgroup");
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
@@ -625,9 +630,9 @@ __device__ __forceinline__ void k_zfwd_body(const NLArgs& a) {
 }
 
 template <typename TS, typename T, int L, int ZT>
-__global__ __launch_bounds__(NT2) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L, ZT>(a); }
+__global__ __launch_bounds__((z_threads<L, ZT>())) void k_zfwd(NLArgs a) { k_zfwd_body<TS, T, L, ZT>(a); }
 template <typename TS, typename T, int L, int ZT>
-__global__ __launch_bounds__(NT2) void k_zfwd_b(const NLArgs* __restrict__ aa) {
+__global__ __launch_bounds__((z_threads<L, ZT>())) void k_zfwd_b(const NLArgs* __restrict__ aa) {
     k_zfwd_body<TS, T, L, ZT>(aa[blockIdx.y]);  // record read in place, not copied to scratch
 }
 
@@ -654,22 +659,23 @@ static int radix_of(int L) {
     }
 }
 
-bool ztile_ok(int zt, int K) { return (zt == 4 || zt == 8 || zt == 16) && radix_of(3 * K) * zt <= NT2; }
+bool ztile_ok(int zt, int K) { return (zt == 4 || zt == 8 || zt == 16) && radix_of(3 * K) * zt <= 256; }
 bool tz_ok(int tz, int M) { return (tz == 2 || tz == 4 || tz == 8) && radix_of(3 * M) * tz <= 64; }
 
 template <typename TS, typename T, int L, int ZT>
 static void launch_z(const NLArgs& a, const NLArgs* batch, int members, bool inv, hipStream_t s, const KernelTiming& kt) {
     const int ntile = (a.N + ZT - 1) / ZT;
     const bool b = batch != nullptr;
-    if constexpr (ZT * radix_max<L>() <= NT2) {
+    if constexpr (ZT * radix_max<L>() <= 256) {
+        constexpr int NT = z_threads<L, ZT>();
         if (inv) {
             const dim3 g(6 * a.M * ntile, b ? members : 1);
-            if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, batch);
-            else launch_timed((k_zinv<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, true, ZT>()), s, kt, a);
+            if (b) hipLaunchKernelGGL((k_zinv_b<TS, T, L, ZT>), g, dim3(NT), (z_lds<T, L, true, ZT>()), s, batch);
+            else launch_timed((k_zinv<TS, T, L, ZT>), g, dim3(NT), (z_lds<T, L, true, ZT>()), s, kt, a);
         } else {
             const dim3 g(3 * a.M * ntile, b ? members : 1);
-            if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, batch);
-            else launch_timed((k_zfwd<TS, T, L, ZT>), g, dim3(NT2), (z_lds<T, L, false, ZT>()), s, kt, a);
+            if (b) hipLaunchKernelGGL((k_zfwd_b<TS, T, L, ZT>), g, dim3(NT), (z_lds<T, L, false, ZT>()), s, batch);
+            else launch_timed((k_zfwd<TS, T, L, ZT>), g, dim3(NT), (z_lds<T, L, false, ZT>()), s, kt, a);
         }
     }
 }

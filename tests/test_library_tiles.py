@@ -1,9 +1,8 @@
 """Tile cache of the batched ensemble step (host only, no device): entries
 written by the library read back unchanged; a cache in the same format
 written by hand (extra keys, candidates, other key order) parses; malformed
-files and inadmissible tiles (a z-tile whose radix pass exceeds the
-workgroup, gm = 4 for mp = 2, tz = 8 with the radix-16 length 192) are
-rejected."""
+files and inadmissible tiles (a z-tile other than 4, 8, 16, gm = 4 for
+mp = 2, tz = 8 with the radix-16 length 192) are rejected."""
 import json
 
 import pytest
@@ -36,7 +35,7 @@ def test_hand_written_cache_parses(tmp_path):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(ENTRIES[0], ztile=16, K=64),   # length 192, radix 16: 16 x 16 > 128
+    dict(ENTRIES[0], ztile=32, K=64),   # z tiles are 4, 8 or 16 radial lines
     dict(ENTRIES[0], tz=8, M=64),       # length 192 in theta: 8 x 16 > 64
     dict(ENTRIES[2], gm=4),             # mp = 2 shares at most 2 m
     dict(ENTRIES[0], tz=3),
