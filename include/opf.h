@@ -56,7 +56,7 @@ enum { OPF_SOLVE_PRED = 0, OPF_SOLVE_CORR = 1, OPF_SOLVE_RAW = 2 };
  * N radial points, |m| < M, |k| < K).
  *  N        radial points, 12 <= N <= 64
  *  M, K     Fourier modes |m| < M, |k| < K; 3M and 3K must factor into 2s and
- *           3s (the dealiased grid is 3K x 3M), 2 <= M <= 48, 2 <= K <= 64
+ *           3s (the dealiased grid is 3K x 3M), 2 <= M <= 64, 2 <= K <= 64
  *  mp       azimuthal periodicity (rotational symmetry order), >= 1
  *  stencil  finite-difference points, must be 9
  *  alpha    axial wavenumber (pipe length 2pi/alpha), > 0

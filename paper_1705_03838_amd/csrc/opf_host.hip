@@ -73,7 +73,7 @@ opf_status validate(const opf_params* p, std::string* why) {
     if (p->stencil != W9) return bad("stencil must be 9");
     if (p->N < 12) return bad("N must be >= 12");
     if (p->N > NMAX) { if (why) *why = "N > 64 not supported"; return OPF_E_UNSUPPORTED; }
-    if (p->M < 2 || p->K < 2 || p->M > 48 || p->K > 64) return bad("M must be in [2, 48], K in [2, 64]");
+    if (p->M < 2 || p->K < 2 || p->M > 64 || p->K > 64) return bad("M and K must be in [2, 64]");
     if (!factor23(3 * p->M) || !factor23(3 * p->K) || !nonlinear_supported(p->M, p->K)) {
         if (why) *why = "3M and 3K must be supported FFT lengths (2^a 3^b <= 192)";
         return OPF_E_UNSUPPORTED;

@@ -22,6 +22,8 @@ CASES = {
     "mp3": dict(N=33, M=6, K=3, mp=3, alpha=1.1, Re=1200.0, dt=0.01),
     # 49 <= N <= 63: the 64-row solve with NB - 25 narrow substitution rows
     "n56": dict(N=56, M=6, K=4, mp=1, alpha=1.0, Re=3000.0, dt=0.005),
+    # the longest theta line, 3M = 192
+    "m64": dict(N=14, M=64, K=3, mp=1, alpha=1.2, Re=1000.0, dt=0.01),
 }
 
 
