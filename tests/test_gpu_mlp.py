@@ -36,11 +36,11 @@ def torch_cuda():
     return torch
 
 
-def make_net(torch_cuda, width=64, layers=3, max_rows=0, seed=7, **kw):
+def make_net(torch_cuda, width=64, layers=3, max_rows=0, seed=7, rank=RANK, **kw):
     import paper_1705_03838_amd as opf
     from oracle.mlp import flatten, init_params, unflatten
     s = make_solver(**GRID)
-    net = opf.Mlp(s, width=width, layers=layers, rank=RANK, max_rows=max_rows, **kw)
+    net = opf.Mlp(s, width=width, layers=layers, rank=rank, max_rows=max_rows, **kw)
     p = init_params(net.din, width, layers, net.dout, seed=seed)
     rng = np.random.default_rng(seed)
     for k in p:
@@ -162,9 +162,12 @@ def test_factors_and_precondition_match_oracle(torch_cuda):
     assert np.array_equal(z0, -v)
 
 
-def test_pair_gradient_matches_oracle(torch_cuda):
+@pytest.mark.parametrize("rank", [RANK, 3])
+def test_pair_gradient_matches_oracle(torch_cuda, rank):
+    """Rank 2 divides the loss head's 256 threads (each thread keeps one
+    column's C and G in registers); rank 3 takes the general path."""
     from oracle.mlp import backprop, feature_rows, forward, head
-    s, net, p = make_net(torch_cuda)
+    s, net, p = make_net(torch_cuda, rank=rank)
     pairs = np.stack([np.stack([field(s, 40 + i), field(s, 50 + i)]) for i in range(5)])
     pairs[2, 1, :, 3, 2] = 0.0  # an empty (J z) profile: that mode-pair is skipped
     idx = np.array([3, 0, 2, 2], dtype=np.int32)
@@ -173,11 +176,11 @@ def test_pair_gradient_matches_oracle(torch_cuda):
     # the head on the device's own model rows: FP32 accumulation of the loss only
     X = feature_rows(GRID["M"], GRID["K"], GRID["mp"], GRID["alpha"])
     Fdev = net.forward(torch_cuda.from_numpy(X.astype(np.float32))).cpu().numpy().astype(np.float64)
-    Ldev, _ = head(Fdev, pairs[idx], RANK)
+    Ldev, _ = head(Fdev, pairs[idx], rank)
     say("   loss", lg, Ldev)
     assert abs(lg - Ldev) <= 1e-5 * Ldev
     F, cache = forward(p, X, 3, bf16=True)
-    L, dF = head(F.astype(np.float32).astype(np.float64), pairs[idx], RANK)
+    L, dF = head(F.astype(np.float32).astype(np.float64), pairs[idx], rank)
     assert abs(lg - L) <= 1e-2 * L
     gref = backprop(p, cache, dF, 3, bf16=True)
     check_grads(g, gref, 3)
