@@ -174,15 +174,27 @@ __device__ __forceinline__ void lds_dma16(const void* src, void* dst_wave) {
 }
 __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
-// Copy nbytes (a multiple of 16; both ends 16-byte aligned) from global
-// memory to LDS by DMA, 1 KB per wave instruction, the four waves taking
-// alternate kilobytes.
-__device__ __forceinline__ void dma_copy(const void* src, void* dst, int nbytes, int w, int lane) {
-    const int nch = (nbytes + 1023) >> 10;
-    for (int ch = w; ch < nch; ch += 4) {
-        const int off = (ch << 10) + 16 * lane;
-        if (off < nbytes)
-            lds_dma16(static_cast<const char*>(src) + off, static_cast<char*>(dst) + (ch << 10));
+// LDS stride (doubles) of a factor image of FW doubles: FW rounded up to 2
+// more than a multiple of 32, so that image o starts 4 o four-byte words
+// past a bank boundary.  The substitution lanes of different operators read
+// the same row at the same time; with images a whole number of bank periods
+// apart those reads would all hit the same four banks.
+constexpr int solve_image_lds_stride(int FW) { return FW + (34 - FW % 32) % 32; }
+
+// Copy nimg consecutive factor images of FW doubles each from global memory
+// to LDS at a stride of FWP doubles, by DMA: 1 KB per wave instruction, the
+// four waves taking alternate kilobytes.  FW * 8 and FWP * 8 are multiples of
+// 16 and both ends 16-byte aligned.
+template <int FW, int FWP>
+__device__ __forceinline__ void dma_images(const double* src, double* dst, int nimg, int w, int lane) {
+    constexpr int NB8 = FW * 8, NCH = (NB8 + 1023) >> 10;
+    static_assert(NB8 % 16 == 0 && (FWP * 8) % 16 == 0, "16-byte DMA units");
+    for (int ch = w; ch < nimg * NCH; ch += 4) {
+        const int im = ch / NCH, c = ch - im * NCH;
+        const int off = (c << 10) + 16 * lane;
+        if (off < NB8)
+            lds_dma16(reinterpret_cast<const char*>(src + (size_t)im * FW) + off,
+                      reinterpret_cast<char*>(dst + im * FWP) + (c << 10));
     }
 }
 
@@ -219,16 +231,17 @@ struct Row9 {
 template <typename TNL, int NB, int NW>
 __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     constexpr int FW = solve_image_doubles(NB, NW);
+    constexpr int FWP = solve_image_lds_stride(FW);  // image stride in LDS
     constexpr int XS = NB + 1;         // radial line stride (complex)
-    constexpr int FA = NFH * FW;       // factor area (doubles)
-    static_assert(4 * FW + NSLOT * XS * 2 <= FA, "pressure images and columns fit the factor area");
+    constexpr int FA = NFH * FWP;      // factor area (doubles)
+    static_assert(4 * FWP + NSLOT * XS * 2 <= FA, "pressure images and columns fit the factor area");
     __shared__ __align__(16) double sF[FA];
     __shared__ __align__(16) dcplx sX[NSLOT][3][XS];
     // slot q's A^-1 (32 doubles), overwritten by its correction a (8 doubles)
     // once read; the flux correction of (0,0) in slot 0's last entry
     __shared__ __align__(16) double sAi[NSLOT][32];
     double& sGam = sAi[0][31];
-    dcplx(*sY)[XS] = reinterpret_cast<dcplx(*)[XS]>(sF + 4 * FW);  // pressure columns
+    dcplx(*sY)[XS] = reinterpret_cast<dcplx(*)[XS]>(sF + 4 * FWP);  // pressure columns
 
     const Tables& t = a.t;
     const int N = a.N, K = a.K, nk = a.nk, mp = a.mp;
@@ -276,7 +289,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             for (int c = 0; c < 3; ++c)
                 if (n < N) lds_dma16(src + 2 * (c * S + slot_off(q) + n), &sX[q][c][0]);
         }
-        dma_copy(t.img + ippe * FW, sF, nfp * FW * 8, w, n);
+        dma_images<FW, FWP>(t.img + ippe * FW, sF, nfp, w, n);
         if (w == 0) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {  // four slots (16 lanes of 16 bytes each) per instruction
@@ -386,14 +399,14 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     }
     __syncthreads();
     if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1))
-        lds_solve<NB, NW>(sF + (n >> 2) * FW, &sY[n >> 1][0].x + (n & 1));
+        lds_solve<NB, NW>(sF + (n >> 2) * FWP, &sY[n >> 1][0].x + (n & 1));
     __syncthreads();
 
     // ---- R -= grad P, scaled by 1/U_ii of each Helmholtz operator; (0,0):
     //      u_r = 0, real R_theta and R_z.  The Helmholtz images that do not
     //      cover the pressure columns are requested first.
     const int nfh1 = min(nfh, 4);
-    dma_copy(t.img + ihelm * FW, sF, nfh1 * FW * 8, w, n);
+    dma_images<FW, FWP>(t.img + ihelm * FW, sF, nfh1, w, n);
     {
         Row9 W1e;
         W1e.load(t.d1, N, mw & 1, nr);
@@ -441,7 +454,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     }
     __syncthreads();  // the pressure columns are read: the rest of the Helmholtz images may land there
     if (nfh > nfh1)
-        dma_copy(t.img + (ihelm + nfh1) * FW, sF + nfh1 * FW, (nfh - nfh1) * FW * 8, w, n);
+        dma_images<FW, FWP>(t.img + (ihelm + nfh1) * FW, sF + nfh1 * FWP, nfh - nfh1, w, n);
     lds_dma_wait();
     __syncthreads();
     if (w == 0 && n < 6 * NSLOT) {
@@ -449,7 +462,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         if (slot_ok(q)) {
             const int m = mp * (m0 + (q >> 1));
             const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
-            lds_solve<NB, NW>(sF + (mu - mu_lo) * FW, &sX[q][c][0].x + (n & 1));
+            lds_solve<NB, NW>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (n & 1));
         }
     }
     __syncthreads();
