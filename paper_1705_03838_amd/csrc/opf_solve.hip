@@ -50,6 +50,20 @@ __device__ __forceinline__ dcplx load_c(const void* base, size_t idx) {
     const T* p = reinterpret_cast<const T*>(base) + 2 * idx;
     return {double(p[0]), double(p[1])};
 }
+// A complex value as stored (two T), read now and widened where it is used.
+template <typename T>
+struct vec2 {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ vec2<T> load_v(const void* base, size_t idx) {
+    const T* p = reinterpret_cast<const T*>(base) + 2 * idx;
+    return {p[0], p[1]};
+}
+template <typename T>
+__device__ __forceinline__ dcplx to_c(vec2<T> v) {
+    return {double(v.x), double(v.y)};
+}
 template <typename T>
 __device__ __forceinline__ void store_c(void* base, size_t idx, dcplx v) {
     T* p = reinterpret_cast<T*>(base) + 2 * idx;
@@ -76,89 +90,103 @@ __device__ __forceinline__ void curl_row(dcplx duz, dcplx dut, double rinv, int 
 // lane per right-hand side.  Forward sweep with the unit lower Lh, right-
 // looking: once y_i is known it updates the next four (eight from row NW on)
 // entries, kept in registers, so one multiply-add per row lies on the
-// dependency chain; backward sweep with the unit upper W likewise.  Factor
-// rows and right-hand-side entries are fetched PF rows ahead.  Each row's
-// instructions stay in place (a scheduling barrier per row): free scheduling
-// would hoist the LDS reads of many rows at once, far past the register
-// budget of three workgroups per compute unit.
+// dependency chain; backward sweep with the unit upper W likewise.
+//
+// The sweeps are bound by LDS latency: a row's factor record and right-hand-
+// side entry are read DN rows ahead (DW for the wide rows past NW, whose
+// records are twice as long), within the register budget of three
+// workgroups per compute unit.  Rows go in pairs so that the two entries
+// read and the two results written become one ds_read2 / ds_write2 each:
+// three LDS instructions per row, which keeps about five rows in flight
+// under the LDS counter's limit of 15.  Each pair's instructions stay in
+// place (a scheduling barrier per pair): free scheduling would hoist the
+// reads of many rows at once.
 template <int NB, int NW>
 __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* col) {
-    constexpr int PF = 4;
+    constexpr int DN = 6, DW = 4, DB = 6;  // read-ahead in rows: narrow and wide forward rows, backward rows
+    static_assert(NB % 2 == 0, "rows go in pairs");
     constexpr int FWD = solve_image_fwd(NB, NW);
     auto frow = [](int i) { return i < NW ? 4 * i : 4 * NW + 8 * (i - NW); };
     auto brow = [](int i) { return FWD + 4 * (i - 1); };
-    double2 L[PF][4];
-    double nb[PF];  // col[i + 8] for the coming rows
+    // row r is requested just before row issue(r) is computed (r <= 7: before the sweep)
+    auto fissue = [](int r) { return r - (r < NW ? DN : DW); };
+    double2 Lr[NB][4];
+    double nb[NB];  // col[2 (r + 8)] for row r
+    auto fload = [&](int r) {
+        const double2* f = reinterpret_cast<const double2*>(F + frow(r));
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-        const double2* f = reinterpret_cast<const double2*>(F + frow(p));
+        for (int j = 0; j < (r < NW ? 2 : 4); ++j) Lr[r][j] = f[j];
+        nb[r] = r + 8 < NB ? col[2 * (r + 8)] : 0.0;
+    };
 #pragma unroll
-        for (int j = 0; j < (p < NW ? 2 : 4); ++j) L[p][j] = f[j];
-        nb[p] = 8 + p < NB ? col[2 * (8 + p)] : 0.0;
-    }
+    for (int r = 0; r < NB; ++r)
+        if (fissue(r) < 0) fload(r);
     double b0 = col[0], b1 = col[2], b2 = col[4], b3 = col[6];
     double b4 = col[8], b5 = col[10], b6 = col[12], b7 = col[14];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int p = i % PF;
-        const double2 l01 = L[p][0], l23 = L[p][1], l45 = L[p][2], l67 = L[p][3];
-        const double next = nb[p];
-        if (i + PF < NB) {
-            const double2* f = reinterpret_cast<const double2*>(F + frow(i + PF));
+    for (int i = 0; i < NB; i += 2) {
 #pragma unroll
-            for (int j = 0; j < (i + PF < NW ? 2 : 4); ++j) L[p][j] = f[j];
-            nb[p] = i + PF + 8 < NB ? col[2 * (i + PF + 8)] : 0.0;
-        }
+        for (int r = i + 1; r < NB && r <= i + 1 + DN; ++r)
+            if (fissue(r) == i || fissue(r) == i + 1) fload(r);
         __builtin_amdgcn_sched_barrier(0);
-        const double y = b0;
-        col[2 * i] = y;
-        b0 = b1 - l01.x * y;
-        b1 = b2 - l01.y * y;
-        b2 = b3 - l23.x * y;
-        b3 = b4 - l23.y * y;
-        if (i < NW) {
-            b4 = b5;
-            b5 = b6;
-            b6 = b7;
-            b7 = next;
-        } else {
-            b4 = b5 - l45.x * y;
-            b5 = b6 - l45.y * y;
-            b6 = b7 - l67.x * y;
-            b7 = next - l67.y * y;
-        }
-    }
-    double2 U[PF][2];
-    double nc[PF];  // col[i - 4] for the coming rows
+        double y[2];
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-        const int i = NB - 1 - p;
-        const double2* f = reinterpret_cast<const double2*>(F + brow(i));
-        U[p][0] = f[0];
-        U[p][1] = f[1];
-        nc[p] = i - 4 >= 0 ? col[2 * (i - 4)] : 0.0;
+        for (int h = 0; h < 2; ++h) {
+            const int r = i + h;
+            y[h] = b0;
+            b0 = b1 - Lr[r][0].x * y[h];
+            b1 = b2 - Lr[r][0].y * y[h];
+            b2 = b3 - Lr[r][1].x * y[h];
+            b3 = b4 - Lr[r][1].y * y[h];
+            if (r < NW) {
+                b4 = b5;
+                b5 = b6;
+                b6 = b7;
+                b7 = nb[r];
+            } else {
+                b4 = b5 - Lr[r][2].x * y[h];
+                b5 = b6 - Lr[r][2].y * y[h];
+                b6 = b7 - Lr[r][3].x * y[h];
+                b7 = nb[r] - Lr[r][3].y * y[h];
+            }
+        }
+        col[2 * i] = y[0];
+        col[2 * i + 2] = y[1];
     }
+    // backward: row i (from NB - 1 down to 1) needs W's record of row i and
+    // col[2 (i - 4)]; step t = NB - 1 - i
+    double2 Ur[NB][2];
+    double nc[NB];
+    auto bload = [&](int i) {
+        const double2* f = reinterpret_cast<const double2*>(F + brow(i));
+        Ur[i][0] = f[0];
+        Ur[i][1] = f[1];
+        nc[i] = i - 4 >= 0 ? col[2 * (i - 4)] : 0.0;
+    };
+#pragma unroll
+    for (int i = NB - 1; i >= 1; --i)
+        if (NB - 1 - i - DB < 0) bload(i);
     double c0 = col[2 * (NB - 1)], c1 = col[2 * (NB - 2)], c2 = col[2 * (NB - 3)], c3 = col[2 * (NB - 4)];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        const int i = NB - 1 - t, p = t % PF;
-        const double2 u12 = U[p][0], u34 = U[p][1];
-        const double next = nc[p];
-        if (t + PF < NB - 1) {  // row 0 has nothing above the diagonal: no record
-            const double2* f = reinterpret_cast<const double2*>(F + brow(i - PF));
-            U[p][0] = f[0];
-            U[p][1] = f[1];
-            nc[p] = i - PF - 4 >= 0 ? col[2 * (i - PF - 4)] : 0.0;
-        }
+    for (int t = 0; t < NB; t += 2) {
+#pragma unroll
+        for (int u = t + 1; u < NB - 1 && u <= t + 1 + DB; ++u)  // row 0 has nothing above the diagonal: no record
+            if (u - DB == t || u - DB == t + 1) bload(NB - 1 - u);
         __builtin_amdgcn_sched_barrier(0);
-        const double x = c0;
-        col[2 * i] = x;
-        if (i > 0) {
-            c0 = c1 - u12.x * x;
-            c1 = c2 - u12.y * x;
-            c2 = c3 - u34.x * x;
-            c3 = next - u34.y * x;
+        double x[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = NB - 1 - t - h;
+            x[h] = c0;
+            if (i > 0) {
+                c0 = c1 - Ur[i][0].x * x[h];
+                c1 = c2 - Ur[i][0].y * x[h];
+                c2 = c3 - Ur[i][1].x * x[h];
+                c3 = nc[i] - Ur[i][1].y * x[h];
+            }
         }
+        col[2 * (NB - 1 - t)] = x[0];
+        col[2 * (NB - 2 - t)] = x[1];
     }
 }
 
@@ -222,12 +250,15 @@ struct Row9 {
 // Wave w does the radial-line work of slots 2w, 2w+1 (one lane per radial
 // node); wave 0 does the substitutions, one lane per complex right-hand side.
 // LDS: the factor area (the pressure images and columns, then the Helmholtz
-// images), the radial lines (u^n as loaded, then the right-hand sides and
-// the solution) and the slots' inverse influence matrices: about 53 KB at
-// NB = 64, so three workgroups share a compute unit.  Every input is
-// requested at the start (u^n lines, pressure images and A^-1 by LDS DMA,
-// the nonlinear terms into registers); the Helmholtz images follow as soon as
-// the pressure images are consumed.
+// images, at a bank-staggered stride), the radial lines (u^n, then the
+// right-hand sides and the solution) and the slots' inverse influence
+// matrices: about 53 KB at NB = 64, so three workgroups share a compute unit.
+// Every input is requested at the start (pressure images and A^-1 by LDS
+// DMA, then each slot's u^n and nonlinear terms into registers), and the
+// first slot's right-hand side is formed while the second slot's data are
+// still arriving; the weights and influence data of later phases are
+// requested a phase ahead, and the Helmholtz images follow as soon as the
+// pressure images are consumed.
 template <typename TNL, int NB, int NW>
 __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     constexpr int FW = solve_image_doubles(NB, NW);
@@ -277,95 +308,108 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         return ((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * N;
     };
 
-    // ---- requests: u^n (or R) lines of this wave's slots and the pressure
-    //      images by DMA, the slots' A^-1 (wave 0), the nonlinear terms
-    {
-        const double* src = a.kind == OPF_SOLVE_RAW ? static_cast<const double*>(a.n0) : a.u0;
+    // ---- requests, in the order the phases need them: the pressure images
+    //      and the slots' A^-1 by LDS DMA, the stencil weights, then slot 2w
+    //      and slot 2w+1 (u^n or R and the nonlinear terms, one radial row per
+    //      lane) into registers.  The register loads are unconditional (rows
+    //      and modes clamped to valid ones), so the counted wait before slot
+    //      2w's right-hand side leaves slot 2w+1's loads in flight: loads are
+    //      served in order, and slot 2w's right-hand side is formed while
+    //      slot 2w+1's data arrive.  The nonlinear-term loads a kind does not
+    //      use (N^p for PRED, both for RAW) read one fixed 16-byte location
+    //      instead: one cache line for the whole wave, no extra HBM traffic.
+    dma_images<FW, FWP>(t.img + ippe * FW, sF, nfp, w, n);
+    if (w == 0) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = 2 * w + j;
-            if (!slot_ok(q)) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (n < N) lds_dma16(src + 2 * (c * S + slot_off(q) + n), &sX[q][c][0]);
-        }
-        dma_images<FW, FWP>(t.img + ippe * FW, sF, nfp, w, n);
-        if (w == 0) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {  // four slots (16 lanes of 16 bytes each) per instruction
-                const int q = 4 * i + (n >> 4);
-                if (slot_ok(q))
-                    lds_dma16(t.ainv + (((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * 16) * 2 + 2 * (n & 15),
-                              &sAi[4 * i][0]);
-            }
-        }
-    }
-    dcplx na[2][3];  // nonlinear terms (PRED: N^n, CORR: (1-c) N^n + c N^p) of this lane's row
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int q = 2 * w + j;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) na[j][c] = dcplx{0.0, 0.0};
-        if (a.kind == OPF_SOLVE_RAW || !slot_ok(q) || n >= N) continue;
-        const size_t off = slot_off(q) + n;
-        if (a.kind == OPF_SOLVE_PRED) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) na[j][c] = load_c<TNL>(a.n0, c * S + off);
-        } else {
-            const double cc = a.c, c1 = 1.0 - a.c;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                na[j][c] = c1 * load_c<TNL>(a.n0, c * S + off) + cc * load_c<TNL>(a.n1, c * S + off);
+        for (int i = 0; i < 2; ++i) {  // four slots (16 lanes of 16 bytes each) per instruction
+            const int q = 4 * i + (n >> 4);
+            if (slot_ok(q))
+                lds_dma16(t.ainv + (((size_t)(m0 + (q >> 1)) * nk + (slot_k(q) + K - 1)) * 16) * 2 + 2 * (n & 15),
+                          &sAi[4 * i][0]);
         }
     }
     Row9 Lo, Le;  // weights of d2/dr2 + (1/r) d/dr, parity of this wave's m +- 1 and of m
     Lo.load(t.wl, N, (mw + 1) & 1, nr);
     Le.load(t.wl, N, mw & 1, nr);
+    const double* src = a.kind == OPF_SOLVE_RAW ? static_cast<const double*>(a.n0) : a.u0;
+    const bool use0 = a.kind != OPF_SOLVE_RAW, use1 = a.kind == OPF_SOLVE_CORR;
+    const void* nl0 = use0 ? a.n0 : static_cast<const void*>(t.rinv);
+    const void* nl1 = use1 ? a.n1 : static_cast<const void*>(t.rinv);
+    dcplx ul[2][3];               // u^n (RAW: R) of this lane's row
+    vec2<TNL> x0[2][3], x1[2][3];  // N^n and N^p as stored
+    auto request = [&](int j) {
+        const int q = 2 * w + j;
+        const size_t off = ((size_t)min(m0 + (q >> 1), a.M - 1) * nk + (slot_k(q) + K - 1)) * N + nr;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ul[j][c] = load_c<double>(src, c * S + off);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x0[j][c] = load_v<TNL>(nl0, use0 ? c * S + off : 0);
+            x1[j][c] = load_v<TNL>(nl1, use1 ? c * S + off : 0);
+        }
+    };
+    request(0);
+    __builtin_amdgcn_sched_barrier(0);
+    request(1);
+    __builtin_amdgcn_sched_barrier(0);
     // rows N..NB of this wave's lines stay zero (branch-free substitution)
     for (int i = n; i < 2 * 3 * (XS - N); i += 64) {
         const int j = i / (3 * (XS - N)), rem = i % (3 * (XS - N));
         sX[2 * w + j][rem / (XS - N)][N + rem % (XS - N)] = dcplx{0.0, 0.0};
     }
-    lds_dma_wait();
-    __builtin_amdgcn_wave_barrier();
+    // Slot 2w+1's nine loads (nine instructions: the u^n and N^n, N^p reads
+    // lie far apart and none is dropped) are the last vector-memory
+    // instructions issued: with at most nine outstanding, everything older
+    // (the DMA, the weights, slot 2w) has landed.  The compiler's own wait
+    // would be vmcnt(0) while the DMA is pending, which would also wait for
+    // slot 2w+1.
+    __builtin_amdgcn_s_waitcnt(0x0F79);  // vmcnt(9)
+    __builtin_amdgcn_sched_barrier(0);
 
     // ---- R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) in the (+,-,z) form,
-    //      from this wave's own lines (no workgroup barrier needed)
-    {
-        dcplx rr[2][3];
+    //      slot by slot from this wave's own lines (no workgroup barrier)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = 2 * w + j;
-            const dcplx ur = sX[q][0][nr], ut = sX[q][1][nr], uz = sX[q][2][nr];
-            if (a.kind == OPF_SOLVE_RAW) {
-                rr[j][0] = ur + ix(ut);
-                rr[j][1] = ur - ix(ut);
-                rr[j][2] = uz;
-            } else {
-                const int m = mp * (m0 + (q >> 1)), k = slot_k(q);
-                const double kap2 = a.alpha * k * a.alpha * k;
-                const dcplx dr = Lo.apply(sX[q][0], s0r), dt = Lo.apply(sX[q][1], s0r), dz = Le.apply(sX[q][2], s0r);
-                const dcplx up = ur + ix(ut), um = ur - ix(ut);
-                const double r2 = rinvr * rinvr;
-                const dcplx Lp = (dr + ix(dt)) - (double(m + 1) * double(m + 1) * r2 + kap2) * up;
-                const dcplx Lm = (dr - ix(dt)) - (double(m - 1) * double(m - 1) * r2 + kap2) * um;
-                const dcplx Lz = dz - (double(m) * double(m) * r2 + kap2) * uz;
-                rr[j][0] = a.inv_dt * up + a.aexp * Lp + (na[j][0] + ix(na[j][1]));
-                rr[j][1] = a.inv_dt * um + a.aexp * Lm + (na[j][0] - ix(na[j][1]));
-                rr[j][2] = a.inv_dt * uz + a.aexp * Lz + na[j][2];
-                if (m == 0 && k == 0) rr[j][2].x += a.force;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();  // every lane of the wave has read the u^n lines
+    for (int j = 0; j < 2; ++j) {
+        const int q = 2 * w + j;
         if (n < N) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int q = 2 * w + j;
-                if (!slot_ok(q)) continue;
+            for (int c = 0; c < 3; ++c) sX[q][c][n] = ul[j][c];
+        }
+        __builtin_amdgcn_wave_barrier();
+        dcplx rr[3];
+        const dcplx ur = ul[j][0], ut = ul[j][1], uz = ul[j][2];
+        if (a.kind == OPF_SOLVE_RAW) {
+            rr[0] = ur + ix(ut);
+            rr[1] = ur - ix(ut);
+            rr[2] = uz;
+        } else {
+            dcplx na[3];  // PRED: N^n; CORR: (1-c) N^n + c N^p
+            if (a.kind == OPF_SOLVE_PRED) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sX[q][c][n] = rr[j][c];
-                sY[q][n] = 0.5 * (rr[j][0] + rr[j][1]);  // R_r, for the divergence
+                for (int c = 0; c < 3; ++c) na[c] = to_c(x0[j][c]);
+            } else {
+                const double cc = a.c, c1 = 1.0 - a.c;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) na[c] = c1 * to_c(x0[j][c]) + cc * to_c(x1[j][c]);
             }
+            const int m = mp * (m0 + (q >> 1)), k = slot_k(q);
+            const double kap2 = a.alpha * k * a.alpha * k;
+            const dcplx dr = Lo.apply(sX[q][0], s0r), dt = Lo.apply(sX[q][1], s0r), dz = Le.apply(sX[q][2], s0r);
+            const dcplx up = ur + ix(ut), um = ur - ix(ut);
+            const double r2 = rinvr * rinvr;
+            const dcplx Lp = (dr + ix(dt)) - (double(m + 1) * double(m + 1) * r2 + kap2) * up;
+            const dcplx Lm = (dr - ix(dt)) - (double(m - 1) * double(m - 1) * r2 + kap2) * um;
+            const dcplx Lz = dz - (double(m) * double(m) * r2 + kap2) * uz;
+            rr[0] = a.inv_dt * up + a.aexp * Lp + (na[0] + ix(na[1]));
+            rr[1] = a.inv_dt * um + a.aexp * Lm + (na[0] - ix(na[1]));
+            rr[2] = a.inv_dt * uz + a.aexp * Lz + na[2];
+            if (m == 0 && k == 0) rr[2].x += a.force;
+        }
+        __builtin_amdgcn_wave_barrier();  // every lane of the wave has read the u^n lines
+        if (n < N && slot_ok(q)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sX[q][c][n] = rr[c];
+            sY[q][n] = 0.5 * (rr[0] + rr[1]);  // R_r, for the divergence
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -397,6 +441,15 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             if (n < XS - 64) sY[q][64 + n] = dcplx{0.0, 0.0};
         }
     }
+    lds_dma_wait();  // this wave's share of the pressure images and A^-1 (landed long ago)
+    // the next phase's weights and 1/U_ii of H_{m+1}, H_{|m-1|}, H_m at this
+    // row, requested now so that they arrive during the substitution
+    Row9 W1e;
+    W1e.load(t.d1, N, mw & 1, nr);
+    const double* dvh = t.dinv + (size_t)kabs * a.MU * NB;
+    const double dvp = n < N ? dvh[(size_t)(mw + 1) * NB + n] : 0.0;
+    const double dvm = n < N ? dvh[(size_t)abs(mw - 1) * NB + n] : 0.0;
+    const double dvz = n < N ? dvh[(size_t)mw * NB + n] : 0.0;
     __syncthreads();
     if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1))
         lds_solve<NB, NW>(sF + (n >> 2) * FWP, &sY[n >> 1][0].x + (n & 1));
@@ -408,13 +461,6 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const int nfh1 = min(nfh, 4);
     dma_images<FW, FWP>(t.img + ihelm * FW, sF, nfh1, w, n);
     {
-        Row9 W1e;
-        W1e.load(t.d1, N, mw & 1, nr);
-        // 1/U_ii of H_{m+1}, H_{|m-1|}, H_m at this row
-        const double* dvh = t.dinv + (size_t)kabs * a.MU * NB;
-        const double dvp = n < N ? dvh[(size_t)(mw + 1) * NB + n] : 0.0;
-        const double dvm = n < N ? dvh[(size_t)abs(mw - 1) * NB + n] : 0.0;
-        const double dvz = n < N ? dvh[(size_t)mw * NB + n] : 0.0;
         if (n < N) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -456,6 +502,14 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     if (nfh > nfh1)
         dma_images<FW, FWP>(t.img + (ihelm + nfh1) * FW, sF + nfh1 * FWP, nfh - nfh1, w, n);
     lds_dma_wait();
+    // influence data of this wave's m (one radial row per lane), requested
+    // before the substitution and used after it
+    double hv[NHOM];
+    {
+        const double* h = t.hom + ((size_t)min(m0 + w, a.M - 1) * K + kabs) * NHOM * N;
+#pragma unroll
+        for (int j = 0; j < NHOM; ++j) hv[j] = h[j * N + nr];
+    }
     __syncthreads();
     if (w == 0 && n < 6 * NSLOT) {
         const int q = n / 6, c = (n >> 1) % 3;
@@ -466,13 +520,6 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         }
     }
     __syncthreads();
-    // influence data of this wave's m (one radial row per lane)
-    double hv[NHOM];
-    {
-        const double* h = t.hom + ((size_t)min(m0 + w, a.M - 1) * K + kabs) * NHOM * N;
-#pragma unroll
-        for (int j = 0; j < NHOM; ++j) hv[j] = h[j * N + nr];
-    }
     // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
     if (w == 1 && m0 == 0 && kabs == 0) {  // (0,0): flux of u_z,b over the radial quadrature
         double qs = n < N ? t.quad[n] * sX[0][2][n].x : 0.0;
@@ -518,9 +565,9 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         }
     }
     __syncthreads();
-    Row9 W1o, W1e;  // first-derivative weights of this lane's row, parities of m +- 1 and m (vorticity)
+    Row9 W1o, W1v;  // first-derivative weights of this lane's row, parities of m +- 1 and m (vorticity)
     W1o.load(t.d1, N, (mw + 1) & 1, nr);
-    W1e.load(t.d1, N, mw & 1, nr);
+    W1v.load(t.d1, N, mw & 1, nr);
     if (n < N) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -584,7 +631,7 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             const int mi = m0 + (q >> 1), m = mp * mi, k = slot_k(q);
             const bool mirror = (mi == 0 && kabs > 0);
             dcplx wo[3];
-            curl_row(W1e.apply(sX[q][2], s0r), W1o.apply(sX[q][1], s0r), rinvr, m, a.alpha * k, sX[q][0][n],
+            curl_row(W1v.apply(sX[q][2], s0r), W1o.apply(sX[q][1], s0r), rinvr, m, a.alpha * k, sX[q][0][n],
                      sX[q][1][n], sX[q][2][n], wo[0], wo[1], wo[2]);
             const size_t off = slot_off(q) + n;
             const size_t offc = ((size_t)mi * nk + (K - 1 - kabs)) * N + n;
