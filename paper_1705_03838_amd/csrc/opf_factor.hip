@@ -19,6 +19,91 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// Twisted elimination of the band held in T (N = NB rows, offsets -8..+4)
+// and the twisted substitution image (layout and scaling as described at
+// solve_twisted): columns 0..h-1 top-down (lane t updates row j+1+t/4,
+// column j+1+t%4), columns NB-1..h+4 bottom-up (lane t updates row
+// j-1-t/8, column j-8+t%8), both without pivoting; the multipliers replace
+// the eliminated entries.  The middle block is inverted by Gauss-Jordan with
+// row pivoting.  Called by all 64 lanes.
+__device__ void twisted_image(const FactorArgs& a, double* T, double* G, double* Dv, double amax, int& bad) {
+    const int N = a.N, NB = a.NB, h = tw_h(NB), n = threadIdx.x;
+    for (int j = 0; j < h; ++j) {
+        const double piv = T[j * BW + 8];
+        if (!(fabs(piv) > 1e-14 * amax)) bad = bad ? bad : 2;
+        const int i = j + 1 + (n & 31) / 4, col = j + 1 + (n & 3);
+        if (n < 32 && i < N) {
+            const double l = T[i * BW + (j - i + 8)] / piv;
+            if (col < N && col - i >= -8) T[i * BW + (col - i + 8)] -= l * T[j * BW + (col - j + 8)];
+            if ((n & 3) == 0) T[i * BW + (j - i + 8)] = l;
+        }
+        __syncthreads();
+    }
+    for (int j = N - 1; j >= h + 4; --j) {
+        const double piv = T[j * BW + 8];
+        if (!(fabs(piv) > 1e-14 * amax)) bad = bad ? bad : 2;
+        const int i = j - 1 - (n & 31) / 8, col = j - 8 + (n & 7);
+        if (n < 32 && i >= 0) {
+            const double u = T[i * BW + (j - i + 8)] / piv;
+            if (col >= 0) T[i * BW + (col - i + 8)] -= u * T[j * BW + (col - j + 8)];
+            if ((n & 7) == 0) T[i * BW + (j - i + 8)] = u;
+        }
+        __syncthreads();
+    }
+    auto sv = [&](int i) { return i >= h && i < h + 4 ? 1.0 : 1.0 / T[i * BW + 8]; };
+    if (n == 0) {
+        double m[4][8];
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                m[r][c] = T[(h + r) * BW + (c - r + 8)];
+                m[r][4 + c] = r == c ? 1.0 : 0.0;
+            }
+        for (int c = 0; c < 4; ++c) {
+            int pr = c;
+            for (int r = c + 1; r < 4; ++r)
+                if (fabs(m[r][c]) > fabs(m[pr][c])) pr = r;
+            if (!(fabs(m[pr][c]) > 1e-14 * amax)) bad = bad ? bad : 2;
+            if (pr != c)
+                for (int e = 0; e < 8; ++e) {
+                    const double x = m[c][e];
+                    m[c][e] = m[pr][e];
+                    m[pr][e] = x;
+                }
+            const double inv = 1.0 / m[c][c];
+            for (int e = 0; e < 8; ++e) m[c][e] *= inv;
+            for (int r = 0; r < 4; ++r)
+                if (r != c) {
+                    const double f = m[r][c];
+                    for (int e = 0; e < 8; ++e) m[r][e] -= f * m[c][e];
+                }
+        }
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) G[tw_mi(NB) + 4 * r + c] = m[r][4 + c];
+    }
+    if (n < h) {
+        const int t = n, j = NB - 1 - t;
+        for (int d = 0; d < 4; ++d) {
+            const int i = t + 1 + d, ib = j - 1 - d;
+            G[4 * t + d] = sv(i) * T[i * BW + (t - i + 8)] * T[t * BW + 8];
+            G[tw_p1b(NB) + 4 * t + d] = sv(ib) * T[ib * BW + (j - ib + 8)] * T[j * BW + 8];
+        }
+    }
+    if (n < 4) G[tw_z4(NB) + n] = 0.0;
+    if (n < h + 4) {
+        const int t = n, ja = h + 3 - t, jb = h + t;
+        for (int d = 0; d < 4; ++d) {
+            const int i = ja - 1 - d;
+            G[tw_p3a(NB) + 4 * t + d] = i >= 0 && i < h ? T[i * BW + (ja - i + 8)] * sv(i) : 0.0;
+        }
+        double* g = G + tw_p3b_rec(NB, t);
+        for (int d = 0; d < (tw_wide(NB, t) ? 8 : 4); ++d) {
+            const int i = jb + 1 + d;
+            g[d] = i >= h + 4 && i < NB ? T[i * BW + (jb - i + 8)] * sv(i) : 0.0;
+        }
+    }
+    if (n < NB) Dv[n] = sv(n);
+}
+
 // One system per 64-thread workgroup.  System q < MU K is H_{mu,|k|} with
 // mu = q / K, |k| = q % K; q >= MU K is the pressure operator L_{m,|k|},
 // m = mp (q - MU K) / K, with P(1) = 0 (the unused (0,0) record gets
@@ -29,6 +114,7 @@ __device__ inline double wave_max(double v) {
 // 1e-14 max|A|, 3 element growth (|U| > 1e3 max|A| or |L| > 1e3).
 __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     __shared__ double B[NMAX * BW];
+    __shared__ double T[NMAX * BW];  // the band again, for the twisted elimination
     const int q = first + blockIdx.x;
     const int N = a.N, n = threadIdx.x;
     const bool helm = q < a.MU * a.K;
@@ -82,6 +168,12 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
     }
     amax = wave_max(amax);
     __syncthreads();
+    const bool tw = solve_twisted(a.NB, a.NW);
+    if (tw) {
+        for (int e = n; e < N * BW; e += 64) T[e] = B[e];
+        if (N != a.NB) bad = 1;  // the twisted images assume N = NB
+    }
+    __syncthreads();
     // elimination: lane t updates row j+1+t/4, column j+1+t%4
     const int ti = 1 + (n & 31) / 4, tc = 1 + (n & 3);
     for (int j = 0; j < N; ++j) {
@@ -117,7 +209,9 @@ __global__ __launch_bounds__(64) void k_factor(FactorArgs a, int first) {
         f[9] = 0.0;
     }
     // image: Lh[n+d][n] = L[n+d][n] U_nn / U_{n+d,n+d}, W[n-d][n] = U[n-d][n] / U_{n-d,n-d}
-    if (n < a.NB) {
+    if (tw) {
+        twisted_image(a, T, G, Dv, amax, bad);
+    } else if (n < a.NB) {
         const int nd = n < a.NW ? 4 : 8;
         double* g = G + (n < a.NW ? 4 * n : 4 * a.NW + 8 * (n - a.NW));
         for (int d = 1; d <= nd; ++d)

@@ -32,6 +32,45 @@ constexpr int NHOM = 7;   // real radial lines of influence data per (m,|k|)
 // entries above the diagonal); rows N..NB-1 are zero.  dinv = 1/U_ii per row.
 __host__ __device__ constexpr int solve_image_fwd(int NB, int NW) { return 4 * NW + 8 * (NB - NW); }
 __host__ __device__ constexpr int solve_image_doubles(int NB, int NW) { return solve_image_fwd(NB, NW) + 4 * (NB - 1); }
+// Twisted substitution images, used where NW = NB - 9 (then N = NB: the
+// clamped wall stencils put the first column with more than four entries
+// below the diagonal at N - 9).  The operator is eliminated from both ends
+// without pivoting: columns 0..h-1 top-down, columns NB-1..h+4 bottom-up,
+// h = (NB - 4) / 2, which leaves rows h..h+3 coupled only among themselves.
+// With p_i the pivots of the top and bottom rows and s_i = 1/p_i there (1 on
+// the middle rows), the right-hand side arrives scaled by s (dinv = s), and
+// a top lane and a bottom lane solve together:
+//   phase 1, h steps each: the top lane runs down rows 0..h-1, the bottom
+//     lane up rows NB-1..h+4, each record holding the four scaled
+//     multipliers s_i l_ij p_j of its column (rows below, resp. above);
+//   middle: both lanes add their four remainders for rows h..h+3, subtract
+//     the right-hand side once and apply Mi, the inverse of the middle block;
+//   phase 3, h + 4 steps each: the top lane runs up columns h+3..0, the
+//     bottom lane down columns h..NB-1 (the first four steps with the middle
+//     values known), records holding s_i A~[i][j] for the rows of its own
+//     part: four entries, eight for the bottom columns NB-9..NB-7 (the top
+//     lane reads four zeros there).
+// Layout per operator (doubles): phase-1 top records, phase-1 bottom
+// records, Mi (16, row-major), four zeros, phase-3 top records, phase-3
+// bottom records; 8 NB + 32 in all, the size of the standard image with
+// NW = NB - 9.
+__host__ __device__ constexpr bool solve_twisted(int NB, int NW) { return NW == NB - 9; }
+__host__ __device__ constexpr int tw_h(int NB) { return (NB - 4) / 2; }
+__host__ __device__ constexpr int tw_p1b(int NB) { return 4 * tw_h(NB); }
+__host__ __device__ constexpr int tw_mi(int NB) { return 8 * tw_h(NB); }
+__host__ __device__ constexpr int tw_z4(int NB) { return tw_mi(NB) + 16; }
+__host__ __device__ constexpr int tw_p3a(int NB) { return tw_z4(NB) + 4; }
+__host__ __device__ constexpr int tw_p3b(int NB) { return tw_p3a(NB) + 4 * (tw_h(NB) + 4); }
+// first of the three wide phase-3 steps of the bottom lane (columns NB-9..NB-7)
+__host__ __device__ constexpr int tw_w0(int NB) { return NB - 9 - tw_h(NB); }
+__host__ __device__ constexpr bool tw_wide(int NB, int t) { return t >= tw_w0(NB) && t < tw_w0(NB) + 3; }
+// offset of the bottom lane's phase-3 record of step t
+__host__ __device__ constexpr int tw_p3b_rec(int NB, int t) {
+    return tw_p3b(NB) + 4 * t + 4 * ((t < tw_w0(NB) ? tw_w0(NB) : (t > tw_w0(NB) + 3 ? tw_w0(NB) + 3 : t)) - tw_w0(NB));
+}
+static_assert(tw_p3b_rec(64, tw_h(64) + 4) == solve_image_doubles(64, 55), "twisted image size, NB = 64");
+static_assert(tw_p3b_rec(48, tw_h(48) + 4) == solve_image_doubles(48, 39), "twisted image size, NB = 48");
+static_assert(tw_p3b_rec(32, tw_h(32) + 4) == solve_image_doubles(32, 23), "twisted image size, NB = 32");
 // Padded row count and narrow-row count of the substitution for N radial
 // points whose LU columns j < narrow have at most four entries below the
 // diagonal: NB = 32, 48 or 64, NW = NB - 9, NB - 25 or 0 (the largest the

@@ -190,6 +190,117 @@ __device__ __forceinline__ void lds_solve(const double* __restrict__ F, double* 
     }
 }
 
+// Twisted substitution (image layout and scaling as described at
+// solve_twisted): two lanes share a right-hand side, lane `bottom` = 0
+// taking rows 0..h+3 from the top, lane 1 rows h..NB-1 from the bottom, the
+// pair 32 lanes apart in one wave.  Each lane keeps the register window of
+// the one-lane sweeps, walking its rows in its own direction; the two meet in
+// the 4 x 4 middle block.  The chains are h and h + 4 rows instead of NB and
+// NB - 1.  Reads run DT steps ahead.  (Pairing steps into ds_read2 /
+// ds_write2 as the one-lane sweeps do needs a swap of the two values in the
+// bottom lane, whose rows run the other way; measured slower.)
+template <int NB>
+__device__ __forceinline__ void lds_solve_tw(const double* __restrict__ F, double* col, int bottom) {
+    constexpr int h = tw_h(NB), DT = 4;
+    // sweep step t of phase 1 is row t (top) or NB-1-t (bottom); of phase 3,
+    // row h+3-t (top) or h+t (bottom)
+    double* c1 = col + (bottom ? 2 * (NB - 1) : 0);
+    double* c3 = col + (bottom ? 2 * h : 2 * (h + 3));
+    const int dir = bottom ? -2 : 2;  // doubles per phase-1 step (phase 3: the opposite)
+    const double* R1 = F + (bottom ? tw_p1b(NB) : 0);
+    // ---- phase 1: h steps, four-entry records
+    double2 L1[h][2];
+    double n1[h];  // right-hand side of sweep row t + 4 (the middle rows at most)
+    auto load1 = [&](int t) {
+        const double2* f = reinterpret_cast<const double2*>(R1 + 4 * t);
+        L1[t][0] = f[0];
+        L1[t][1] = f[1];
+        n1[t] = c1[dir * (t + 4)];
+    };
+#pragma unroll
+    for (int t = 0; t < DT; ++t) load1(t);
+    double b0 = c1[0], b1 = c1[dir], b2 = c1[2 * dir], b3 = c1[3 * dir];
+#pragma unroll
+    for (int t = 0; t < h; ++t) {
+        if (t + DT < h) load1(t + DT);
+        __builtin_amdgcn_sched_barrier(0);
+        const double y = b0;
+        c1[dir * t] = y;
+        b0 = b1 - L1[t][0].x * y;
+        b1 = b2 - L1[t][0].y * y;
+        b2 = b3 - L1[t][1].x * y;
+        b3 = n1[t] - L1[t][1].y * y;
+    }
+    // ---- middle: rows h..h+3 (top lane's b0..b3, bottom lane's b3..b0)
+    const double o0 = __shfl_xor(b0, 32), o1 = __shfl_xor(b1, 32), o2 = __shfl_xor(b2, 32), o3 = __shfl_xor(b3, 32);
+    const double2* mi = reinterpret_cast<const double2*>(F + tw_mi(NB));
+    double r[4];
+    {
+        const double mine[4] = {b0, b1, b2, b3}, other[4] = {o0, o1, o2, o3};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double top = bottom ? other[k] : mine[k], bot = bottom ? mine[3 - k] : other[3 - k];
+            r[k] = top + bot - col[2 * (h + k)];
+        }
+    }
+    double xm[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 m01 = mi[2 * k], m23 = mi[2 * k + 1];
+        xm[k] = m01.x * r[0] + m01.y * r[1] + m23.x * r[2] + m23.y * r[3];
+    }
+    if (!bottom) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[2 * (h + k)] = xm[k];
+    }
+    // ---- phase 3: h + 4 steps; the first four take the middle values
+    double2 L3[h + 4][4];
+    double n3[h + 4];  // right-hand side of sweep row t + 8
+    auto load3 = [&](int t) {
+        const double* rp = F + (bottom ? tw_p3b_rec(NB, t) : tw_p3a(NB) + 4 * t);
+        const double2* f = reinterpret_cast<const double2*>(rp);
+        L3[t][0] = f[0];
+        L3[t][1] = f[1];
+        if (tw_wide(NB, t)) {
+            const double2* g = reinterpret_cast<const double2*>(bottom ? rp + 4 : F + tw_z4(NB));
+            L3[t][2] = g[0];
+            L3[t][3] = g[1];
+        }
+        n3[t] = t + 8 <= h + 3 ? c3[-dir * (t + 8)] : 0.0;
+    };
+#pragma unroll
+    for (int t = 0; t < DT; ++t) load3(t);
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    double d4 = c3[-dir * 4], d5 = c3[-dir * 5], d6 = c3[-dir * 6], d7 = c3[-dir * 7];
+#pragma unroll
+    for (int t = 0; t < h + 4; ++t) {
+        if (t + DT < h + 4) load3(t + DT);
+        __builtin_amdgcn_sched_barrier(0);
+        double x;
+        if (t < 4) {
+            x = bottom ? xm[t] : xm[3 - t];
+        } else {
+            x = d0;
+            c3[-dir * t] = x;
+        }
+        d0 = d1 - L3[t][0].x * x;
+        d1 = d2 - L3[t][0].y * x;
+        d2 = d3 - L3[t][1].x * x;
+        d3 = d4 - L3[t][1].y * x;
+        if (tw_wide(NB, t)) {
+            d4 = d5 - L3[t][2].x * x;
+            d5 = d6 - L3[t][2].y * x;
+            d6 = d7 - L3[t][3].x * x;
+            d7 = n3[t] - L3[t][3].y * x;
+        } else {
+            d4 = d5;
+            d5 = d6;
+            d6 = d7;
+            d7 = n3[t];
+        }
+    }
+}
+
 // LDS DMA (global_load_lds_dwordx4): each active lane loads 16 bytes from
 // its own global address into LDS at dst + 16 * lane, without registers.
 // dst must be the same for the whole wave.  Completion is tracked by the
@@ -451,8 +562,12 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const double dvm = n < N ? dvh[(size_t)abs(mw - 1) * NB + n] : 0.0;
     const double dvz = n < N ? dvh[(size_t)mw * NB + n] : 0.0;
     __syncthreads();
-    if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1))
+    if constexpr (solve_twisted(NB, NW)) {  // right-hand side n & 31, its top lane n < 32
+        if (w == 0 && (n & 31) < 2 * NSLOT && slot_ok((n & 31) >> 1))
+            lds_solve_tw<NB>(sF + ((n & 31) >> 2) * FWP, &sY[(n & 31) >> 1][0].x + (n & 1), n >> 5);
+    } else if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1)) {
         lds_solve<NB, NW>(sF + (n >> 2) * FWP, &sY[n >> 1][0].x + (n & 1));
+    }
     __syncthreads();
 
     // ---- R -= grad P, scaled by 1/U_ii of each Helmholtz operator; (0,0):
@@ -511,7 +626,17 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
         for (int j = 0; j < NHOM; ++j) hv[j] = h[j * N + nr];
     }
     __syncthreads();
-    if (w == 0 && n < 6 * NSLOT) {
+    if constexpr (solve_twisted(NB, NW)) {  // right-hand side 32 w + (n & 31), waves 0 and 1
+        const int rh = 32 * w + (n & 31);
+        if (w < 2 && rh < 6 * NSLOT) {
+            const int q = rh / 6, c = (rh >> 1) % 3;
+            if (slot_ok(q)) {
+                const int m = mp * (m0 + (q >> 1));
+                const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
+                lds_solve_tw<NB>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (rh & 1), n >> 5);
+            }
+        }
+    } else if (w == 0 && n < 6 * NSLOT) {
         const int q = n / 6, c = (n >> 1) % 3;
         if (slot_ok(q)) {
             const int m = mp * (m0 + (q >> 1));

@@ -24,6 +24,10 @@ CASES = {
     "n56": dict(N=56, M=6, K=4, mp=1, alpha=1.0, Re=3000.0, dt=0.005),
     # the longest theta line, 3M = 192
     "m64": dict(N=14, M=64, K=3, mp=1, alpha=1.2, Re=1000.0, dt=0.01),
+    # N = 32, 48, 64 fill their padded row count: the twisted two-lane substitution
+    "n32": dict(N=32, M=4, K=4, mp=1, alpha=1.3, Re=2000.0, dt=0.01),
+    "n48": dict(N=48, M=6, K=3, mp=2, alpha=1.25, Re=2400.0, dt=0.01),
+    "n64": dict(N=64, M=4, K=3, mp=1, alpha=0.5, Re=5300.0, dt=0.005),
 }
 
 
