@@ -50,6 +50,15 @@ __device__ void twisted_image(const FactorArgs& a, double* T, double* G, double*
         }
         __syncthreads();
     }
+    // element growth of the eliminated rows (the multipliers left out: the
+    // bottom-up ones against the identity wall row are the wall stencil's
+    // entries themselves, large by construction and exact)
+    double g = 0.0;
+    if (n < N) {
+        const int lo = n < h ? n : (n < h + 4 ? h : max(n - 8, 0)), hi = n < h ? n + 4 : (n < h + 4 ? h + 3 : n);
+        for (int c = lo; c <= hi && c < N; ++c) g = fmax(g, fabs(T[n * BW + (c - n + 8)]));
+    }
+    if (wave_max(g) > 1e3 * amax) bad = bad ? bad : 3;
     auto sv = [&](int i) { return i >= h && i < h + 4 ? 1.0 : 1.0 / T[i * BW + 8]; };
     if (n == 0) {
         double m[4][8];
