@@ -393,7 +393,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
         }
         dftn<T, RB>(u, +1);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();  // the line is this wave's own: LDS accesses stay in order
     if (actB) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) lb[zb * LS + jb + r * RA] = u[r];
@@ -420,7 +420,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) lb[zb * LS + r * (RA + 1) + jb] = u[r];
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();  // pass B' reads this wave's own line
     // forward pass B' (radix RA): lane (zz, j), j < RB, takes output j of
     // pass-A' lanes r = 0..RA-1; results are bins j + r RB
     const int zc2 = lane / RB, jc = lane % RB;
@@ -434,7 +434,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
         }
         dftn<T, RA>(x2, -1);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     if (actC) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) lb[zc2 * LS + jc + r * RB] = x2[r];
