@@ -317,7 +317,8 @@ template <> struct ThetaLayout<192> { static constexpr int LS = 220; };
 // LDS bytes of one k_theta_lp workgroup
 template <typename T, int L, int TZ>
 constexpr size_t theta_lp_lds() {
-    return (size_t)(radix_max<L>() * radix_max<L>() + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
+    constexpr int tw = TwoPass<L>::RA == TwoPass<L>::RB ? 0 : radix_max<L>() * radix_max<L>();  // RA = RB: twiddles in registers
+    return (size_t)(tw + 3 * TZ * ThetaLayout<L>::LS) * sizeof(cpx<T>);
 }
 
 // Blocks g*8G + x + 8y (x < 8, y < G) take tiles g*8G + G x + y, so the G
@@ -336,9 +337,13 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     constexpr int XG = 128 / (TZ * (int)sizeof(cpx<T>)) > 0 ? 128 / (TZ * (int)sizeof(cpx<T>)) : 1;  // tiles per 128-byte line of H and G
     static_assert(RA * TZ <= 64 && RB * TZ <= 64, "a line pass must fit one wave");
     static_assert(LS >= L + RM, "segment too short for the skewed layout");
+    // RA = RB: a lane's twiddles W_L^{j r} are the same in the inverse pass B
+    // and the forward pass B' (j = lane % RA in both), so each lane keeps its
+    // RA - 1 values in registers and no table is staged in LDS
+    constexpr bool TWREG = RA == RB;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
-    cpx<T>* buf = tw2 + RM * RM;                         // [3][TZ][LS]
+    cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j (RA != RB)
+    cpx<T>* buf = TWREG ? tw2 : tw2 + RM * RM;           // [3][TZ][LS]
     constexpr int M = L / 3;  // the theta line is the 3/2-padded length 3M
     const int N = a.N, L3K = 3 * a.K;
     const int nzt = (L3K + TZ - 1) / TZ;
@@ -348,7 +353,8 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
     const int tid = threadIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const cpx<T>* twg = reinterpret_cast<const cpx<T>*>(a.twt);  // W_L^t, t < L
-    for (int t = tid; t < RM * RM; t += NT3) tw2[t] = twg[((t % RM) * (t / RM)) % L];
+    if constexpr (!TWREG)
+        for (int t = tid; t < RM * RM; t += NT3) tw2[t] = twg[((t % RM) * (t / RM)) % L];
     const cpx<T>* H = reinterpret_cast<const cpx<T>*>(a.H);
     const size_t fstride = (size_t)N * M * L3K;
     const size_t nbase = (size_t)n * M * L3K;
@@ -379,17 +385,24 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) lb[za * LS + r * (RB + 1) + ja] = v[r];
     }
-    __syncthreads();  // pass A results and tw2
     // inverse pass B: lane (zz, j); output r of pass-A lane r', then theta
     // points j + r RA in natural order
     const int zb = lane / RA, jb = lane % RA;
+    cpx<T> twr[RA];  // W_L^{jb r} (TWREG)
+    if constexpr (TWREG) {
+#pragma unroll
+        for (int r = 1; r < RA; ++r) twr[r] = twg[(jb * r) % L];
+        __builtin_amdgcn_wave_barrier();  // pass A results: this wave's own line
+    } else {
+        __syncthreads();  // pass A results and tw2
+    }
     const bool actB = zb < TZ;
     cpx<T> u[RB];
     if (actB) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const cpx<T> x = lb[zb * LS + jb * (RB + 1) + r];
-            u[r] = r == 0 ? x : cmulc(x, tw2[r * RM + jb]);
+            u[r] = r == 0 ? x : cmulc(x, TWREG ? twr[r] : tw2[r * RM + jb]);
         }
         dftn<T, RB>(u, +1);
     }
@@ -410,7 +423,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
             T nr = ut * wz - uz * wt, nt = uz * wr - ur * wz, nz = ur * wt - ut * wr;
             // W_L^{jb + r RA} = W_L^{jb} W_RB^{r}
-            if constexpr (ROT) add_coriolis<T>(a, cmul(tw2[RM + jb], unit_root<T, RB>(r)), ur, ut, uz, nr, nt, nz);
+            if constexpr (ROT) add_coriolis<T>(a, cmul(TWREG ? twr[1] : tw2[RM + jb], unit_root<T, RB>(r)), ur, ut, uz, nr, nt, nz);
             u[r] = p == 0 ? cpx<T>{nr, nt} : cpx<T>{nz, T(0)};
         }
         dftn<T, RB>(u, -1);
@@ -430,7 +443,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
             const cpx<T> x = lb[zc2 * LS + jc * (RA + 1) + r];
-            x2[r] = r == 0 ? x : cmul(x, tw2[r * RM + jc]);
+            x2[r] = r == 0 ? x : cmul(x, TWREG ? twr[r] : tw2[r * RM + jc]);
         }
         dftn<T, RA>(x2, -1);
     }
