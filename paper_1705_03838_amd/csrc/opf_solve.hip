@@ -562,11 +562,21 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     const double dvm = n < N ? dvh[(size_t)abs(mw - 1) * NB + n] : 0.0;
     const double dvz = n < N ? dvh[(size_t)mw * NB + n] : 0.0;
     __syncthreads();
+    // The substituting waves run at a raised issue priority: a substitution is
+    // one dependent chain per right-hand side, and on a busy compute unit the
+    // waves of the other resident workgroups (still forming right-hand sides,
+    // their loads having arrived later) would otherwise delay its steps.
     if constexpr (solve_twisted(NB, NW)) {  // right-hand side n & 31, its top lane n < 32
-        if (w == 0 && (n & 31) < 2 * NSLOT && slot_ok((n & 31) >> 1))
-            lds_solve_tw<NB>(sF + ((n & 31) >> 2) * FWP, &sY[(n & 31) >> 1][0].x + (n & 1), n >> 5);
-    } else if (w == 0 && n < 2 * NSLOT && slot_ok(n >> 1)) {
-        lds_solve<NB, NW>(sF + (n >> 2) * FWP, &sY[n >> 1][0].x + (n & 1));
+        if (w == 0) {
+            __builtin_amdgcn_s_setprio(2);
+            if ((n & 31) < 2 * NSLOT && slot_ok((n & 31) >> 1))
+                lds_solve_tw<NB>(sF + ((n & 31) >> 2) * FWP, &sY[(n & 31) >> 1][0].x + (n & 1), n >> 5);
+            __builtin_amdgcn_s_setprio(0);
+        }
+    } else if (w == 0) {
+        __builtin_amdgcn_s_setprio(2);
+        if (n < 2 * NSLOT && slot_ok(n >> 1)) lds_solve<NB, NW>(sF + (n >> 2) * FWP, &sY[n >> 1][0].x + (n & 1));
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
 
@@ -628,21 +638,29 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
     __syncthreads();
     if constexpr (solve_twisted(NB, NW)) {  // right-hand side 32 w + (n & 31), waves 0 and 1
         const int rh = 32 * w + (n & 31);
-        if (w < 2 && rh < 6 * NSLOT) {
-            const int q = rh / 6, c = (rh >> 1) % 3;
+        if (w < 2) {
+            __builtin_amdgcn_s_setprio(2);
+            if (rh < 6 * NSLOT) {
+                const int q = rh / 6, c = (rh >> 1) % 3;
+                if (slot_ok(q)) {
+                    const int m = mp * (m0 + (q >> 1));
+                    const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
+                    lds_solve_tw<NB>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (rh & 1), n >> 5);
+                }
+            }
+            __builtin_amdgcn_s_setprio(0);
+        }
+    } else if (w == 0) {
+        __builtin_amdgcn_s_setprio(2);
+        if (n < 6 * NSLOT) {
+            const int q = n / 6, c = (n >> 1) % 3;
             if (slot_ok(q)) {
                 const int m = mp * (m0 + (q >> 1));
                 const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
-                lds_solve_tw<NB>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (rh & 1), n >> 5);
+                lds_solve<NB, NW>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (n & 1));
             }
         }
-    } else if (w == 0 && n < 6 * NSLOT) {
-        const int q = n / 6, c = (n >> 1) % 3;
-        if (slot_ok(q)) {
-            const int m = mp * (m0 + (q >> 1));
-            const int mu = c == 0 ? m + 1 : (c == 1 ? abs(m - 1) : m);
-            lds_solve<NB, NW>(sF + (mu - mu_lo) * FWP, &sX[q][c][0].x + (n & 1));
-        }
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     // ---- influence matrix a = -A^{-1} g(u_b); fixed flux on (0,0) --------
