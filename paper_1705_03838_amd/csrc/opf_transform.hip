@@ -69,11 +69,24 @@ __device__ __forceinline__ void dft(cpx<T>* v, int sign) {
 template <typename TO, typename TI>
 __device__ __forceinline__ cpx<TO> cvt(cpx<TI> a) { return {TO(a.x), TO(a.y)}; }
 
-// Small DFT of length R in registers, R in {2,3,4,6,8,9,12,16}.  Composite R
-// = R1 R2 (R1 in {3,4}) by one Cooley-Tukey split: R2 DFTs of length R1 on
-// stride-R2 subsets, twiddles W_R^{n2 k1}, R1 DFTs of length R2; output
-// index k1 + R1 k2.  The twiddles W_R^e are compile-time constants.
+// Small DFT of length R in registers, R in {2,3,4,6,8,9,12,16}.
+// - Composite R = R1 R2 (R1 in {3,4}) by one Cooley-Tukey split: R2 DFTs of
+//   length R1 on stride-R2 subsets, twiddles W_R^{n2 k1}, R1 DFTs of length
+//   R2; output index k1 + R1 k2.  The twiddles W_R^e are compile-time
+//   constants.
+// - With PF set, R = 6 and 12 = R1 3 (R1 in {2, 4}, prime to 3) take the
+//   prime-factor (Good-Thomas) split instead, which needs no twiddles: input
+//   n = (3 n1 + R1 n2) mod R, DFTs of length R1 over n1, then of length 3
+//   over n2; output k is the residue pair (k mod R1, k mod 3) = (k1, k2)
+//   rebuilt by the Chinese remainder theorem.  It saves the 6 twiddle
+//   products of a 12-point DFT (two of them by 0 and +-1, which the compiler
+//   may not fold), about a tenth of the theta stage's VALU instructions.
 template <int R> struct Split1 { static constexpr int R1 = (R == 6 || R == 9) ? 3 : 4; };
+constexpr int crt_coef(int a, int m) {  // a (a^-1 mod m): 1 mod m, 0 mod a
+    int i = 0;
+    while ((a * i) % m != 1 % m) ++i;
+    return a * i;
+}
 
 // cos and sin of 2 pi e / R, evaluated by the compiler: the angle is reduced
 // exactly to y = 2 pi e / R - o pi / 2 with |y| <= pi / 4 (o the nearest
@@ -115,10 +128,26 @@ __device__ __forceinline__ cpx<T> unit_root(int e) {
     return {T(RootTable<R>::v.c[e]), T(-RootTable<R>::v.s[e])};
 }
 
-template <typename T, int R>
+template <typename T, int R, bool PF = false>
 __device__ __forceinline__ void dftn(cpx<T>* v, int sign) {
     if constexpr (R <= 4) {
         dft<T, R>(v, sign);
+    } else if constexpr (PF && (R == 6 || R == 12)) {
+        constexpr int R1 = R / 3, C1 = crt_coef(3, R1), C2 = crt_coef(R1, 3);
+        cpx<T> y[3][R1];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[(3 * n1 + R1 * n2) % R];
+            dft<T, R1>(y[n2], sign);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cpx<T> z[3] = {y[0][k1], y[1][k1], y[2][k1]};
+            dft<T, 3>(z, sign);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) v[(C1 * k1 + C2 * k2) % R] = z[k2];
+        }
     } else {
         constexpr int R1 = Split1<R>::R1, R2 = R / R1;
         cpx<T> y[R2][R1];
@@ -209,6 +238,9 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
     static_assert(ZT * RM <= NT2, "a pass must fit the workgroup");
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tw2 = reinterpret_cast<cpx<T>*>(smem_raw);  // [RM][RM]: W_L^{j r} at r RM + j
+    // prime-factor split in FP32 only: measured 6% faster there, 7% slower in
+    // FP64 (a bandwidth-bound kernel, which the twiddle products do not limit)
+    constexpr bool ZPF = sizeof(T) == 4;
     cpx<T>* buf = tw2 + RM * RM;                         // [ZT][LS]
     constexpr int K = L / 3, nk = 2 * K - 1;  // the z line is the 3/2-padded length 3K
     const int N = a.N, M = a.M;
@@ -234,7 +266,7 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
             else if (bin > L - K) kk = bin - L + K - 1;
             v[r] = kk >= 0 ? cvt<T>(src[(size_t)kk * N + n]) : cpx<T>{T(0), T(0)};
         }
-        dftn<T, RA>(v, +1);
+        dftn<T, RA, ZPF>(v, +1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) buf[na * LS + r * (RB + 1) + ja] = v[r];
     }
@@ -248,7 +280,7 @@ __device__ __forceinline__ void k_zinv_body(const NLArgs& a) {
             const cpx<T> x = buf[nb * LS + jb * (RB + 1) + r];  // output jb of pass-A lane r
             u[r] = r == 0 ? x : cmulc(x, tw2[r * RM + jb]);
         }
-        dftn<T, RB>(u, +1);
+        dftn<T, RB, ZPF>(u, +1);
         cpx<T>* dst = reinterpret_cast<cpx<T>*>(a.H) + ((size_t)f * N * M + (size_t)(n0 + nb) * M + m) * L;
 #pragma unroll
         for (int r = 0; r < RB; ++r) dst[jb + r * RA] = u[r];
@@ -381,7 +413,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             }
             v[r] = val;
         }
-        dftn<T, RA>(v, +1);
+        dftn<T, RA, true>(v, +1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) lb[za * LS + r * (RB + 1) + ja] = v[r];
     }
@@ -404,7 +436,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             const cpx<T> x = lb[zb * LS + jb * (RB + 1) + r];
             u[r] = r == 0 ? x : cmulc(x, TWREG ? twr[r] : tw2[r * RM + jb]);
         }
-        dftn<T, RB>(u, +1);
+        dftn<T, RB, true>(u, +1);
     }
     __builtin_amdgcn_wave_barrier();  // the line is this wave's own: LDS accesses stay in order
     if (actB) {
@@ -426,7 +458,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             if constexpr (ROT) add_coriolis<T>(a, cmul(TWREG ? twr[1] : tw2[RM + jb], unit_root<T, RB>(r)), ur, ut, uz, nr, nt, nz);
             u[r] = p == 0 ? cpx<T>{nr, nt} : cpx<T>{nz, T(0)};
         }
-        dftn<T, RB>(u, -1);
+        dftn<T, RB, true>(u, -1);
     }
     __syncthreads();  // every line has been read
     if (out && actB) {
@@ -445,7 +477,7 @@ __device__ __forceinline__ void k_theta_lp_body(const NLArgs& a) {
             const cpx<T> x = lb[zc2 * LS + jc * (RA + 1) + r];
             x2[r] = r == 0 ? x : cmul(x, TWREG ? twr[r] : tw2[r * RM + jc]);
         }
-        dftn<T, RA>(x2, -1);
+        dftn<T, RA, true>(x2, -1);
     }
     __builtin_amdgcn_wave_barrier();
     if (actC) {
@@ -528,7 +560,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
     }
     __syncthreads();  // twiddles
     if (ja < RB) {
-        dftn<T, RA>(v, +1);
+        dftn<T, RA, true>(v, +1);
 #pragma unroll
         for (int r = 0; r < RA; ++r) lb[za * LS + ja * RA + r] = v[r];
     }
@@ -542,7 +574,7 @@ __global__ __launch_bounds__(128) void k_cfl(NLArgs a, const double* __restrict_
             const cpx<T> x = lb[zb * LS + jb + r * RA];
             u[r] = r == 0 ? x : cmulc(x, tw[jb * r]);
         }
-        dftn<T, RB>(u, +1);
+        dftn<T, RB, true>(u, +1);
     }
     __syncthreads();
     if (actB) {
