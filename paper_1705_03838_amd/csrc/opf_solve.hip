@@ -459,23 +459,40 @@ __device__ __forceinline__ void k_solve_body(const SolveArgs& a) {
             x1[j][c] = load_v<TNL>(nl1, use1 ? c * S + off : 0);
         }
     };
+    const auto zero_tail_rows = [&] {  // rows N..NB of this wave's lines stay zero (branch-free substitution)
+        for (int i = n; i < 2 * 3 * (XS - N); i += 64) {
+            const int j = i / (3 * (XS - N)), rem = i % (3 * (XS - N));
+            sX[2 * w + j][rem / (XS - N)][N + rem % (XS - N)] = dcplx{0.0, 0.0};
+        }
+    };
     request(0);
     __builtin_amdgcn_sched_barrier(0);
-    request(1);
-    __builtin_amdgcn_sched_barrier(0);
-    // rows N..NB of this wave's lines stay zero (branch-free substitution)
-    for (int i = n; i < 2 * 3 * (XS - N); i += 64) {
-        const int j = i / (3 * (XS - N)), rem = i % (3 * (XS - N));
-        sX[2 * w + j][rem / (XS - N)][N + rem % (XS - N)] = dcplx{0.0, 0.0};
+    if constexpr (sizeof(TNL) == 8) {
+        // FP64 nonlinear terms: slot 2w+1 is requested only once slot 2w has
+        // arrived.  The launch's load burst is served roughly in the order the
+        // requests reach the memory system, so every workgroup then has its
+        // first slot by about the middle of the burst and forms that slot's
+        // right-hand side before its last data arrive; the workgroups that
+        // come last in the order, which set the launch's length, gain most.
+        // (With FP32 terms the burst is shorter and this measured slower.)
+        zero_tail_rows();
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        request(1);
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        request(1);
+        __builtin_amdgcn_sched_barrier(0);
+        zero_tail_rows();
+        // Slot 2w+1's nine loads (nine instructions: the u^n and N^n, N^p
+        // reads lie far apart and none is dropped) are the last vector-memory
+        // instructions issued: with at most nine outstanding, everything older
+        // (the DMA, the weights, slot 2w) has landed.  The compiler's own wait
+        // would be vmcnt(0) while the DMA is pending, which would also wait
+        // for slot 2w+1.
+        __builtin_amdgcn_s_waitcnt(0x0F79);  // vmcnt(9)
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // Slot 2w+1's nine loads (nine instructions: the u^n and N^n, N^p reads
-    // lie far apart and none is dropped) are the last vector-memory
-    // instructions issued: with at most nine outstanding, everything older
-    // (the DMA, the weights, slot 2w) has landed.  The compiler's own wait
-    // would be vmcnt(0) while the DMA is pending, which would also wait for
-    // slot 2w+1.
-    __builtin_amdgcn_s_waitcnt(0x0F79);  // vmcnt(9)
-    __builtin_amdgcn_sched_barrier(0);
 
     // ---- R = [1/dt + (1-c) L / Re] u^n + N (+ forcing) in the (+,-,z) form,
     //      slot by slot from this wave's own lines (no workgroup barrier)
