@@ -52,6 +52,19 @@ def kernel_bytes(name, N, M, K, mixed):
     raise KeyError(name)
 
 
+def solve_table_bytes(N, M, K, mp):
+    """Operator tables one solve launch reads once besides the spectral
+    fields, which the algorithmic count leaves out: the substitution images
+    (8 NB + 32 doubles each, for N = NB) of the M K pressure and MU K
+    Helmholtz operators, their 1/U_ii rows (NB doubles), the influence data
+    (7 radial lines per (m, |k|)) and the 4 x 4 complex A^-1 per (m, k).
+    None where N is not a padded row count (other image sizes)."""
+    if N not in (32, 48, 64):
+        return None
+    MU, nk, NB = mp * (M - 1) + 2, 2 * K - 1, N
+    return 8 * ((M + MU) * K * (8 * NB + 32 + NB) + M * K * 7 * N + M * nk * 32)
+
+
 def step_bytes(N, M, K, mixed):
     """Bytes the step's kernels move: two nonlinear evaluations (with the
     z-transformed intermediate) and two solves."""
@@ -562,9 +575,14 @@ def main():
         avg_ms = tot[dom] / launches
         ach = b / (avg_ms * 1e-3) / 1e9
         tr = traffic_for(dom, prec, args.workload)
+        extra = {}
+        tab = solve_table_bytes(N, M, K, w["mp"]) if dom == "solve" else None
+        if tab is not None:  # the solve's traffic also holds its operator tables
+            extra = {"tables_bytes_per_launch": tab,
+                     "achieved_with_tables": round((b + tab) / (avg_ms * 1e-3) / 1e9, 1)}
         return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": tr, "alg_bytes_per_launch": int(b),
+                "traffic": tr, "alg_bytes_per_launch": int(b), **extra,
                 "avg_launch_us": round(avg_ms * 1e3, 2),
                 "kernels_us": {k: round(v * 1e3, 2) for k, v in per.items()}}
 
