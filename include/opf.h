@@ -134,7 +134,9 @@ opf_status opf_get_state(opf_ctx* ctx, void* u_dev);
 /* Advance the state by nsteps predictor-corrector steps (Section 2):
  * N^n = (u x omega)(u^n); u^p = S(R0); N^p = (u x omega)(u^p); u^{n+1} = S(R1),
  * R0 = [1/dt + (1-c)L/Re] u^n + N^n + f, R1 = [..] u^n + c N^p + (1-c) N^n + f.
- * One hipGraph launch per step. */
+ * The steps run as captured hipGraphs: one launch per 8 steps, then one per
+ * remaining step; changing dt, the wall velocity or the rotation drops them.
+ * Asynchronous on the context's stream. */
 opf_status opf_step(opf_ctx* ctx, int32_t nsteps);
 
 /* Dealiased nonlinear term N = u x omega, omega = curl u (Section 2.2:

@@ -28,7 +28,8 @@ struct opf_ctx {
     double qG_inv = 0.0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;   // one step
+    hipGraphExec_t graphs = nullptr;  // STEP_GRAPH_STEPS steps
     unsigned char* ws = nullptr;
     size_t ws_bytes = 0;
     Tables t{};
@@ -827,9 +828,17 @@ opf_status opf_create(const opf_params* p, void* dev_workspace, size_t bytes, vo
     return OPF_OK;
 }
 
+// Forget the captured step graphs (they hold the step's arguments by value).
+void drop_step_graphs(opf_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graphs) (void)hipGraphExecDestroy(c->graphs);
+    c->graph = c->graphs = nullptr;
+}
+
 opf_status opf_destroy(opf_ctx* c) {
     if (!c) return OPF_E_INVALID;
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graphs) (void)hipGraphExecDestroy(c->graphs);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return OPF_OK;
@@ -858,32 +867,52 @@ opf_status opf_get_state(opf_ctx* c, void* u) {
     return OPF_OK;
 }
 
+// Steps per graph of the multi-step graph: a run of nsteps launches
+// nsteps / STEP_GRAPH_STEPS of them, then single-step graphs for the rest.
+constexpr int STEP_GRAPH_STEPS = 8;
+
+// Capture `steps` consecutive steps into one executable graph.
+opf_status capture_steps(opf_ctx* c, int steps, hipGraphExec_t* out) {
+    if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    opf_status st = OPF_OK;
+    for (int i = 0; i < steps && st == OPF_OK; ++i) st = enqueue_step(c, c->cap);
+    hipError_t he = hipStreamEndCapture(c->cap, &g);
+    if (st != OPF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (he != hipSuccess) {
+        c->err = std::string("capture: ") + hipGetErrorString(he);
+        return OPF_E_HIP;
+    }
+    he = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) {
+        *out = nullptr;
+        c->err = std::string("instantiate: ") + hipGetErrorString(he);
+        return OPF_E_HIP;
+    }
+    return OPF_OK;
+}
+
 opf_status opf_step(opf_ctx* c, int32_t nsteps) {
     if (!c || nsteps < 0) return OPF_E_INVALID;
     if (!c->have_state) return OPF_E_STATE;
-    if (!c->graph) {
-        if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-        hipGraph_t g = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-        const opf_status st = enqueue_step(c, c->cap);
-        hipError_t he = hipStreamEndCapture(c->cap, &g);
-        if (st != OPF_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
+    int i = 0;
+    if (nsteps >= STEP_GRAPH_STEPS) {
+        if (!c->graphs) {
+            const opf_status st = capture_steps(c, STEP_GRAPH_STEPS, &c->graphs);
+            if (st != OPF_OK) return st;
         }
-        if (he != hipSuccess) {
-            c->err = std::string("capture: ") + hipGetErrorString(he);
-            return OPF_E_HIP;
-        }
-        he = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (he != hipSuccess) {
-            c->graph = nullptr;
-            c->err = std::string("instantiate: ") + hipGetErrorString(he);
-            return OPF_E_HIP;
-        }
+        for (; i + STEP_GRAPH_STEPS <= nsteps; i += STEP_GRAPH_STEPS) HIPCHK(c, hipGraphLaunch(c->graphs, c->stream));
     }
-    for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    if (i < nsteps && !c->graph) {
+        const opf_status st = capture_steps(c, 1, &c->graph);
+        if (st != OPF_OK) return st;
+    }
+    for (; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     if (nsteps > 0) c->pc_valid = true;
     return OPF_OK;
 }
@@ -1095,10 +1124,7 @@ opf_status opf_set_dt(opf_ctx* c, double dt) {
         if (back != OPF_OK) c->have_state = false;  // tables lost: refuse to step
         return st;
     }
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_step_graphs(c);
     return OPF_OK;
 }
 
@@ -1130,10 +1156,7 @@ opf_status opf_set_wall_velocity(opf_ctx* c, const double* b) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     c->has_wall = b != nullptr;
-    if (c->graph) {  // the step graph holds the previous boundary condition
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_step_graphs(c);  // the step graph holds the previous boundary condition
     return OPF_OK;
 }
 
@@ -1148,10 +1171,7 @@ opf_status opf_set_rotation(opf_ctx* c, double ox, double oy, double oz) {
     c->rot[0] = ox;
     c->rot[1] = oy;
     c->rot[2] = oz;
-    if (c->graph) {  // the step graph holds the previous value
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_step_graphs(c);  // the step graph holds the previous value
     return OPF_OK;
 }
 

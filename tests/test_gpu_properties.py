@@ -39,22 +39,24 @@ def pipe64(**over):
     return w, kw
 
 
+@pytest.mark.parametrize("nsteps", [5, 21])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_step_equals_kernel_by_kernel_launches(torch_cuda, precision):
-    """opf_step replays one captured graph per step; opf_profile_steps
-    launches the same kernels one by one with timing events.  From the same
-    state both must give bitwise the same state."""
+def test_graph_step_equals_kernel_by_kernel_launches(torch_cuda, precision, nsteps):
+    """opf_step replays captured graphs (one of 8 steps, then one step at a
+    time: 21 = 2 x 8 + 5 uses both); opf_profile_steps launches the same
+    kernels one by one with timing events.  From the same state both must
+    give bitwise the same state."""
     import paper_1705_03838_amd as opf
     w, kw = pipe64()
     prec = opf.OPF_MIXED if precision == "mixed" else opf.OPF_FP64
-    say("graph vs kernel-by-kernel, pipe64", precision)
+    say("graph vs kernel-by-kernel, pipe64", precision, nsteps, "steps")
     s = make_solver(precision=prec, **kw)
     u = torch_cuda.from_numpy(workload_state(w, oracle_nodes(kw["N"])))
     s.set_state(u)
-    s.step(5)
+    s.step(nsteps)
     a = s.get_state().clone()
     s.set_state(u)
-    s.profile_steps(5)
+    s.profile_steps(nsteps)
     b = s.get_state()
     assert torch_cuda.equal(a, b)
     s.close()
